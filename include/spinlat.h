@@ -1,0 +1,202 @@
+/*
+ * spinlat.h -- C ABI of the MI355X (gfx950) spin-lattice library.
+ *
+ * One call of sl_step advances a periodic system of N atoms, each carrying
+ * a position r_i, a velocity v_i and a unit spin s_i, with the symplectic
+ * Suzuki-Trotter splitting of Tranchida, Plimpton, Thibaudeau and Thompson
+ * (J. Comput. Phys. 2018; Sec. 3, Eq. general_ST_decomposition):
+ *   half kick, spin half-step, drift, spin half-step, half kick,
+ * where each spin half-step is a forward then a backward sweep over
+ * classes of non-interacting spins (Sec. 5.1, Eq. spin_ST_sectoring) and
+ * each spin update is the closed-form rotation of Sec. 3 about the
+ * precession vector omega_i (Sec. 2) gathered right before the update.
+ *
+ * Conventions shared by every entry point:
+ *  - Units: A, ps, eV, amu, K, T. Spins are unit vectors.
+ *  - Arrays cross the ABI as AoS double[N][3] (or double[N], int[N]) in the
+ *    caller's atom order ("user order"); the library keeps its own
+ *    structure-of-arrays copies, reordered by colour class and cell.
+ *  - `where` is SL_HOST (host pointer) or SL_DEVICE (device pointer on the
+ *    system's stream, e.g. a torch tensor's data_ptr()). Caller memory is
+ *    copied in or out during the call and never retained.
+ *  - The library owns every device buffer it allocates.
+ *  - Every function returns 0 (SL_OK) or a negative SL_E_* code; nothing
+ *    throws or aborts across the ABI. sl_last_error() gives the message.
+ *  - sl_step is asynchronous on the system's stream except for one host
+ *    wait per step on the previous step's completion (the neighbour-list
+ *    rebuild decision) and a synchronisation at each rebuild. Errors seen
+ *    on the device (list overflow, non-finite values) are sticky and are
+ *    returned by the next sl_step or sl_get_* call.
+ *  - A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef SPINLAT_H
+#define SPINLAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SL_OK               0
+#define SL_E_ARG           -1  /* invalid argument or unnormalised spin     */
+#define SL_E_BOX           -2  /* box side below twice the list radius      */
+#define SL_E_NONFINITE     -3  /* NaN/Inf in the input or in the trajectory */
+#define SL_E_NBR_OVERFLOW  -4  /* more neighbours than max_nbr/max_spin_nbr  */
+#define SL_E_COLOR         -5  /* two interacting spins share a colour      */
+#define SL_E_HIP           -6  /* HIP runtime error                         */
+#define SL_E_STATE         -7  /* call out of order (e.g. step before state) */
+#define SL_E_NOMEM         -8  /* device allocation failed                  */
+
+#define SL_HOST   0
+#define SL_DEVICE 1
+
+#define SL_FP64   0            /* every quantity in FP64                     */
+#define SL_FP32   1            /* spins, omega, forces and rotations in FP32;
+                                  positions, velocities and reductions FP64 */
+
+typedef struct sl_system sl_system;
+
+/* Creation parameters. */
+typedef struct {
+    int64_t n_atoms;       /* N >= 1                                        */
+    double box[3];         /* orthorhombic periodic box sides, A            */
+    int precision;         /* SL_FP64 or SL_FP32                            */
+    int frozen;            /* 1: positions fixed, spin dynamics only        */
+    double skin;           /* Verlet skin, A (ignored when frozen)          */
+    int max_nbr;           /* list row capacity (0: default 80)             */
+    int max_spin_nbr;      /* spin-segment capacity (0: default 32)         */
+    uint64_t seed;         /* Philox key of the spin bath                   */
+    uint32_t replica;      /* replica index folded into the Philox counter  */
+    int thermo_every;      /* record E and M every n steps (0: never)       */
+    void *stream;          /* hipStream_t to run on; NULL: own stream       */
+} sl_params;
+
+/* Interaction parameters.
+ *  - Mechanical pair potential: Morse M(r) = D (e^{-2a(r-r0)} - 2 e^{-a(r-r0)})
+ *    for r < morse_rc; morse_shift = 1 uses the shifted-force form
+ *    M(r) - M(rc) - (r - rc) M'(rc) so V and V' are continuous at rc.
+ *  - Exchange (appendix A.1, Eq. BSfunction): Bethe-Slater
+ *    J(r) = 4 ex_alpha u (1 - ex_gamma u) e^{-u}, u = (r/ex_delta)^2, for
+ *    r < ex_rc; enters H as -sum_{i<j} J(r_ij) s_i.s_j (each pair once).
+ *  - Zeeman (Sec. 2, Eq. s_hamiltonian): -sum_i g mu_B B.s_i.
+ *  - Uniaxial anisotropy (appendix A.2): -sum_i K (s_i.n)^2.
+ *  - Spin bath (Sec. 4.1, Eq. sLLG): transverse damping lambda and white
+ *    noise at temperature T with D_S = lambda (1 + lambda^2) k_B T / hbar. */
+typedef struct {
+    int morse_on;
+    double morse_D, morse_alpha, morse_r0, morse_rc;
+    int morse_shift;
+    double ex_alpha, ex_gamma, ex_delta, ex_rc;
+    double zeeman_g;
+    double B[3];
+    double aniso_K;
+    double aniso_n[3];
+    double lambda;
+    double temperature;
+} sl_potential;
+
+/* Energies in eV: kinetic sum_i m v^2/2, pair, exchange, Zeeman, anisotropy. */
+typedef struct {
+    double kin, pair, exchange, zeeman, aniso, total;
+} sl_energy;
+
+typedef struct {
+    int64_t step;            /* step counter (Philox counter word)          */
+    int64_t rebuilds;        /* neighbour-list rebuilds so far              */
+    int n_colours;           /* current number of colour classes K         */
+    int jp_rounds;           /* colouring rounds of the last rebuild        */
+    int max_spin_nbr_seen;   /* largest spin segment of the last build      */
+    int max_nbr_seen;        /* largest row of the last build               */
+} sl_stats;
+
+/* Create a system. Fails with SL_E_ARG (bad sizes or precision) or SL_E_BOX
+ * (a box side shorter than twice the largest list radius, which would make
+ * the minimum image ambiguous; checked again at sl_set_potential). */
+int sl_create(const sl_params *p, sl_system **out);
+
+/* Destroy a system and free its device memory. NULL is allowed. */
+int sl_destroy(sl_system *sys);
+
+/* Set the state in user order (Sec. 3: X = (r, p, s); velocities here).
+ * r: double[N][3] unwrapped positions (may be NULL to keep the current);
+ * v: double[N][3] (NULL: keep); s: double[N][3] with ||s_i| - 1| <= 1e-12
+ * (otherwise SL_E_ARG; NULL: keep); mass: double[N] in amu, > 0 (NULL:
+ * keep). Any NaN/Inf gives SL_E_NONFINITE. Invalidates the forces, the
+ * neighbour list (unless user-supplied) and the colouring. */
+int sl_set_state(sl_system *sys, const double *r, const double *v,
+                 const double *s, const double *mass, int where);
+
+/* Copy the state out in user order; NULL outputs are skipped. Synchronises. */
+int sl_get_state(sl_system *sys, double *r, double *v, double *s, int where);
+
+/* Set the interactions (see sl_potential). Invalidates the list. */
+int sl_set_potential(sl_system *sys, const sl_potential *pot);
+
+/* Device cell-list neighbour build with Verlet skin `skin` and row capacity
+ * max_nbr (0 keeps the current values). Rows hold every j closer than
+ * max(cutoffs) + skin, the entries closer than ex_rc + skin first (the
+ * spin segment, which is also the graph the colouring must respect).
+ * Rebuild rule: before step k the list is rebuilt when
+ * max_i |r_i - r_i^build| + 2|dt| max_i |v_i|, taken at the boundary before
+ * step k-1, reaches skin/2 - 0.01 A. */
+int sl_set_neighbor(sl_system *sys, double skin, int max_nbr);
+
+/* User-supplied full list in CSR form over user ids: offsets[N+1], idx[].
+ * Each row is split (stably) into entries closer than ex_rc + skin first.
+ * Disables automatic rebuilds. */
+int sl_set_neighbor_list(sl_system *sys, const int *offsets, const int *idx,
+                         int where);
+
+/* Current list in user ids: nspin[N], nall[N] and rows concatenated in idx
+ * (row order as stored). Returns the total number of entries (>= 0) or an
+ * error; when cap is smaller than the total only the counts are written. */
+int64_t sl_get_neighbor_list(sl_system *sys, int *nspin, int *nall, int *idx,
+                             int64_t cap);
+
+/* Override the colouring (colour[N] in user order, values 0..63); validated
+ * against the spin segment of the list (SL_E_COLOR on conflict). */
+int sl_set_coloring(sl_system *sys, const int *colour, int where);
+
+/* Colouring in user order and the class count K. Synchronises. */
+int sl_get_coloring(sl_system *sys, int *colour, int *K);
+
+/* Set the step counter (used as a Philox counter word). */
+int sl_set_step(sl_system *sys, int64_t step);
+
+/* Advance n >= 0 steps of length dt (dt < 0 runs backwards). */
+int sl_step(sl_system *sys, int64_t n, double dt);
+
+/* Energy of the current state (computed now). Synchronises. */
+int sl_get_energy(sl_system *sys, sl_energy *out);
+
+/* M = sum_i s_i of the current state. Synchronises. */
+int sl_get_magnetization(sl_system *sys, double M[3]);
+
+/* Samples recorded every thermo_every steps since the last call: up to max
+ * entries of (step, energy, M[3]); *count receives the number written. */
+int sl_get_thermo(sl_system *sys, int max, int64_t *steps, sl_energy *e,
+                  double *M, int *count);
+
+int sl_get_stats(sl_system *sys, sl_stats *out);
+
+/* Wait for the system's stream; returns any sticky device error. */
+int sl_synchronize(sl_system *sys);
+
+/* Per-kernel timing with HIP events on the system's stream. When on, every
+ * launch of the spin-phase, force and rebuild kernels is bracketed by a
+ * pair of events; sl_get_profile returns, per kernel kind, the launch count
+ * and the summed event time in ms. Kinds: 0 spin phase, 1 force,
+ * 2 neighbour rebuild, 3 energy reduction. */
+int sl_set_profiling(sl_system *sys, int on);
+int sl_get_profile(sl_system *sys, int kind, int64_t *launches, double *ms,
+                   double *work_items);
+
+/* Message of the last failed call on this handle (or of the last failed
+ * sl_create when sys is NULL). Never NULL. */
+const char *sl_last_error(const sl_system *sys);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1266 @@
+// sl_api.hip -- host runtime behind the C ABI of spinlat.h: device buffers,
+// the rebuild pipeline (cells, lists, colour classes, permutation), the
+// step schedule and the observables. All per-step work runs in the kernels
+// of sl_dyn.hip; this file only orders launches on the system's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/spinlat.h"
+#include "sl_device.h"
+#include "sl_kernels.h"
+
+using namespace sl;
+
+namespace {
+
+thread_local std::string g_create_err = "";
+
+constexpr int kThermoCap = 1 << 16;
+constexpr int kJpBatch = 16;
+
+struct Atoms {
+  double *rx[2] = {nullptr, nullptr}, *ry[2] = {nullptr, nullptr}, *rz[2] = {nullptr, nullptr};
+  double *vx = nullptr, *vy = nullptr, *vz = nullptr;
+  double *bx = nullptr, *by = nullptr, *bz = nullptr;
+  double *mass = nullptr;
+  void *sx = nullptr, *sy = nullptr, *sz = nullptr;
+  int *id = nullptr, *colour = nullptr, *cell = nullptr;
+  int *nspin = nullptr, *nall = nullptr, *nbr = nullptr;
+};
+
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  double work;
+};
+
+struct SlotMeta {
+  int64_t boundary = -1;
+  double dt = 0.0;
+  bool rebuilt_after = false;
+};
+
+}  // namespace
+
+struct sl_system {
+  sl_params prm{};
+  sl_potential pot{};
+  PotConst pc{};
+  bool have_pot = false;
+  int n = 0, ld = 0, prec = SL_FP64;
+  double L[3] = {0, 0, 0}, invL[3] = {0, 0, 0};
+  double skin = 0.3;
+  int max_nbr = 80, max_spin = 32;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+
+  Atoms a[2];
+  int cur = 0;  // live Atoms copy
+  int pos = 0;  // position buffer holding the current boundary
+
+  // scratch
+  int ncell = 0, nc[3] = {1, 1, 1};
+  int *ccount = nullptr, *cstart = nullptr, *cfill = nullptr, *catoms = nullptr;
+  int cell_cap = 0;
+  int *bcount = nullptr, *bstart = nullptr, *bfill = nullptr;
+  int bin_cap = 0;
+  int *skey = nullptr, *perm = nullptr, *inv = nullptr, *uinv = nullptr, *ctmp = nullptr;
+  double *kx = nullptr, *ky = nullptr, *kz = nullptr;
+  double *stage = nullptr;  // 3n doubles
+  int *err = nullptr, *seen = nullptr, *jpcnt = nullptr, *maxc = nullptr;
+  unsigned long long *dslot = nullptr;
+  unsigned int *done = nullptr;
+  double *partial = nullptr, *red_out = nullptr;
+  double *thermo = nullptr;
+  double *ring = nullptr;      // pinned host [4][4]
+  double *ring_dev = nullptr;  // device alias of ring
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  SlotMeta meta[4];
+
+  // state
+  bool have_state = false, have_list = false, user_list = false, have_colour = false;
+  bool have_D = false;
+  int K = 0;
+  std::vector<int> class_off;
+  int64_t step = 0, rebuilds = 0;
+  int jp_rounds = 0, seen_spin = 0, seen_all = 0;
+  int sticky = 0;
+  std::vector<int64_t> thermo_steps;
+  int thermo_read = 0;
+
+  bool prof = false;
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t prof_launch[4] = {0, 0, 0, 0};
+  double prof_ms[4] = {0, 0, 0, 0};
+  double prof_work[4] = {0, 0, 0, 0};
+
+  std::string last_err;
+};
+
+namespace {
+
+int fail(sl_system *S, int code, const std::string &msg) {
+  if (S) S->last_err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+#define HIPCHK(S, x)                                                                      \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      return fail((S), SL_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define CHK(x)            \
+  do {                    \
+    int rc_ = (x);        \
+    if (rc_) return rc_;  \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+double list_radius(const sl_system *S) {
+  double rc = S->pot.ex_rc;
+  if (!S->prm.frozen && S->pot.morse_on && S->pot.morse_rc > rc) rc = S->pot.morse_rc;
+  return rc + (S->prm.frozen ? 0.0 : S->skin);
+}
+
+double spin_radius(const sl_system *S) {
+  return S->pot.ex_rc + (S->prm.frozen ? 0.0 : S->skin);
+}
+
+int check_box(sl_system *S) {
+  const double rl = list_radius(S);
+  for (int d = 0; d < 3; ++d)
+    if (S->L[d] < 2.0 * rl)
+      return fail(S, SL_E_BOX, "box side " + std::to_string(S->L[d]) +
+                                   " A is below twice the list radius " + std::to_string(rl));
+  return SL_OK;
+}
+
+void make_potconst(sl_system *S) {
+  const sl_potential &p = S->pot;
+  PotConst &c = S->pc;
+  std::memset(&c, 0, sizeof(c));
+  c.morse_on = (p.morse_on && !S->prm.frozen) ? 1 : 0;
+  c.mD = p.morse_D;
+  c.mA = p.morse_alpha;
+  c.mR0 = p.morse_r0;
+  c.mRc = p.morse_rc;
+  c.mRc2 = p.morse_rc * p.morse_rc;
+  if (p.morse_shift) {
+    const double e = std::exp(-p.morse_alpha * (p.morse_rc - p.morse_r0));
+    c.mMc = p.morse_D * (e * e - 2.0 * e);
+    c.mdMc = -2.0 * p.morse_alpha * p.morse_D * (e * e - e);
+  }
+  c.ex_on = (p.ex_alpha != 0.0 && p.ex_rc > 0.0) ? 1 : 0;
+  c.eA4 = 4.0 * p.ex_alpha;
+  c.eG = p.ex_gamma;
+  c.eInvD2 = 1.0 / (p.ex_delta * p.ex_delta);
+  c.eRc2 = p.ex_rc * p.ex_rc;
+  c.eA8InvD2 = 8.0 * p.ex_alpha / (p.ex_delta * p.ex_delta);
+  for (int d = 0; d < 3; ++d) {
+    c.zB[d] = p.zeeman_g * kMuB * p.B[d];
+    c.zw[d] = c.zB[d] / kHbar;
+    c.an[d] = p.aniso_n[d];
+  }
+  c.aK = p.aniso_K;
+  c.aK2h = 2.0 * p.aniso_K / kHbar;
+  c.aniso_on = p.aniso_K != 0.0 ? 1 : 0;
+  c.langevin = p.lambda > 0.0 ? 1 : 0;
+  c.lam = p.lambda;
+  c.lamfac = 1.0 / (1.0 + p.lambda * p.lambda);
+}
+
+template <typename real>
+SysView<real> view(sl_system *S, int posbuf) {
+  Atoms &A = S->a[S->cur];
+  SysView<real> v;
+  v.n = S->n;
+  v.ld = S->ld;
+  for (int d = 0; d < 3; ++d) {
+    v.L[d] = S->L[d];
+    v.invL[d] = S->invL[d];
+  }
+  v.rx = A.rx[posbuf];
+  v.ry = A.ry[posbuf];
+  v.rz = A.rz[posbuf];
+  v.sx = (real *)A.sx;
+  v.sy = (real *)A.sy;
+  v.sz = (real *)A.sz;
+  v.nbr = A.nbr;
+  v.nspin = A.nspin;
+  v.nall = A.nall;
+  v.id = A.id;
+  return v;
+}
+
+// --- profiling -------------------------------------------------------------
+hipEvent_t get_event(sl_system *S) {
+  if (!S->ev_pool.empty()) {
+    hipEvent_t e = S->ev_pool.back();
+    S->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+struct ProfScope {
+  sl_system *S;
+  int kind;
+  double work;
+  hipEvent_t a = nullptr;
+  ProfScope(sl_system *S_, int kind_, double work_) : S(S_), kind(kind_), work(work_) {
+    if (S->prof) {
+      a = get_event(S);
+      (void)hipEventRecord(a, S->st);
+    }
+  }
+  ~ProfScope() {
+    if (S->prof) {
+      hipEvent_t b = get_event(S);
+      (void)hipEventRecord(b, S->st);
+      S->prof_recs.push_back({kind, a, b, work});
+    }
+  }
+};
+
+void prof_collect(sl_system *S) {
+  if (S->prof_recs.empty()) return;
+  (void)hipStreamSynchronize(S->st);
+  for (auto &r : S->prof_recs) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    S->prof_launch[r.kind] += 1;
+    S->prof_ms[r.kind] += ms;
+    S->prof_work[r.kind] += r.work;
+    S->ev_pool.push_back(r.a);
+    S->ev_pool.push_back(r.b);
+  }
+  S->prof_recs.clear();
+}
+
+// --- device error word ------------------------------------------------------
+int read_err(sl_system *S) {
+  int e = 0;
+  HIPCHK(S, hipMemcpyAsync(&e, S->err, sizeof(int), hipMemcpyDeviceToHost, S->st));
+  HIPCHK(S, hipStreamSynchronize(S->st));
+  S->sticky |= e;
+  return SL_OK;
+}
+
+int sticky_code(sl_system *S) {
+  if (S->sticky & kErrNonFinite) return fail(S, SL_E_NONFINITE, "non-finite force, velocity or position");
+  if (S->sticky & kErrNbrOverflow)
+    return fail(S, SL_E_NBR_OVERFLOW, "neighbour row overflow: seen " + std::to_string(S->seen_all) +
+                                          " (spin " + std::to_string(S->seen_spin) + "), capacity " +
+                                          std::to_string(S->max_nbr) + " (spin " +
+                                          std::to_string(S->max_spin) + ")");
+  if (S->sticky & kErrColour) return fail(S, SL_E_COLOR, "two interacting spins share a colour");
+  return SL_OK;
+}
+
+// --- allocation -------------------------------------------------------------
+int alloc_atoms(sl_system *S, Atoms &A) {
+  const int n = S->n;
+  const size_t rs = S->prec == SL_FP64 ? sizeof(double) : sizeof(float);
+  for (int b = 0; b < 2; ++b) {
+    HIPCHK(S, dalloc(&A.rx[b], n));
+    HIPCHK(S, dalloc(&A.ry[b], n));
+    HIPCHK(S, dalloc(&A.rz[b], n));
+  }
+  HIPCHK(S, dalloc(&A.vx, n));
+  HIPCHK(S, dalloc(&A.vy, n));
+  HIPCHK(S, dalloc(&A.vz, n));
+  HIPCHK(S, dalloc(&A.bx, n));
+  HIPCHK(S, dalloc(&A.by, n));
+  HIPCHK(S, dalloc(&A.bz, n));
+  HIPCHK(S, dalloc(&A.mass, n));
+  HIPCHK(S, hipMalloc(&A.sx, rs * (n > 0 ? n : 1)));
+  HIPCHK(S, hipMalloc(&A.sy, rs * (n > 0 ? n : 1)));
+  HIPCHK(S, hipMalloc(&A.sz, rs * (n > 0 ? n : 1)));
+  HIPCHK(S, dalloc(&A.id, n));
+  HIPCHK(S, dalloc(&A.colour, n));
+  HIPCHK(S, dalloc(&A.cell, n));
+  HIPCHK(S, dalloc(&A.nspin, n));
+  HIPCHK(S, dalloc(&A.nall, n));
+  HIPCHK(S, dalloc(&A.nbr, (size_t)S->ld * S->max_nbr));
+  HIPCHK(S, hipMemsetAsync(A.nspin, 0, sizeof(int) * n, S->st));
+  HIPCHK(S, hipMemsetAsync(A.nall, 0, sizeof(int) * n, S->st));
+  return SL_OK;
+}
+
+void free_atoms(Atoms &A) {
+  for (int b = 0; b < 2; ++b) {
+    dfree(A.rx[b]); dfree(A.ry[b]); dfree(A.rz[b]);
+  }
+  dfree(A.vx); dfree(A.vy); dfree(A.vz);
+  dfree(A.bx); dfree(A.by); dfree(A.bz);
+  dfree(A.mass); dfree(A.sx); dfree(A.sy); dfree(A.sz);
+  dfree(A.id); dfree(A.colour); dfree(A.cell);
+  dfree(A.nspin); dfree(A.nall); dfree(A.nbr);
+  A = Atoms();
+}
+
+int ensure_cells(sl_system *S, int ncell) {
+  if (ncell + 1 <= S->cell_cap) return SL_OK;
+  dfree(S->ccount); dfree(S->cstart); dfree(S->cfill);
+  S->cell_cap = ncell + 1;
+  HIPCHK(S, dalloc(&S->ccount, S->cell_cap));
+  HIPCHK(S, dalloc(&S->cstart, S->cell_cap + 1));
+  HIPCHK(S, dalloc(&S->cfill, S->cell_cap));
+  return SL_OK;
+}
+
+int ensure_bins(sl_system *S, int nbin) {
+  if (nbin + 1 <= S->bin_cap) return SL_OK;
+  dfree(S->bcount); dfree(S->bstart); dfree(S->bfill);
+  S->bin_cap = nbin + 1;
+  HIPCHK(S, dalloc(&S->bcount, S->bin_cap));
+  HIPCHK(S, dalloc(&S->bstart, S->bin_cap + 1));
+  HIPCHK(S, dalloc(&S->bfill, S->bin_cap));
+  return SL_OK;
+}
+
+void cell_grid(sl_system *S, CellGrid &G) {
+  const double rl = list_radius(S);
+  for (int d = 0; d < 3; ++d) {
+    int k = rl > 0 ? (int)std::floor(S->L[d] / rl) : 1;
+    if (k < 3) k = 1;
+    if (k > 1024) k = 1024;
+    G.nc[d] = k;
+    G.L[d] = S->L[d];
+  }
+  // at most ~2 cells per atom: larger cells are still valid, only slower
+  const long cap = std::max<long>(2L * S->n, 27L);
+  while ((long)G.nc[0] * G.nc[1] * G.nc[2] > cap) {
+    int d = 0;
+    for (int e = 1; e < 3; ++e)
+      if (G.nc[e] > G.nc[d]) d = e;
+    if (G.nc[d] <= 3) break;
+    G.nc[d] = std::max(3, (G.nc[d] * 4) / 5);
+  }
+  for (int d = 0; d < 3; ++d) S->nc[d] = G.nc[d];
+  S->ncell = G.nc[0] * G.nc[1] * G.nc[2];
+}
+
+// Cell index of every atom at the current positions and the sorted cell
+// member lists (cstart/catoms).
+int bin_cells(sl_system *S, CellGrid &G) {
+  Atoms &A = S->a[S->cur];
+  cell_grid(S, G);
+  CHK(ensure_cells(S, S->ncell));
+  launch_zero_i(S->ncell, S->ccount, S->st);
+  launch_cell_assign(S->n, A.rx[S->pos], A.ry[S->pos], A.rz[S->pos], G, A.cell, S->ccount, S->st);
+  launch_scan(S->ccount, S->cstart, S->ncell, S->st);
+  launch_zero_i(S->ncell, S->cfill, S->st);
+  launch_bucket_scatter(S->n, A.cell, S->cstart, S->cfill, S->catoms, S->st);
+  launch_bucket_sort(S->ncell, S->cstart, S->catoms, S->st);
+  return SL_OK;
+}
+
+ColourArgs colour_args(sl_system *S) {
+  Atoms &A = S->a[S->cur];
+  ColourArgs C;
+  C.n = S->n;
+  C.ld = S->ld;
+  C.nbr = A.nbr;
+  C.nspin = A.nspin;
+  C.id = A.id;
+  C.kx = S->kx;
+  C.ky = S->ky;
+  C.kz = S->kz;
+  C.colour = A.colour;
+  return C;
+}
+
+int jp_rounds(sl_system *S, const ColourArgs &C) {
+  HIPCHK(S, hipMemsetAsync(S->jpcnt, 0, 2 * sizeof(int), S->st));
+  int r = 0;
+  for (;;) {
+    for (int b = 0; b < kJpBatch; ++b, ++r) launch_colour_round(C, &S->jpcnt[r & 1], &S->jpcnt[(r + 1) & 1], S->st);
+    int rem = 0;
+    HIPCHK(S, hipMemcpyAsync(&rem, &S->jpcnt[(r - 1) & 1], sizeof(int), hipMemcpyDeviceToHost, S->st));
+    HIPCHK(S, hipStreamSynchronize(S->st));
+    if (rem == 0) break;
+    if (r > S->n + 2 * kJpBatch) return fail(S, SL_E_COLOR, "colouring rounds made no progress");
+  }
+  S->jp_rounds = r;
+  return SL_OK;
+}
+
+// Colour classes (repairing the previous colouring when there is one) and
+// permutation of all per-atom arrays into (colour, cell) order.
+int colour_and_permute(sl_system *S, bool repair) {
+  ProfScope ps(S, 2, 0.0);
+  const int n = S->n;
+  CellGrid G;
+  {
+    Atoms &A = S->a[S->cur];
+    cell_grid(S, G);
+    CHK(ensure_cells(S, S->ncell));
+    launch_zero_i(S->ncell, S->ccount, S->st);
+    launch_cell_assign(n, A.rx[S->pos], A.ry[S->pos], A.rz[S->pos], G, A.cell, S->ccount, S->st);
+    launch_keys(n, A.rx[S->pos], A.ry[S->pos], A.rz[S->pos], S->L, S->kx, S->ky, S->kz, S->st);
+  }
+  ColourArgs C = colour_args(S);
+  if (!S->have_colour) {
+    launch_colour_fill(n, C.colour, -1, S->st);
+  } else if (repair) {
+    launch_colour_mark(C, S->ctmp, S->st);
+    HIPCHK(S, hipMemcpyAsync(C.colour, S->ctmp, sizeof(int) * n, hipMemcpyDeviceToDevice, S->st));
+  }
+  CHK(jp_rounds(S, C));
+  int mc = -1;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    HIPCHK(S, hipMemsetAsync(S->maxc, 0xff, sizeof(int), S->st));
+    launch_colour_stats(C, S->maxc, S->err, S->st);
+    HIPCHK(S, hipMemcpyAsync(&mc, S->maxc, sizeof(int), hipMemcpyDeviceToHost, S->st));
+    CHK(read_err(S));
+    CHK(sticky_code(S));
+    if (mc + 1 <= 32 || attempt == 1) break;
+    launch_colour_fill(n, C.colour, -1, S->st);  // too many colours: start over
+    CHK(jp_rounds(S, C));
+  }
+  S->K = n > 0 ? mc + 1 : 0;
+  S->have_colour = true;
+
+  // permutation: counting sort by colour * ncell + cell, buckets in old order
+  const int nbin = S->K * S->ncell;
+  CHK(ensure_bins(S, nbin));
+  Atoms &A = S->a[S->cur];
+  Atoms &B = S->a[1 - S->cur];
+  launch_zero_i(nbin, S->bcount, S->st);
+  launch_sort_key(n, A.colour, A.cell, S->ncell, S->skey, S->bcount, S->st);
+  launch_scan(S->bcount, S->bstart, nbin, S->st);
+  launch_zero_i(nbin, S->bfill, S->st);
+  launch_bucket_scatter(n, S->skey, S->bstart, S->bfill, S->perm, S->st);
+  launch_bucket_sort(nbin, S->bstart, S->perm, S->st);
+  launch_inverse(n, S->perm, S->inv, S->st);
+  PermuteArgs P;
+  std::memset(&P, 0, sizeof(P));
+  P.n = n;
+  P.perm = S->perm;
+  int k = 0;
+  for (int b = 0; b < 2; ++b) {
+    P.src_d[k] = A.rx[b]; P.dst_d[k++] = B.rx[b];
+    P.src_d[k] = A.ry[b]; P.dst_d[k++] = B.ry[b];
+    P.src_d[k] = A.rz[b]; P.dst_d[k++] = B.rz[b];
+  }
+  P.src_d[k] = A.vx; P.dst_d[k++] = B.vx;
+  P.src_d[k] = A.vy; P.dst_d[k++] = B.vy;
+  P.src_d[k] = A.vz; P.dst_d[k++] = B.vz;
+  P.src_d[k] = A.bx; P.dst_d[k++] = B.bx;
+  P.src_d[k] = A.by; P.dst_d[k++] = B.by;
+  P.src_d[k] = A.bz; P.dst_d[k++] = B.bz;
+  P.src_d[k] = A.mass; P.dst_d[k++] = B.mass;
+  if (S->prec == SL_FP64) {
+    P.src_d[k] = (const double *)A.sx; P.dst_d[k++] = (double *)B.sx;
+    P.src_d[k] = (const double *)A.sy; P.dst_d[k++] = (double *)B.sy;
+    P.src_d[k] = (const double *)A.sz; P.dst_d[k++] = (double *)B.sz;
+  } else {
+    P.src_f[0] = (const float *)A.sx; P.dst_f[0] = (float *)B.sx;
+    P.src_f[1] = (const float *)A.sy; P.dst_f[1] = (float *)B.sy;
+    P.src_f[2] = (const float *)A.sz; P.dst_f[2] = (float *)B.sz;
+    P.nf = 3;
+  }
+  P.nd = k;
+  P.src_i[0] = A.id; P.dst_i[0] = B.id;
+  P.src_i[1] = A.colour; P.dst_i[1] = B.colour;
+  P.src_i[2] = A.cell; P.dst_i[2] = B.cell;
+  P.ni = 3;
+  launch_permute_atoms(P, S->st);
+  launch_permute_nbr(n, S->ld, S->perm, S->inv, A.nbr, A.nspin, A.nall, B.nbr, B.nspin, B.nall, S->st);
+  S->cur = 1 - S->cur;
+  // class offsets = bucket starts of the first cell of every colour
+  std::vector<int> bs(nbin + 1);
+  HIPCHK(S, hipMemcpyAsync(bs.data(), S->bstart, sizeof(int) * (nbin + 1), hipMemcpyDeviceToHost, S->st));
+  HIPCHK(S, hipStreamSynchronize(S->st));
+  S->class_off.assign(S->K + 1, 0);
+  for (int c = 0; c <= S->K; ++c) S->class_off[c] = bs[(size_t)c * S->ncell];
+  return SL_OK;
+}
+
+// Full rebuild at the current boundary: cells, lists, colour repair, order.
+int rebuild(sl_system *S) {
+  if (S->user_list) return colour_and_permute(S, false);
+  CHK(check_box(S));
+  {
+    ProfScope ps(S, 2, (double)S->n);
+    CellGrid G;
+    CHK(bin_cells(S, G));
+    Atoms &A = S->a[S->cur];
+    NbrBuildArgs B;
+    B.n = S->n;
+    B.ld = S->ld;
+    B.max_nbr = S->max_nbr;
+    B.max_spin = S->max_spin;
+    const double rs = spin_radius(S), rl = std::max(list_radius(S), rs);
+    B.rs2 = rs * rs;
+    B.rl2 = rl * rl;
+    B.G = G;
+    B.rx = A.rx[S->pos];
+    B.ry = A.ry[S->pos];
+    B.rz = A.rz[S->pos];
+    B.cell = A.cell;
+    B.cstart = S->cstart;
+    B.catoms = S->catoms;
+    B.nbr = A.nbr;
+    B.nspin = A.nspin;
+    B.nall = A.nall;
+    B.bx = A.bx;
+    B.by = A.by;
+    B.bz = A.bz;
+    B.err = S->err;
+    B.seen = S->seen;
+    HIPCHK(S, hipMemsetAsync(S->seen, 0, 2 * sizeof(int), S->st));
+    launch_nbr_build(B, S->st);
+    int seen[2] = {0, 0};
+    HIPCHK(S, hipMemcpyAsync(seen, S->seen, sizeof(seen), hipMemcpyDeviceToHost, S->st));
+    CHK(read_err(S));
+    S->seen_spin = seen[0];
+    S->seen_all = seen[1];
+    CHK(sticky_code(S));
+  }
+  S->have_list = true;
+  S->rebuilds++;
+  return colour_and_permute(S, true);
+}
+
+int ensure_ready(sl_system *S) {
+  if (!S->have_state) return fail(S, SL_E_STATE, "no state set");
+  if (!S->have_pot) return fail(S, SL_E_STATE, "no potential set");
+  if (!S->have_list) {
+    CHK(rebuild(S));
+  } else if (!S->have_colour) {
+    CHK(colour_and_permute(S, false));
+  }
+  return SL_OK;
+}
+
+// --- launches ---------------------------------------------------------------
+template <typename real>
+void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps, const int *subs,
+                 double h) {
+  SpinPhaseArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.begin = S->class_off[c];
+  A.end = S->class_off[c + 1];
+  A.nrep = nrep;
+  A.h = h;
+  if (S->pc.langevin) {
+    const double lam = S->pot.lambda;
+    const double DS = lam * (1.0 + lam * lam) * kKb * S->pot.temperature / kHbar;
+    A.amp = std::sqrt(2.0 * DS / std::fabs(h));
+  }
+  for (int r = 0; r < nrep; ++r) {
+    A.step[r] = steps[r];
+    A.sub[r] = subs[r];
+  }
+  A.seed = S->prm.seed;
+  A.replica = S->prm.replica;
+  A.rs2 = S->pot.ex_rc * S->pot.ex_rc;
+  ProfScope ps(S, 0, (double)(A.end - A.begin));
+  launch_spin_phase<real>(view<real>(S, posbuf), S->pc, A, S->st);
+}
+
+// A run of dt/4 updates (class, step, sub) applied in order with merging of
+// consecutive updates of one class.
+struct Upd {
+  int c;
+  int64_t step;
+  int sub;
+};
+
+template <typename real>
+void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) {
+  size_t i = 0;
+  while (i < u.size()) {
+    int64_t steps[kMaxRep];
+    int subs[kMaxRep];
+    int nrep = 0;
+    const int c = u[i].c;
+    while (i < u.size() && u[i].c == c && nrep < kMaxRep) {
+      steps[nrep] = u[i].step;
+      subs[nrep] = u[i].sub;
+      ++nrep;
+      ++i;
+    }
+    spin_launch<real>(S, posbuf, c, nrep, steps, subs, h);
+  }
+}
+
+// Forward (classes 1..K) then backward (K..1) sweep of one spin half-step.
+void half_step_updates(const sl_system *S, int64_t step, int sub_fwd, std::vector<Upd> &u) {
+  for (int c = 0; c < S->K; ++c) u.push_back({c, step, sub_fwd});
+  for (int c = S->K - 1; c >= 0; --c) u.push_back({c, step, sub_fwd + 1});
+}
+
+template <typename real>
+int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary) {
+  Atoms &A = S->a[S->cur];
+  ForceArgs F;
+  std::memset(&F, 0, sizeof(F));
+  F.mode = mode;
+  F.dt = dt;
+  F.ftm2v = 1.0 / kMvv2e;
+  F.mass = A.mass;
+  F.vx = A.vx;
+  F.vy = A.vy;
+  F.vz = A.vz;
+  F.nx = A.rx[1 - posbuf];
+  F.ny = A.ry[1 - posbuf];
+  F.nz = A.rz[1 - posbuf];
+  F.bx = A.bx;
+  F.by = A.by;
+  F.bz = A.bz;
+  F.partial = S->partial;
+  F.dslot = S->dslot;
+  F.done = S->done;
+  F.err = S->err;
+  F.frozen = S->prm.frozen;
+  const int slot = (int)(boundary & 3);
+  F.host_out = S->ring_dev + 4 * slot;
+  if (mode & (kModeFinal | kModeNext)) {
+    S->ring[4 * slot + 3] = 0.0;
+    S->meta[slot].boundary = boundary;
+    S->meta[slot].dt = dt;
+    S->meta[slot].rebuilt_after = false;
+  }
+  {
+    ProfScope ps(S, 1, (double)S->n);
+    launch_force<real>(view<real>(S, posbuf), S->pc, F, S->st);
+  }
+  if (mode & (kModeFinal | kModeNext)) HIPCHK(S, hipEventRecord(S->ev[slot], S->st));
+  return SL_OK;
+}
+
+int record_thermo(sl_system *S, int64_t boundary) {
+  const int nb = (S->n + kBlock - 1) / kBlock;
+  const int k = (int)S->thermo_steps.size();
+  if (k >= kThermoCap) return SL_OK;
+  launch_reduce8(S->partial, nb, S->thermo + (size_t)k * 8, S->st);
+  S->thermo_steps.push_back(boundary);
+  return SL_OK;
+}
+
+template <typename real>
+int energy_now(sl_system *S, double out[8]) {
+  CHK(force_launch<real>(S, S->pos, kModeEnergy, 0.0, -1));
+  const int nb = (S->n + kBlock - 1) / kBlock;
+  launch_reduce8(S->partial, nb, S->red_out, S->st);
+  HIPCHK(S, hipMemcpyAsync(out, S->red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, S->st));
+  CHK(read_err(S));
+  return sticky_code(S);
+}
+
+// Wait until the force kernel of `boundary` finished and return its
+// rebuild predictor D (dmax + 2|dt| vmax), or -1 when not available.
+int wait_predictor(sl_system *S, int64_t boundary, double *D) {
+  *D = -1.0;
+  const int slot = (int)(boundary & 3);
+  if (boundary < 0 || S->meta[slot].boundary != boundary) return SL_OK;
+  HIPCHK(S, hipEventSynchronize(S->ev[slot]));
+  const double *o = S->ring + 4 * slot;
+  if (o[3] != 1.0) return fail(S, SL_E_HIP, "rebuild predictor not written");
+  S->sticky |= (int)o[2];
+  CHK(sticky_code(S));
+  const double dmax = S->meta[slot].rebuilt_after ? 0.0 : o[0];
+  *D = dmax + 2.0 * std::fabs(S->meta[slot].dt) * o[1];
+  return SL_OK;
+}
+
+template <typename real>
+int step_frozen(sl_system *S, int64_t n, double dt) {
+  const double h = dt / 4.0;
+  const int te = S->prm.thermo_every;
+  int64_t k = 0;
+  while (k < n) {
+    // steps up to the next thermo sample go in one merged update list
+    int64_t chunk = n - k;
+    if (te > 0) {
+      const int64_t to_sample = te - (S->step % te);
+      chunk = std::min(chunk, to_sample);
+    }
+    chunk = std::min<int64_t>(chunk, 64);
+    std::vector<Upd> u;
+    for (int64_t q = 0; q < chunk; ++q) {
+      half_step_updates(S, S->step + q, 0, u);
+      half_step_updates(S, S->step + q, 2, u);
+    }
+    run_updates<real>(S, S->pos, u, h);
+    S->step += chunk;
+    k += chunk;
+    if (te > 0 && S->step % te == 0) {
+      CHK(force_launch<real>(S, S->pos, kModeEnergy, 0.0, -1));
+      CHK(record_thermo(S, S->step));
+    }
+  }
+  return SL_OK;
+}
+
+template <typename real>
+int step_coupled(sl_system *S, int64_t n, double dt) {
+  const double h = dt / 4.0;
+  const double thr = S->skin / 2.0 - 0.01;
+  const int te = S->prm.thermo_every;
+  const int64_t k0 = S->step;
+  // decision for the first step uses the predictor of the boundary before it
+  if (!S->user_list && S->have_D) {
+    double D;
+    CHK(wait_predictor(S, k0 - 1, &D));
+    if (D >= thr) CHK(rebuild(S));
+  }
+  CHK(force_launch<real>(S, S->pos, kModeNext, dt, k0));
+  S->have_D = true;
+  for (int64_t k = k0; k < k0 + n; ++k) {
+    if (k > k0 && !S->user_list) {
+      double D;
+      CHK(wait_predictor(S, k - 1, &D));
+      if (D >= thr) {
+        CHK(rebuild(S));
+        S->meta[k & 3].rebuilt_after = true;
+      }
+    }
+    std::vector<Upd> u;
+    half_step_updates(S, k, 0, u);
+    run_updates<real>(S, S->pos, u, h);
+    u.clear();
+    half_step_updates(S, k, 2, u);
+    run_updates<real>(S, 1 - S->pos, u, h);
+    const int64_t b = k + 1;
+    int mode = kModeFinal;
+    if (k + 1 < k0 + n) mode |= kModeNext;
+    const bool sample = te > 0 && b % te == 0;
+    if (sample) mode |= kModeEnergy;
+    CHK(force_launch<real>(S, 1 - S->pos, mode, dt, b));
+    if (sample) CHK(record_thermo(S, b));
+    S->pos = 1 - S->pos;
+    S->step = b;
+  }
+  return SL_OK;
+}
+
+int load_aos(sl_system *S, const double *src, int where, std::vector<double> &host) {
+  const size_t bytes = sizeof(double) * 3 * (size_t)S->n;
+  host.resize(3 * (size_t)S->n);
+  if (where == SL_DEVICE) {
+    HIPCHK(S, hipMemcpyAsync(host.data(), src, bytes, hipMemcpyDeviceToHost, S->st));
+    HIPCHK(S, hipStreamSynchronize(S->st));
+  } else {
+    std::memcpy(host.data(), src, bytes);
+  }
+  return SL_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+int sl_create(const sl_params *p, sl_system **out) {
+  if (!out) return fail(nullptr, SL_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(nullptr, SL_E_ARG, "params is NULL");
+  if (p->n_atoms < 1 || p->n_atoms > (1 << 28)) return fail(nullptr, SL_E_ARG, "n_atoms out of range");
+  if (p->precision != SL_FP64 && p->precision != SL_FP32) return fail(nullptr, SL_E_ARG, "bad precision");
+  for (int d = 0; d < 3; ++d)
+    if (!(p->box[d] > 0.0) || !std::isfinite(p->box[d])) return fail(nullptr, SL_E_BOX, "box sides must be positive");
+  if (p->skin < 0.0) return fail(nullptr, SL_E_ARG, "negative skin");
+  if (p->max_nbr < 0 || p->max_spin_nbr < 0 || p->max_spin_nbr > 63)
+    return fail(nullptr, SL_E_ARG, "bad neighbour capacities");
+  sl_system *S = new sl_system();
+  S->prm = *p;
+  S->n = (int)p->n_atoms;
+  S->ld = (S->n + 63) / 64 * 64;
+  S->prec = p->precision;
+  for (int d = 0; d < 3; ++d) {
+    S->L[d] = p->box[d];
+    S->invL[d] = 1.0 / p->box[d];
+  }
+  S->skin = p->frozen ? 0.0 : p->skin;
+  S->max_nbr = p->max_nbr > 0 ? p->max_nbr : 80;
+  S->max_spin = p->max_spin_nbr > 0 ? p->max_spin_nbr : 32;
+  if (S->max_spin > S->max_nbr) S->max_spin = S->max_nbr;
+  int rc = SL_OK;
+  auto bail = [&](int code) {
+    g_create_err = S->last_err;
+    sl_destroy(S);
+    return code;
+  };
+  if (p->stream) {
+    S->st = (hipStream_t)p->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess) {
+      S->st = nullptr;
+      S->last_err = "hipStreamCreate failed";
+      return bail(SL_E_HIP);
+    }
+    S->own_stream = true;
+  }
+  if ((rc = alloc_atoms(S, S->a[0])) || (rc = alloc_atoms(S, S->a[1]))) return bail(rc == SL_E_HIP ? SL_E_NOMEM : rc);
+  const int n = S->n;
+  const int nb = (n + kBlock - 1) / kBlock;
+#define A_(x) if (hipSuccess != (x)) { S->last_err = #x; return bail(SL_E_NOMEM); }
+  A_(dalloc(&S->catoms, n));
+  A_(dalloc(&S->skey, n));
+  A_(dalloc(&S->perm, n));
+  A_(dalloc(&S->inv, n));
+  A_(dalloc(&S->uinv, n));
+  A_(dalloc(&S->ctmp, n));
+  A_(dalloc(&S->kx, n));
+  A_(dalloc(&S->ky, n));
+  A_(dalloc(&S->kz, n));
+  A_(dalloc(&S->stage, 3 * (size_t)n));
+  A_(dalloc(&S->err, 1));
+  A_(dalloc(&S->seen, 2));
+  A_(dalloc(&S->jpcnt, 2));
+  A_(dalloc(&S->maxc, 1));
+  A_(dalloc(&S->dslot, 2));
+  A_(dalloc(&S->done, 1));
+  A_(dalloc(&S->partial, (size_t)nb * 8));
+  A_(dalloc(&S->red_out, 8));
+  A_(dalloc(&S->thermo, (size_t)kThermoCap * 8));
+  A_(hipHostMalloc((void **)&S->ring, 16 * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
+  for (int k = 0; k < 4; ++k) A_(hipEventCreateWithFlags(&S->ev[k], hipEventDisableTiming));
+  A_(hipHostGetDevicePointer((void **)&S->ring_dev, S->ring, 0));
+#undef A_
+  std::memset(S->ring, 0, 16 * sizeof(double));
+  (void)hipMemsetAsync(S->err, 0, sizeof(int), S->st);
+  (void)hipMemsetAsync(S->dslot, 0, 2 * sizeof(unsigned long long), S->st);
+  (void)hipMemsetAsync(S->done, 0, sizeof(unsigned int), S->st);
+  launch_iota(n, S->a[0].id, S->st);
+  if (hipStreamSynchronize(S->st) != hipSuccess) {
+    S->last_err = "initial synchronisation failed";
+    return bail(SL_E_HIP);
+  }
+  *out = S;
+  return SL_OK;
+}
+
+int sl_destroy(sl_system *S) {
+  if (!S) return SL_OK;
+  if (S->st) (void)hipStreamSynchronize(S->st);
+  for (auto &r : S->prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : S->ev_pool) (void)hipEventDestroy(e);
+  for (int k = 0; k < 4; ++k)
+    if (S->ev[k]) (void)hipEventDestroy(S->ev[k]);
+  free_atoms(S->a[0]);
+  free_atoms(S->a[1]);
+  for (void *p : {(void *)S->ccount, (void *)S->cstart, (void *)S->cfill, (void *)S->catoms,
+                  (void *)S->bcount, (void *)S->bstart, (void *)S->bfill, (void *)S->skey,
+                  (void *)S->perm, (void *)S->inv, (void *)S->uinv, (void *)S->ctmp,
+                  (void *)S->kx, (void *)S->ky, (void *)S->kz, (void *)S->stage, (void *)S->err,
+                  (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
+                  (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo})
+    dfree(p);
+  if (S->ring) (void)hipHostFree(S->ring);
+  if (S->own_stream && S->st) (void)hipStreamDestroy(S->st);
+  delete S;
+  return SL_OK;
+}
+
+int sl_set_potential(sl_system *S, const sl_potential *pot) {
+  if (!S || !pot) return fail(S, SL_E_ARG, "NULL argument");
+  const double vals[] = {pot->morse_D, pot->morse_alpha, pot->morse_r0, pot->morse_rc,
+                         pot->ex_alpha, pot->ex_gamma, pot->ex_delta, pot->ex_rc, pot->zeeman_g,
+                         pot->B[0], pot->B[1], pot->B[2], pot->aniso_K, pot->aniso_n[0],
+                         pot->aniso_n[1], pot->aniso_n[2], pot->lambda, pot->temperature};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(S, SL_E_ARG, "non-finite potential parameter");
+  if (pot->ex_delta <= 0.0 || pot->ex_rc < 0.0 || pot->morse_rc < 0.0 || pot->lambda < 0.0 ||
+      pot->temperature < 0.0)
+    return fail(S, SL_E_ARG, "invalid potential parameter");
+  S->pot = *pot;
+  S->have_pot = true;
+  make_potconst(S);
+  CHK(check_box(S));
+  if (!S->user_list) S->have_list = false;
+  S->have_D = false;
+  return SL_OK;
+}
+
+int sl_set_state(sl_system *S, const double *r, const double *v, const double *s,
+                 const double *mass, int where) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  if (where != SL_HOST && where != SL_DEVICE) return fail(S, SL_E_ARG, "bad 'where'");
+  if (!S->have_state && (!r || !v || !s || !mass))
+    return fail(S, SL_E_ARG, "the first sl_set_state needs r, v, s and mass");
+  CHK(sl_synchronize(S));
+  const int n = S->n;
+  std::vector<double> hr, hv, hs, hm;
+  if (r) CHK(load_aos(S, r, where, hr));
+  if (v) CHK(load_aos(S, v, where, hv));
+  if (s) CHK(load_aos(S, s, where, hs));
+  if (mass) {
+    hm.resize(n);
+    if (where == SL_DEVICE) {
+      HIPCHK(S, hipMemcpy(hm.data(), mass, sizeof(double) * n, hipMemcpyDeviceToHost));
+    } else {
+      std::memcpy(hm.data(), mass, sizeof(double) * n);
+    }
+  }
+  for (auto *vec : {&hr, &hv, &hs, &hm})
+    for (double x : *vec)
+      if (!std::isfinite(x)) return fail(S, SL_E_NONFINITE, "non-finite value in the state");
+  for (double x : hm)
+    if (!(x > 0.0)) return fail(S, SL_E_ARG, "masses must be positive");
+  for (int i = 0; s && i < n; ++i) {
+    const double q = std::sqrt(hs[3 * i] * hs[3 * i] + hs[3 * i + 1] * hs[3 * i + 1] + hs[3 * i + 2] * hs[3 * i + 2]);
+    if (std::fabs(q - 1.0) > 1e-12) return fail(S, SL_E_ARG, "spin " + std::to_string(i) + " is not a unit vector");
+  }
+  Atoms &A = S->a[S->cur];
+  auto up = [&](const std::vector<double> &h, double *x, double *y, double *z) -> int {
+    HIPCHK(S, hipMemcpyAsync(S->stage, h.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, S->st));
+    launch_load_vec(n, A.id, S->stage, x, y, z, S->st);
+    HIPCHK(S, hipStreamSynchronize(S->st));
+    return SL_OK;
+  };
+  if (r) CHK(up(hr, A.rx[S->pos], A.ry[S->pos], A.rz[S->pos]));
+  if (v) CHK(up(hv, A.vx, A.vy, A.vz));
+  if (s) {
+    if (S->prec == SL_FP64) {
+      CHK(up(hs, (double *)A.sx, (double *)A.sy, (double *)A.sz));
+    } else {
+      HIPCHK(S, hipMemcpyAsync(S->stage, hs.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, S->st));
+      launch_load_vec_f(n, A.id, S->stage, (float *)A.sx, (float *)A.sy, (float *)A.sz, S->st);
+      HIPCHK(S, hipStreamSynchronize(S->st));
+    }
+  }
+  if (mass) {
+    HIPCHK(S, hipMemcpyAsync(S->stage, hm.data(), sizeof(double) * n, hipMemcpyHostToDevice, S->st));
+    launch_load_scalar(n, A.id, S->stage, A.mass, S->st);
+    HIPCHK(S, hipStreamSynchronize(S->st));
+  }
+  S->have_state = true;
+  if (!S->user_list) S->have_list = false;
+  S->have_colour = false;
+  S->have_D = false;
+  S->sticky = 0;
+  HIPCHK(S, hipMemsetAsync(S->err, 0, sizeof(int), S->st));
+  return SL_OK;
+}
+
+int sl_get_state(sl_system *S, double *r, double *v, double *s, int where) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  if (!S->have_state) return fail(S, SL_E_STATE, "no state set");
+  CHK(sl_synchronize(S));
+  const int n = S->n;
+  Atoms &A = S->a[S->cur];
+  auto down = [&](double *dst, const double *x, const double *y, const double *z, bool f32) -> int {
+    if (!dst) return SL_OK;
+    if (f32) launch_store_vec_f(n, A.id, (const float *)x, (const float *)y, (const float *)z, S->stage, S->st);
+    else launch_store_vec(n, A.id, x, y, z, S->stage, S->st);
+    HIPCHK(S, hipMemcpyAsync(dst, S->stage, sizeof(double) * 3 * n,
+                             where == SL_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, S->st));
+    HIPCHK(S, hipStreamSynchronize(S->st));
+    return SL_OK;
+  };
+  CHK(down(r, A.rx[S->pos], A.ry[S->pos], A.rz[S->pos], false));
+  CHK(down(v, A.vx, A.vy, A.vz, false));
+  CHK(down(s, (const double *)A.sx, (const double *)A.sy, (const double *)A.sz, S->prec == SL_FP32));
+  return SL_OK;
+}
+
+int sl_set_neighbor(sl_system *S, double skin, int max_nbr) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  if (skin < 0.0 || max_nbr < 0) return fail(S, SL_E_ARG, "bad skin or capacity");
+  if (!S->prm.frozen) S->skin = skin;
+  if (max_nbr > 0 && max_nbr != S->max_nbr) {
+    CHK(sl_synchronize(S));
+    dfree(S->a[0].nbr);
+    dfree(S->a[1].nbr);
+    S->a[0].nbr = S->a[1].nbr = nullptr;
+    S->max_nbr = max_nbr;
+    if (S->max_spin > max_nbr) S->max_spin = max_nbr;
+    HIPCHK(S, dalloc(&S->a[0].nbr, (size_t)S->ld * S->max_nbr));
+    HIPCHK(S, dalloc(&S->a[1].nbr, (size_t)S->ld * S->max_nbr));
+  }
+  S->user_list = false;
+  S->have_list = false;
+  S->have_D = false;
+  if (S->have_pot) CHK(check_box(S));
+  return SL_OK;
+}
+
+int sl_set_neighbor_list(sl_system *S, const int *offsets, const int *idx, int where) {
+  if (!S || !offsets) return fail(S, SL_E_ARG, "NULL argument");
+  if (!S->have_state || !S->have_pot) return fail(S, SL_E_STATE, "set state and potential first");
+  CHK(sl_synchronize(S));
+  const int n = S->n;
+  std::vector<int> off(n + 1);
+  if (where == SL_DEVICE) HIPCHK(S, hipMemcpy(off.data(), offsets, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+  else std::memcpy(off.data(), offsets, sizeof(int) * (n + 1));
+  if (off[0] != 0) return fail(S, SL_E_ARG, "offsets[0] must be 0");
+  for (int i = 0; i < n; ++i)
+    if (off[i + 1] < off[i]) return fail(S, SL_E_ARG, "offsets must be non-decreasing");
+  const int tot = off[n];
+  std::vector<int> ix(tot);
+  if (tot > 0) {
+    if (!idx) return fail(S, SL_E_ARG, "idx is NULL");
+    if (where == SL_DEVICE) HIPCHK(S, hipMemcpy(ix.data(), idx, sizeof(int) * tot, hipMemcpyDeviceToHost));
+    else std::memcpy(ix.data(), idx, sizeof(int) * tot);
+  }
+  for (int i = 0; i < n; ++i)
+    for (int p = off[i]; p < off[i + 1]; ++p)
+      if (ix[p] < 0 || ix[p] >= n || ix[p] == i) return fail(S, SL_E_ARG, "neighbour index out of range");
+  int *doff = nullptr, *didx = nullptr;
+  HIPCHK(S, dalloc(&doff, n + 1));
+  HIPCHK(S, dalloc(&didx, tot));
+  HIPCHK(S, hipMemcpy(doff, off.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+  if (tot > 0) HIPCHK(S, hipMemcpy(didx, ix.data(), sizeof(int) * tot, hipMemcpyHostToDevice));
+  Atoms &A = S->a[S->cur];
+  launch_user_inverse(n, A.id, S->uinv, S->st);
+  CsrArgs C;
+  C.n = n;
+  C.ld = S->ld;
+  C.max_nbr = S->max_nbr;
+  C.off = doff;
+  C.idx = didx;
+  C.id = A.id;
+  C.uinv = S->uinv;
+  C.rx = A.rx[S->pos];
+  C.ry = A.ry[S->pos];
+  C.rz = A.rz[S->pos];
+  for (int d = 0; d < 3; ++d) {
+    C.L[d] = S->L[d];
+    C.invL[d] = S->invL[d];
+  }
+  const double rs = spin_radius(S);
+  C.rs2 = rs * rs;
+  C.nbr = A.nbr;
+  C.nspin = A.nspin;
+  C.nall = A.nall;
+  C.bx = A.bx;
+  C.by = A.by;
+  C.bz = A.bz;
+  C.err = S->err;
+  launch_csr_to_ell(C, S->st);
+  CHK(read_err(S));
+  dfree(doff);
+  dfree(didx);
+  CHK(sticky_code(S));
+  S->user_list = true;
+  S->have_list = true;
+  S->have_D = false;
+  return SL_OK;
+}
+
+int64_t sl_get_neighbor_list(sl_system *S, int *nspin, int *nall, int *idx, int64_t cap) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  if (!S->have_list) return fail(S, SL_E_STATE, "no neighbour list");
+  CHK(sl_synchronize(S));
+  const int n = S->n;
+  Atoms &A = S->a[S->cur];
+  std::vector<int> ns(n), na(n), id(n), nb((size_t)S->ld * S->max_nbr);
+  HIPCHK(S, hipMemcpy(ns.data(), A.nspin, sizeof(int) * n, hipMemcpyDeviceToHost));
+  HIPCHK(S, hipMemcpy(na.data(), A.nall, sizeof(int) * n, hipMemcpyDeviceToHost));
+  HIPCHK(S, hipMemcpy(id.data(), A.id, sizeof(int) * n, hipMemcpyDeviceToHost));
+  HIPCHK(S, hipMemcpy(nb.data(), A.nbr, sizeof(int) * nb.size(), hipMemcpyDeviceToHost));
+  std::vector<int> uinv(n);
+  for (int i = 0; i < n; ++i) uinv[id[i]] = i;
+  int64_t tot = 0;
+  for (int u = 0; u < n; ++u) {
+    const int i = uinv[u];
+    if (nspin) nspin[u] = ns[i];
+    if (nall) nall[u] = na[i];
+    tot += na[i];
+  }
+  if (idx && cap >= tot) {
+    int64_t p = 0;
+    for (int u = 0; u < n; ++u) {
+      const int i = uinv[u];
+      for (int k = 0; k < na[i]; ++k) idx[p++] = id[nb[(size_t)k * S->ld + i]];
+    }
+  }
+  return tot;
+}
+
+int sl_set_coloring(sl_system *S, const int *colour, int where) {
+  if (!S || !colour) return fail(S, SL_E_ARG, "NULL argument");
+  CHK(ensure_ready(S));
+  CHK(sl_synchronize(S));
+  const int n = S->n;
+  std::vector<int> cu(n), id(n), ci(n);
+  if (where == SL_DEVICE) HIPCHK(S, hipMemcpy(cu.data(), colour, sizeof(int) * n, hipMemcpyDeviceToHost));
+  else std::memcpy(cu.data(), colour, sizeof(int) * n);
+  for (int x : cu)
+    if (x < 0 || x > 63) return fail(S, SL_E_ARG, "colours must lie in 0..63");
+  Atoms &A = S->a[S->cur];
+  HIPCHK(S, hipMemcpy(id.data(), A.id, sizeof(int) * n, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) ci[i] = cu[id[i]];
+  HIPCHK(S, hipMemcpy(A.colour, ci.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  ColourArgs C = colour_args(S);
+  HIPCHK(S, hipMemsetAsync(S->maxc, 0xff, sizeof(int), S->st));
+  launch_colour_stats(C, S->maxc, S->err, S->st);
+  CHK(read_err(S));
+  if (S->sticky & kErrColour) {
+    S->sticky &= ~kErrColour;
+    HIPCHK(S, hipMemset(S->err, 0, sizeof(int)));
+    S->have_colour = false;
+    return fail(S, SL_E_COLOR, "colouring puts two interacting spins in one class");
+  }
+  S->have_colour = true;
+  return colour_and_permute(S, false);
+}
+
+int sl_get_coloring(sl_system *S, int *colour, int *K) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  CHK(sl_synchronize(S));
+  if (K) *K = S->have_colour ? S->K : 0;
+  if (!colour) return SL_OK;
+  const int n = S->n;
+  if (!S->have_colour) {
+    for (int i = 0; i < n; ++i) colour[i] = -1;
+    return SL_OK;
+  }
+  Atoms &A = S->a[S->cur];
+  std::vector<int> id(n), ci(n);
+  HIPCHK(S, hipMemcpy(id.data(), A.id, sizeof(int) * n, hipMemcpyDeviceToHost));
+  HIPCHK(S, hipMemcpy(ci.data(), A.colour, sizeof(int) * n, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) colour[id[i]] = ci[i];
+  return SL_OK;
+}
+
+int sl_set_step(sl_system *S, int64_t step) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  CHK(sl_synchronize(S));
+  S->step = step;
+  for (auto &m : S->meta) m = SlotMeta();
+  S->have_D = false;
+  return SL_OK;
+}
+
+int sl_step(sl_system *S, int64_t n, double dt) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  if (n < 0 || !std::isfinite(dt)) return fail(S, SL_E_ARG, "bad step count or dt");
+  CHK(ensure_ready(S));
+  CHK(sticky_code(S));
+  if (n == 0) return SL_OK;
+  if (S->prm.frozen)
+    return S->prec == SL_FP64 ? step_frozen<double>(S, n, dt) : step_frozen<float>(S, n, dt);
+  return S->prec == SL_FP64 ? step_coupled<double>(S, n, dt) : step_coupled<float>(S, n, dt);
+}
+
+int sl_get_energy(sl_system *S, sl_energy *out) {
+  if (!S || !out) return fail(S, SL_E_ARG, "NULL argument");
+  CHK(sl_synchronize(S));
+  CHK(ensure_ready(S));
+  double e[8];
+  CHK(S->prec == SL_FP64 ? energy_now<double>(S, e) : energy_now<float>(S, e));
+  out->kin = e[0];
+  out->pair = e[1];
+  out->exchange = e[2];
+  out->zeeman = e[3];
+  out->aniso = e[4];
+  out->total = e[0] + e[1] + e[2] + e[3] + e[4];
+  return SL_OK;
+}
+
+int sl_get_magnetization(sl_system *S, double M[3]) {
+  if (!S || !M) return fail(S, SL_E_ARG, "NULL argument");
+  CHK(sl_synchronize(S));
+  CHK(ensure_ready(S));
+  double e[8];
+  CHK(S->prec == SL_FP64 ? energy_now<double>(S, e) : energy_now<float>(S, e));
+  M[0] = e[5];
+  M[1] = e[6];
+  M[2] = e[7];
+  return SL_OK;
+}
+
+int sl_get_thermo(sl_system *S, int max, int64_t *steps, sl_energy *e, double *M, int *count) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  CHK(sl_synchronize(S));
+  const int avail = (int)S->thermo_steps.size() - S->thermo_read;
+  const int k = std::max(0, std::min(max, avail));
+  if (k > 0) {
+    std::vector<double> buf((size_t)k * 8);
+    HIPCHK(S, hipMemcpy(buf.data(), S->thermo + (size_t)S->thermo_read * 8, sizeof(double) * 8 * k,
+                        hipMemcpyDeviceToHost));
+    for (int q = 0; q < k; ++q) {
+      const double *b = &buf[(size_t)q * 8];
+      if (steps) steps[q] = S->thermo_steps[S->thermo_read + q];
+      if (e) {
+        e[q].kin = b[0]; e[q].pair = b[1]; e[q].exchange = b[2]; e[q].zeeman = b[3]; e[q].aniso = b[4];
+        e[q].total = b[0] + b[1] + b[2] + b[3] + b[4];
+      }
+      if (M) { M[3 * q] = b[5]; M[3 * q + 1] = b[6]; M[3 * q + 2] = b[7]; }
+    }
+    S->thermo_read += k;
+  }
+  if (S->thermo_read == (int)S->thermo_steps.size()) {
+    S->thermo_steps.clear();
+    S->thermo_read = 0;
+  }
+  if (count) *count = k;
+  return SL_OK;
+}
+
+int sl_get_stats(sl_system *S, sl_stats *out) {
+  if (!S || !out) return fail(S, SL_E_ARG, "NULL argument");
+  out->step = S->step;
+  out->rebuilds = S->rebuilds;
+  out->n_colours = S->have_colour ? S->K : 0;
+  out->jp_rounds = S->jp_rounds;
+  out->max_spin_nbr_seen = S->seen_spin;
+  out->max_nbr_seen = S->seen_all;
+  return SL_OK;
+}
+
+int sl_synchronize(sl_system *S) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  HIPCHK(S, hipStreamSynchronize(S->st));
+  CHK(read_err(S));
+  return sticky_code(S);
+}
+
+int sl_set_profiling(sl_system *S, int on) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  if (S->prof && !on) prof_collect(S);
+  S->prof = on != 0;
+  for (int k = 0; k < 4; ++k) {
+    S->prof_launch[k] = 0;
+    S->prof_ms[k] = 0.0;
+    S->prof_work[k] = 0.0;
+  }
+  return SL_OK;
+}
+
+int sl_get_profile(sl_system *S, int kind, int64_t *launches, double *ms, double *work_items) {
+  if (!S || kind < 0 || kind > 3) return fail(S, SL_E_ARG, "bad argument");
+  prof_collect(S);
+  if (launches) *launches = S->prof_launch[kind];
+  if (ms) *ms = S->prof_ms[kind];
+  if (work_items) *work_items = S->prof_work[kind];
+  return SL_OK;
+}
+
+const char *sl_last_error(const sl_system *S) {
+  if (!S) return g_create_err.c_str();
+  return S->last_err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// sl_device.h -- device-side helpers and kernel argument blocks of the
+// gfx950 spin-lattice library. Layout in HBM: one array per component
+// (structure of arrays) in the library's internal atom order, which groups
+// atoms by colour class and, inside a class, by cell; neighbour lists are
+// ELL blocks, entry k of atom i at nbr[k * ld + i] so that a wavefront
+// reading entry k of 64 consecutive atoms makes one coalesced access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sl {
+
+// Physical constants (CODATA 2018).
+constexpr double kHbar = 6.582119569e-4;       // eV ps
+constexpr double kKb = 8.617333262e-5;         // eV/K
+constexpr double kMuB = 5.7883818060e-5;       // eV/T
+constexpr double kMvv2e = 1.0364269652680506e-4;  // eV per amu A^2/ps^2
+
+constexpr int kMaxRep = 4;        // consecutive updates one spin launch can do
+constexpr int kBlock = 256;       // threads per block of the per-atom kernels
+
+// Sticky device error bits.
+enum : int { kErrNbrOverflow = 1, kErrNonFinite = 2, kErrColour = 4 };
+
+// Interaction constants, precomputed on the host.
+struct PotConst {
+  int morse_on;
+  double mD, mA, mR0, mRc2;
+  double mMc, mdMc, mRc;  // shifted-force offsets M(rc), M'(rc); 0 if plain
+  int ex_on;
+  double eA4, eG, eInvD2, eRc2, eA8InvD2;  // 4 alpha, gamma, 1/delta^2, rc^2, 8 alpha/delta^2
+  double zw[3];       // g mu_B B / hbar, rad/ps
+  double zB[3];       // g mu_B B, eV (energy)
+  double aK;          // K, eV
+  double aK2h;        // 2K/hbar
+  double an[3];
+  int aniso_on;
+  int langevin;
+  double lam, lamfac;  // lambda, 1/(1+lambda^2)
+};
+
+// Per-system geometry and arrays (device pointers).
+template <typename real>
+struct SysView {
+  int n;          // atoms
+  int ld;         // leading dimension of the ELL lists (>= n, padded)
+  double L[3], invL[3];
+  const double *rx, *ry, *rz;  // positions used by this launch
+  real *sx, *sy, *sz;          // spins
+  const int *nbr;              // ELL neighbour indices
+  const int *nspin, *nall;     // segment lengths
+  const int *id;               // user id of each internal atom
+};
+
+struct SpinPhaseArgs {
+  int begin, end;             // atoms [begin, end) = one colour class
+  int nrep;                   // consecutive updates of this class (1..4)
+  double h;                   // dt/4 (signed)
+  double amp;                 // sqrt(2 D_S / |h|), noise amplitude
+  int64_t step[kMaxRep];      // step counter of each update
+  int sub[kMaxRep];           // sub-update index 0..3 of each update
+  uint64_t seed;
+  uint32_t replica;
+  double rs2;                 // exchange cutoff squared
+};
+
+struct ForceArgs {
+  int mode;                   // bit 1: final kick, 2: next kick + drift, 4: energy
+  double dt;
+  double ftm2v;               // 1/kMvv2e
+  const double *mass;
+  double *vx, *vy, *vz;
+  double *nx, *ny, *nz;       // next positions (drift target)
+  const double *bx, *by, *bz; // positions at the last build
+  double *partial;            // [nblocks][8] energy and M partial sums
+  unsigned long long *dslot;  // [2] device max of |r - r_build| and |v| (bits)
+  unsigned int *done;         // block completion counter
+  double *host_out;           // pinned host: {dmax, vmax, err}
+  int *err;                   // sticky error word (device)
+  int frozen;
+};
+
+enum : int { kModeFinal = 1, kModeNext = 2, kModeEnergy = 4 };
+
+// -------------------------------------------------------------------------
+// Block index -> work tile. Consecutive blocks are dispatched round robin
+// over the 8 XCDs, each with its own L2; remap so that every XCD receives a
+// contiguous range of tiles (spatially adjacent atoms share neighbours, so
+// their gathers hit the same L2).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int nx = 8;
+  int x = b % nx, k = b / nx;
+  int q = nb / nx, r = nb % nx;
+  return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ double min_image(double d, double L, double invL) {
+  return d - L * rint(d * invL);
+}
+
+// -------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): a 10-round bijection
+// of a 128-bit counter under a 64-bit key.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    uint32_t lo0 = M0 * c[0], hi0 = __umulhi(M0, c[0]);
+    uint32_t lo1 = M1 * c[2], hi1 = __umulhi(M1, c[2]);
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0; k1 += W1;
+  }
+}
+
+// Three standard normals for one spin update: counter (atom id, step lo,
+// step hi, replica<<2|sub), key (seed lo, seed hi); u = (x + 1/2) 2^-32 and
+// Box-Muller on (u0, u1) and (u2, u3).
+__device__ __forceinline__ void gauss3(uint64_t seed, uint32_t id, int64_t step,
+                                       uint32_t replica, int sub, double g[3]) {
+  uint32_t c[4] = {id, (uint32_t)((uint64_t)step & 0xffffffffu),
+                   (uint32_t)((uint64_t)step >> 32), (replica << 2) | (uint32_t)(sub & 3)};
+  philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  const double s = 1.0 / 4294967296.0;
+  const double twopi = 6.283185307179586;
+  double u0 = ((double)c[0] + 0.5) * s, u1 = ((double)c[1] + 0.5) * s;
+  double u2 = ((double)c[2] + 0.5) * s, u3 = ((double)c[3] + 0.5) * s;
+  double ra = sqrt(-2.0 * log(u0)), rb = sqrt(-2.0 * log(u2));
+  double sn, cs;
+  sincos(twopi * u1, &sn, &cs);
+  g[0] = ra * cs;
+  g[1] = ra * sn;
+  g[2] = rb * cos(twopi * u3);
+}
+
+__device__ __forceinline__ void gauss3(uint64_t seed, uint32_t id, int64_t step,
+                                       uint32_t replica, int sub, float g[3]) {
+  uint32_t c[4] = {id, (uint32_t)((uint64_t)step & 0xffffffffu),
+                   (uint32_t)((uint64_t)step >> 32), (replica << 2) | (uint32_t)(sub & 3)};
+  philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  const float s = 2.3283064365386963e-10f;
+  const float twopi = 6.2831853071795865f;
+  float u0 = ((float)(c[0] >> 8) + 0.5f) * (s * 256.0f);
+  float u1 = ((float)(c[1] >> 8) + 0.5f) * (s * 256.0f);
+  float u2 = ((float)(c[2] >> 8) + 0.5f) * (s * 256.0f);
+  float u3 = ((float)(c[3] >> 8) + 0.5f) * (s * 256.0f);
+  float ra = sqrtf(-2.0f * logf(u0)), rb = sqrtf(-2.0f * logf(u2));
+  float sn, cs;
+  sincosf(twopi * u1, &sn, &cs);
+  g[0] = ra * cs;
+  g[1] = ra * sn;
+  g[2] = rb * cosf(twopi * u3);
+}
+
+// -------------------------------------------------------------------------
+// Wavefront (64 lanes) and block reductions.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+}  // namespace sl

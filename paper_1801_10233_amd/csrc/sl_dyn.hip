@@ -1,0 +1,301 @@
+// sl_dyn.hip -- per-step kernels of the spin-lattice step on gfx950:
+//   * k_spin_phase: one colour class of a spin sweep (Sec. 3 / Sec. 5.1);
+//   * k_force:      pair + magneto-mechanical force (Eq. p_advance), fused
+//                   with the velocity-Verlet half kicks and the drift into
+//                   the other position buffer, energies on sampled steps
+//                   and the rebuild predictor;
+//   * k_reduce8:    fixed-order second pass of the block partial sums.
+// One thread per atom; per-atom data in structure-of-arrays form so the
+// own-atom loads and stores of a wavefront are fully coalesced, neighbour
+// data gathered through L2 (atoms are sorted by cell inside a class).
+#include "sl_device.h"
+#include "sl_kernels.h"
+
+namespace sl {
+
+// ---------------------------------------------------------------------------
+// Spin colour phase. For every atom i of one class (no two of them
+// interact): omega_i = (1/hbar)[sum_j J(r_ij) s_j + g mu_B B + 2K(s_i.n)n]
+// over the spin segment of its list, then s_i is rotated in closed form by
+// the Cayley map with step h (Sec. 3). With the spin bath, the rotation
+// vector is W = (omega + eta + lambda s x omega)/(1 + lambda^2) with eta
+// drawn from the Philox stream of (atom id, step, replica, sub-update)
+// (Sec. 4.1, Eq. sLLG). nrep > 1 applies consecutive updates of the same
+// class in one launch (nothing else changes in between); the exchange sum
+// does not depend on s_i, so it is gathered once.
+template <typename real, bool LANGEVIN, bool ANISO>
+__global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst P,
+                                                       SpinPhaseArgs A) {
+  const int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = A.begin + t;
+  if (i >= A.end) return;
+  const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
+  real ax = 0, ay = 0, az = 0;
+  const int ns = S.nspin[i];
+  const int ld = S.ld;
+  for (int k = 0; k < ns; ++k) {
+    const int j = S.nbr[(size_t)k * ld + i];
+    const double dx = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
+    const double dy = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
+    const double dz = min_image(riz - S.rz[j], S.L[2], S.invL[2]);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < A.rs2) {
+      const real u = (real)(r2 * P.eInvD2);
+      const real J = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+      ax += J * S.sx[j];
+      ay += J * S.sy[j];
+      az += J * S.sz[j];
+    }
+  }
+  real sx = S.sx[i], sy = S.sy[i], sz = S.sz[i];
+  const real h = (real)A.h;
+  const real ih = (real)(1.0 / kHbar);
+  for (int rep = 0; rep < A.nrep; ++rep) {
+    real ex = ax + (real)P.zB[0], ey = ay + (real)P.zB[1], ez = az + (real)P.zB[2];
+    if (ANISO) {
+      const real sn2 = (real)2 * (real)P.aK * (sx * (real)P.an[0] + sy * (real)P.an[1] + sz * (real)P.an[2]);
+      ex += sn2 * (real)P.an[0];
+      ey += sn2 * (real)P.an[1];
+      ez += sn2 * (real)P.an[2];
+    }
+    real wx, wy, wz;
+    if (sizeof(real) == 8) {
+      wx = ex / (real)kHbar; wy = ey / (real)kHbar; wz = ez / (real)kHbar;
+    } else {
+      wx = ex * ih; wy = ey * ih; wz = ez * ih;
+    }
+    if (LANGEVIN) {
+      real g[3];
+      gauss3(A.seed, (uint32_t)S.id[i], A.step[rep], A.replica, A.sub[rep], g);
+      const real lam = (real)P.lam, amp = (real)A.amp, den = (real)1 + lam * lam;
+      const real cx = sy * wz - sz * wy, cy = sz * wx - sx * wz, cz = sx * wy - sy * wx;
+      wx = (wx + amp * g[0] + lam * cx) / den;
+      wy = (wy + amp * g[1] + lam * cy) / den;
+      wz = (wz + amp * g[2] + lam * cz) / den;
+    }
+    // Cayley rotation of Sec. 3 (Omelyan): exact rotation about W by
+    // 2 atan(h|W|/2); preserves |s| in exact arithmetic.
+    const real cx = wy * sz - wz * sy, cy = wz * sx - wx * sz, cz = wx * sy - wy * sx;
+    const real ws = wx * sx + wy * sy + wz * sz;
+    const real w2 = wx * wx + wy * wy + wz * wz;
+    const real den = (real)1 + h * h * w2 / (real)4;
+    const real q = h * h / (real)4;
+    real nx = (sx + h * cx + q * ((real)2 * wx * ws - w2 * sx)) / den;
+    real ny = (sy + h * cy + q * ((real)2 * wy * ws - w2 * sy)) / den;
+    real nz = (sz + h * cz + q * ((real)2 * wz * ws - w2 * sz)) / den;
+    if (sizeof(real) == 4) {
+      // FP32 form: renormalise after every rotation.
+      const real inv = (real)rsqrtf((float)(nx * nx + ny * ny + nz * nz));
+      nx *= inv; ny *= inv; nz *= inv;
+    }
+    sx = nx; sy = ny; sz = nz;
+  }
+  S.sx[i] = sx;
+  S.sy[i] = sy;
+  S.sz[i] = sz;
+}
+
+// ---------------------------------------------------------------------------
+// Force, kicks and drift at one step boundary. With e_ij = (r_i - r_j)/r:
+//   F_i = sum_j [-V'(r) + J'(r) s_i.s_j] e_ij        (Eq. p_advance)
+// over the full list (both i and j own the pair, no atomics), then
+//   FINAL: v += (dt/2) F/m              (last half kick of the step)
+//   NEXT:  v += (dt/2) F/m; r' = r + dt v  (first half kick and drift of the
+//          next step, written to the other position buffer)
+//   ENERGY: per-atom energies (pairs halved) and M, block partial sums.
+// Every launch with a kick also reduces max |r - r_build| and max |v| at
+// this boundary for the rebuild decision; the last block to finish hands
+// them, with the sticky error word, to pinned host memory.
+template <typename real, int MODE>
+__global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
+  __shared__ double red[kBlock / 64][8];
+  __shared__ double redm[kBlock / 64][2];
+  __shared__ int last;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int i = tile * kBlock + threadIdx.x;
+  double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double dm = 0.0, vm = 0.0;
+  if (i < S.n) {
+    const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
+    const real six = S.sx[i], siy = S.sy[i], siz = S.sz[i];
+    real fx = 0, fy = 0, fz = 0;
+    real ep = 0, ee = 0;
+    const int na = S.nall[i];
+    const int ld = S.ld;
+    for (int k = 0; k < na; ++k) {
+      const int j = S.nbr[(size_t)k * ld + i];
+      const double dxd = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
+      const double dyd = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
+      const double dzd = min_image(riz - S.rz[j], S.L[2], S.invL[2]);
+      const double r2d = dxd * dxd + dyd * dyd + dzd * dzd;
+      const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd;
+      const real r = (real)sqrt(r2d);
+      real c = 0;
+      if (P.morse_on && r2d < P.mRc2) {
+        const real ex = exp(-(real)P.mA * (r - (real)P.mR0));
+        const real dM = -(real)2 * (real)P.mA * (real)P.mD * (ex * ex - ex);
+        c -= dM - (real)P.mdMc;
+        if (MODE & kModeEnergy)
+          ep += (real)0.5 * ((real)P.mD * (ex * ex - (real)2 * ex) - (real)P.mMc -
+                             (r - (real)P.mRc) * (real)P.mdMc);
+      }
+      if (P.ex_on && r2d < P.eRc2) {
+        const real u = (real)(r2d * P.eInvD2);
+        const real eu = exp(-u);
+        const real sisj = six * S.sx[j] + siy * S.sy[j] + siz * S.sz[j];
+        const real dJ = (real)P.eA8InvD2 * r * eu *
+                        ((real)1 - ((real)1 + (real)2 * (real)P.eG) * u + (real)P.eG * u * u);
+        c += dJ * sisj;
+        if (MODE & kModeEnergy)
+          ee -= (real)0.5 * (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * eu * sisj;
+      }
+      fx += c * dx / r;
+      fy += c * dy / r;
+      fz += c * dz / r;
+    }
+    if (!isfinite((double)fx) || !isfinite((double)fy) || !isfinite((double)fz))
+      atomicOr(A.err, kErrNonFinite);
+    if (MODE & (kModeFinal | kModeNext)) {
+      const double m = A.mass[i];
+      double vx = A.vx[i], vy = A.vy[i], vz = A.vz[i];
+      const double kx = 0.5 * A.dt * (double)fx / m * A.ftm2v;
+      const double ky = 0.5 * A.dt * (double)fy / m * A.ftm2v;
+      const double kz = 0.5 * A.dt * (double)fz / m * A.ftm2v;
+      if (MODE & kModeFinal) { vx += kx; vy += ky; vz += kz; }
+      if (MODE & kModeEnergy) e[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz) * kMvv2e;
+      // rebuild predictor at this boundary
+      {
+        const double bx = rix - A.bx[i], by = riy - A.by[i], bz = riz - A.bz[i];
+        dm = sqrt(bx * bx + by * by + bz * bz);
+        vm = sqrt(vx * vx + vy * vy + vz * vz);
+      }
+      if (MODE & kModeNext) {
+        vx += kx; vy += ky; vz += kz;
+        const double nx = rix + A.dt * vx, ny = riy + A.dt * vy, nz = riz + A.dt * vz;
+        A.nx[i] = nx; A.ny[i] = ny; A.nz[i] = nz;
+        if (!isfinite(nx) || !isfinite(ny) || !isfinite(nz)) atomicOr(A.err, kErrNonFinite);
+      }
+      A.vx[i] = vx; A.vy[i] = vy; A.vz[i] = vz;
+    } else if (MODE & kModeEnergy) {
+      const double m = A.mass[i];
+      const double vx = A.vx[i], vy = A.vy[i], vz = A.vz[i];
+      e[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz) * kMvv2e;
+    }
+    if (MODE & kModeEnergy) {
+      e[1] = (double)ep;
+      e[2] = (double)ee;
+      e[3] = -(P.zB[0] * (double)six + P.zB[1] * (double)siy + P.zB[2] * (double)siz);
+      const double sn = P.an[0] * (double)six + P.an[1] * (double)siy + P.an[2] * (double)siz;
+      e[4] = -P.aK * sn * sn;
+      e[5] = (double)six; e[6] = (double)siy; e[7] = (double)siz;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (MODE & kModeEnergy) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double x = wave_sum(e[c]);
+      if (lane == 0) red[wv][c] = x;
+    }
+  }
+  if (MODE & (kModeFinal | kModeNext)) {
+    const double a = wave_max(dm), b = wave_max(vm);
+    if (lane == 0) { redm[wv][0] = a; redm[wv][1] = b; }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (MODE & kModeEnergy) {
+      for (int c = 0; c < 8; ++c) {
+        double x = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) x += red[w][c];
+        A.partial[(size_t)tile * 8 + c] = x;
+      }
+    }
+    last = 0;
+    if (MODE & (kModeFinal | kModeNext)) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) { a = fmax(a, redm[w][0]); b = fmax(b, redm[w][1]); }
+      // non-negative doubles order like their bit patterns
+      atomicMax(&A.dslot[0], (unsigned long long)__double_as_longlong(a));
+      atomicMax(&A.dslot[1], (unsigned long long)__double_as_longlong(b));
+      __threadfence();
+      const unsigned prev = atomicAdd(A.done, 1u);
+      last = (prev == gridDim.x - 1);
+    }
+  }
+  __syncthreads();
+  if ((MODE & (kModeFinal | kModeNext)) && last && threadIdx.x == 0) {
+    __threadfence();
+    const unsigned long long a = atomicExch(&A.dslot[0], 0ull);
+    const unsigned long long b = atomicExch(&A.dslot[1], 0ull);
+    atomicExch(A.done, 0u);
+    const int err = atomicOr(A.err, 0);
+    A.host_out[0] = __longlong_as_double((long long)a);
+    A.host_out[1] = __longlong_as_double((long long)b);
+    A.host_out[2] = (double)err;
+    A.host_out[3] = 1.0;  // written marker
+  }
+}
+
+// Fixed-order sum of nb partial rows of 8 doubles (deterministic result).
+__global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, double *out) {
+  __shared__ double buf[256][8];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += 256)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] += partial[(size_t)b * 8 + c];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) buf[threadIdx.x][c] = acc[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) buf[threadIdx.x][c] += buf[threadIdx.x + w][c];
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) out[threadIdx.x] = buf[0][threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+template <typename real>
+void launch_spin_phase(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
+                       hipStream_t st) {
+  const int cnt = A.end - A.begin;
+  if (cnt <= 0) return;
+  const int nb = (cnt + kBlock - 1) / kBlock;
+  const bool lg = P.langevin != 0, an = P.aniso_on != 0;
+  if (lg && an) hipLaunchKernelGGL((k_spin_phase<real, true, true>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  else if (lg) hipLaunchKernelGGL((k_spin_phase<real, true, false>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  else if (an) hipLaunchKernelGGL((k_spin_phase<real, false, true>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  else hipLaunchKernelGGL((k_spin_phase<real, false, false>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+}
+
+template <typename real>
+void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, hipStream_t st) {
+  const int nb = (S.n + kBlock - 1) / kBlock;
+  if (nb <= 0) return;
+  switch (A.mode) {
+#define SL_FORCE_CASE(m) \
+  case m: hipLaunchKernelGGL((k_force<real, m>), dim3(nb), dim3(kBlock), 0, st, S, P, A); break;
+    SL_FORCE_CASE(1) SL_FORCE_CASE(2) SL_FORCE_CASE(3) SL_FORCE_CASE(4)
+    SL_FORCE_CASE(5) SL_FORCE_CASE(6) SL_FORCE_CASE(7)
+#undef SL_FORCE_CASE
+    default: break;
+  }
+}
+
+void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce8, dim3(1), dim3(256), 0, st, partial, nb, out);
+}
+
+template void launch_spin_phase<double>(const SysView<double> &, const PotConst &,
+                                        const SpinPhaseArgs &, hipStream_t);
+template void launch_spin_phase<float>(const SysView<float> &, const PotConst &,
+                                       const SpinPhaseArgs &, hipStream_t);
+template void launch_force<double>(const SysView<double> &, const PotConst &, const ForceArgs &,
+                                   hipStream_t);
+template void launch_force<float>(const SysView<float> &, const PotConst &, const ForceArgs &,
+                                  hipStream_t);
+
+}  // namespace sl

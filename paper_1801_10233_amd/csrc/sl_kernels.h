@@ -1,0 +1,115 @@
+// sl_kernels.h -- host-side launchers of the gfx950 kernels (internal).
+#pragma once
+
+#include "sl_device.h"
+
+namespace sl {
+
+// --- per-step kernels (sl_dyn.hip) ---
+template <typename real>
+void launch_spin_phase(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
+                       hipStream_t st);
+template <typename real>
+void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, hipStream_t st);
+void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st);
+
+// --- rebuild kernels (sl_nbr.hip) ---
+struct CellGrid {
+  int nc[3];
+  double L[3];
+};
+
+// Cell of every atom from its wrapped position; histogram of cell sizes.
+void launch_cell_assign(int n, const double *rx, const double *ry, const double *rz,
+                        const CellGrid &G, int *cell, int *count, hipStream_t st);
+// Exclusive scan of n ints into out[0..n] (out[n] = total), one block.
+void launch_scan(const int *in, int *out, int n, hipStream_t st);
+// Counting-sort scatter by key, then each bucket sorted ascending so the
+// result does not depend on the order the atomics were served in.
+void launch_bucket_scatter(int n, const int *key, const int *start, int *fill, int *out,
+                           hipStream_t st);
+void launch_bucket_sort(int nbucket, const int *start, int *items, hipStream_t st);
+
+struct NbrBuildArgs {
+  int n, ld, max_nbr, max_spin;
+  double rs2, rl2;
+  CellGrid G;
+  const double *rx, *ry, *rz;
+  const int *cell, *cstart, *catoms;
+  int *nbr, *nspin, *nall;
+  double *bx, *by, *bz;   // reference positions written at build time
+  int *err;
+  int *seen;              // [2]: largest spin segment and row
+};
+void launch_nbr_build(const NbrBuildArgs &A, hipStream_t st);
+
+// Lexicographic colouring keys (z, y, x wrapped) of the current positions.
+void launch_keys(int n, const double *rx, const double *ry, const double *rz, const double L[3],
+                 double *kx, double *ky, double *kz, hipStream_t st);
+
+struct ColourArgs {
+  int n, ld;
+  const int *nbr, *nspin, *id;
+  const double *kx, *ky, *kz;
+  int *colour;
+};
+void launch_colour_fill(int n, int *colour, int value, hipStream_t st);
+// Uncolour every atom that shares its colour with an earlier-key neighbour.
+void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st);
+// One Jones-Plassmann round with key priority, first-fit colour choice.
+void launch_colour_round(const ColourArgs &A, int *remaining, int *reset_next, hipStream_t st);
+void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st);
+
+// Permutation to (colour, cell) order.
+void launch_sort_key(int n, const int *colour, const int *cell, int ncell, int *key, int *count,
+                     hipStream_t st);
+void launch_inverse(int n, const int *perm, int *inv, hipStream_t st);
+
+struct PermuteArgs {
+  int n;
+  const int *perm;              // new -> old
+  const double *src_d[16];
+  double *dst_d[16];
+  int nd;
+  const float *src_f[3];
+  float *dst_f[3];
+  int nf;
+  const int *src_i[4];
+  int *dst_i[4];
+  int ni;
+};
+void launch_permute_atoms(const PermuteArgs &A, hipStream_t st);
+void launch_permute_nbr(int n, int ld, const int *perm, const int *inv, const int *nbr_old,
+                        const int *nspin_old, const int *nall_old, int *nbr_new, int *nspin_new,
+                        int *nall_new, hipStream_t st);
+
+// User CSR (user ids) -> internal ELL, spin-radius entries first.
+struct CsrArgs {
+  int n, ld, max_nbr;
+  const int *off, *idx;      // user CSR
+  const int *id, *uinv;      // internal -> user, user -> internal
+  const double *rx, *ry, *rz;
+  double L[3], invL[3];
+  double rs2;
+  int *nbr, *nspin, *nall;
+  double *bx, *by, *bz;
+  int *err;
+};
+void launch_csr_to_ell(const CsrArgs &A, hipStream_t st);
+void launch_user_inverse(int n, const int *id, int *uinv, hipStream_t st);
+
+// State transfer between user AoS double[N][3] and internal SoA.
+void launch_load_vec(int n, const int *id, const double *aos, double *x, double *y, double *z,
+                     hipStream_t st);
+void launch_load_vec_f(int n, const int *id, const double *aos, float *x, float *y, float *z,
+                       hipStream_t st);
+void launch_store_vec(int n, const int *id, const double *x, const double *y, const double *z,
+                      double *aos, hipStream_t st);
+void launch_store_vec_f(int n, const int *id, const float *x, const float *y, const float *z,
+                        double *aos, hipStream_t st);
+void launch_load_scalar(int n, const int *id, const double *src, double *dst, hipStream_t st);
+void launch_copy_d(int n, const double *src, double *dst, hipStream_t st);
+void launch_iota(int n, int *id, hipStream_t st);
+void launch_zero_i(int n, int *p, hipStream_t st);
+
+}  // namespace sl

@@ -1,0 +1,414 @@
+// sl_nbr.hip -- rebuild-step kernels on gfx950: cell binning, neighbour
+// lists, colour classes of non-interacting spins and the permutation of
+// the per-atom arrays into (colour, cell) order.
+//
+// Colour classes play the role of the paper's sectors (Sec. 5.1): a set of
+// spins none of which interact, so all of them can be rotated at once while
+// the product of single-spin propagators keeps the order of
+// Eq. spin_ST_sectoring. The colouring is first-fit greedy in ascending
+// lexicographic key (z, y, x, id); on the GPU it is computed by
+// Jones-Plassmann rounds with that key as priority: an atom is coloured once
+// every earlier-key neighbour is, with the smallest colour none of its
+// coloured neighbours holds, which gives exactly the greedy result.
+#include "sl_device.h"
+#include "sl_kernels.h"
+
+namespace sl {
+
+static inline int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
+
+__device__ __forceinline__ double wrap(double x, double L) { return x - L * floor(x / L); }
+
+__device__ __forceinline__ int cell_coord(double x, double L, int nc) {
+  int k = (int)(wrap(x, L) / L * nc);
+  return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
+}
+
+__global__ void k_cell_assign(int n, const double *rx, const double *ry, const double *rz,
+                              CellGrid G, int *cell, int *count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int cx = cell_coord(rx[i], G.L[0], G.nc[0]);
+  const int cy = cell_coord(ry[i], G.L[1], G.nc[1]);
+  const int cz = cell_coord(rz[i], G.L[2], G.nc[2]);
+  const int c = (cz * G.nc[1] + cy) * G.nc[0] + cx;
+  cell[i] = c;
+  atomicAdd(&count[c], 1);
+}
+
+__global__ __launch_bounds__(1024) void k_scan(const int *in, int *out, int n) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int beg = min(t * chunk, n), end = min(beg + chunk, n);
+  int s = 0;
+  for (int k = beg; k < end; ++k) s += in[k];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = t > 0 ? part[t - 1] : 0;
+  for (int k = beg; k < end; ++k) {
+    out[k] = run;
+    run += in[k];
+  }
+  if (t == 1023) out[n] = part[1023];
+}
+
+__global__ void k_bucket_scatter(int n, const int *key, const int *start, int *fill, int *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = key[i];
+  out[start[b] + atomicAdd(&fill[b], 1)] = i;
+}
+
+__global__ void k_bucket_sort(int nbucket, const int *start, int *items) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbucket) return;
+  const int a = start[b], e = start[b + 1];
+  for (int p = a + 1; p < e; ++p) {
+    const int x = items[p];
+    int q = p - 1;
+    while (q >= a && items[q] > x) {
+      items[q + 1] = items[q];
+      --q;
+    }
+    items[q + 1] = x;
+  }
+}
+
+// Full neighbour rows from the 27 surrounding cells (fewer when a side has
+// under three cells: then that side is one cell and the minimum image
+// covers it). Pass 0 writes the spin segment (r^2 < rs2), pass 1 the rest
+// (rs2 <= r^2 < rl2). Entries are in cell order, atoms ascending inside a
+// cell, so the row order is deterministic.
+__global__ void k_nbr_build(NbrBuildArgs A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const double rix = A.rx[i], riy = A.ry[i], riz = A.rz[i];
+  const int c = A.cell[i];
+  const int cx = c % A.G.nc[0], cy = (c / A.G.nc[0]) % A.G.nc[1], cz = c / (A.G.nc[0] * A.G.nc[1]);
+  const int ox = A.G.nc[0] >= 3 ? 1 : 0, oy = A.G.nc[1] >= 3 ? 1 : 0, oz = A.G.nc[2] >= 3 ? 1 : 0;
+  const double Lx = A.G.L[0], Ly = A.G.L[1], Lz = A.G.L[2];
+  const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
+  int ns = 0, nt = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int dz = -oz; dz <= oz; ++dz)
+      for (int dy = -oy; dy <= oy; ++dy)
+        for (int dx = -ox; dx <= ox; ++dx) {
+          const int qx = (cx + dx + A.G.nc[0]) % A.G.nc[0];
+          const int qy = (cy + dy + A.G.nc[1]) % A.G.nc[1];
+          const int qz = (cz + dz + A.G.nc[2]) % A.G.nc[2];
+          const int q = (qz * A.G.nc[1] + qy) * A.G.nc[0] + qx;
+          for (int p = A.cstart[q]; p < A.cstart[q + 1]; ++p) {
+            const int j = A.catoms[p];
+            if (j == i) continue;
+            const double ddx = min_image(rix - A.rx[j], Lx, iLx);
+            const double ddy = min_image(riy - A.ry[j], Ly, iLy);
+            const double ddz = min_image(riz - A.rz[j], Lz, iLz);
+            const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            const bool take = pass == 0 ? (r2 < A.rs2) : (r2 >= A.rs2 && r2 < A.rl2);
+            if (!take) continue;
+            if (nt < A.max_nbr) A.nbr[(size_t)nt * A.ld + i] = j;
+            ++nt;
+            if (pass == 0) ++ns;
+          }
+        }
+  }
+  if (nt > A.max_nbr || ns > A.max_spin) atomicOr(A.err, kErrNbrOverflow);
+  atomicMax(&A.seen[0], ns);
+  atomicMax(&A.seen[1], nt);
+  A.nspin[i] = min(ns, A.max_spin);
+  A.nall[i] = min(nt, A.max_nbr);
+  A.bx[i] = rix;
+  A.by[i] = riy;
+  A.bz[i] = riz;
+}
+
+__global__ void k_keys(int n, const double *rx, const double *ry, const double *rz, double Lx,
+                       double Ly, double Lz, double *kx, double *ky, double *kz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  kx[i] = wrap(rx[i], Lx);
+  ky[i] = wrap(ry[i], Ly);
+  kz[i] = wrap(rz[i], Lz);
+}
+
+// key(j) < key(i) in the order (z, y, x, user id).
+__device__ __forceinline__ bool key_less(const ColourArgs &A, int j, int i) {
+  const double zj = A.kz[j], zi = A.kz[i];
+  if (zj != zi) return zj < zi;
+  const double yj = A.ky[j], yi = A.ky[i];
+  if (yj != yi) return yj < yi;
+  const double xj = A.kx[j], xi = A.kx[i];
+  if (xj != xi) return xj < xi;
+  return A.id[j] < A.id[i];
+}
+
+__global__ void k_colour_fill(int n, int *colour, int value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) colour[i] = value;
+}
+
+__global__ void k_colour_mark(ColourArgs A, int *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const int c = A.colour[i];
+  bool drop = false;
+  for (int k = 0; k < A.nspin[i]; ++k) {
+    const int j = A.nbr[(size_t)k * A.ld + i];
+    if (A.colour[j] == c && key_less(A, j, i)) drop = true;
+  }
+  out[i] = drop ? -1 : c;
+}
+
+// One Jones-Plassmann round. A neighbour coloured during this same round is
+// either seen with its final colour or seen uncoloured (then this atom waits
+// a round); both give the sequential greedy result, only the round count
+// can differ.
+__global__ void k_colour_round(ColourArgs A, int *remaining, int *reset_next) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *reset_next = 0;
+  if (i >= A.n) return;
+  volatile int *col = A.colour;
+  if (col[i] >= 0) return;
+  unsigned long long used = 0ull;
+  for (int k = 0; k < A.nspin[i]; ++k) {
+    const int j = A.nbr[(size_t)k * A.ld + i];
+    const int cj = col[j];
+    if (cj >= 0) {
+      used |= 1ull << (cj & 63);
+    } else if (key_less(A, j, i)) {
+      atomicAdd(remaining, 1);
+      return;
+    }
+  }
+  col[i] = __ffsll((long long)~used) - 1;
+}
+
+__global__ void k_colour_stats(ColourArgs A, int *maxc, int *err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const int c = A.colour[i];
+  atomicMax(maxc, c);
+  for (int k = 0; k < A.nspin[i]; ++k)
+    if (A.colour[A.nbr[(size_t)k * A.ld + i]] == c) atomicOr(err, kErrColour);
+  if (c < 0) atomicOr(err, kErrColour);
+}
+
+__global__ void k_sort_key(int n, const int *colour, const int *cell, int ncell, int *key,
+                           int *count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = colour[i] * ncell + cell[i];
+  key[i] = k;
+  atomicAdd(&count[k], 1);
+}
+
+__global__ void k_inverse(int n, const int *perm, int *inv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) inv[perm[i]] = i;
+}
+
+__global__ void k_permute_atoms(PermuteArgs A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const int o = A.perm[i];
+  for (int k = 0; k < A.nd; ++k) A.dst_d[k][i] = A.src_d[k][o];
+  for (int k = 0; k < A.nf; ++k) A.dst_f[k][i] = A.src_f[k][o];
+  for (int k = 0; k < A.ni; ++k) A.dst_i[k][i] = A.src_i[k][o];
+}
+
+__global__ void k_permute_nbr(int n, int ld, const int *perm, const int *inv, const int *nbr_old,
+                              const int *nspin_old, const int *nall_old, int *nbr_new,
+                              int *nspin_new, int *nall_new) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  const int na = nall_old[o];
+  for (int k = 0; k < na; ++k) nbr_new[(size_t)k * ld + i] = inv[nbr_old[(size_t)k * ld + o]];
+  nspin_new[i] = nspin_old[o];
+  nall_new[i] = na;
+}
+
+__global__ void k_csr_to_ell(CsrArgs A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const int u = A.id[i];
+  const int a = A.off[u], b = A.off[u + 1];
+  const double rix = A.rx[i], riy = A.ry[i], riz = A.rz[i];
+  int ns = 0, nt = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int p = a; p < b; ++p) {
+      const int j = A.uinv[A.idx[p]];
+      const double dx = min_image(rix - A.rx[j], A.L[0], A.invL[0]);
+      const double dy = min_image(riy - A.ry[j], A.L[1], A.invL[1]);
+      const double dz = min_image(riz - A.rz[j], A.L[2], A.invL[2]);
+      const bool sp = dx * dx + dy * dy + dz * dz < A.rs2;
+      if (sp != (pass == 0)) continue;
+      if (nt < A.max_nbr) A.nbr[(size_t)nt * A.ld + i] = j;
+      ++nt;
+      if (pass == 0) ++ns;
+    }
+  if (nt > A.max_nbr) atomicOr(A.err, kErrNbrOverflow);
+  A.nspin[i] = min(ns, A.max_nbr);
+  A.nall[i] = min(nt, A.max_nbr);
+  A.bx[i] = rix;
+  A.by[i] = riy;
+  A.bz[i] = riz;
+}
+
+__global__ void k_user_inverse(int n, const int *id, int *uinv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) uinv[id[i]] = i;
+}
+
+__global__ void k_load_vec(int n, const int *id, const double *aos, double *x, double *y,
+                           double *z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t u = (size_t)id[i] * 3;
+  x[i] = aos[u];
+  y[i] = aos[u + 1];
+  z[i] = aos[u + 2];
+}
+
+__global__ void k_load_vec_f(int n, const int *id, const double *aos, float *x, float *y,
+                             float *z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t u = (size_t)id[i] * 3;
+  x[i] = (float)aos[u];
+  y[i] = (float)aos[u + 1];
+  z[i] = (float)aos[u + 2];
+}
+
+__global__ void k_store_vec(int n, const int *id, const double *x, const double *y,
+                            const double *z, double *aos) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t u = (size_t)id[i] * 3;
+  aos[u] = x[i];
+  aos[u + 1] = y[i];
+  aos[u + 2] = z[i];
+}
+
+__global__ void k_store_vec_f(int n, const int *id, const float *x, const float *y,
+                              const float *z, double *aos) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t u = (size_t)id[i] * 3;
+  aos[u] = x[i];
+  aos[u + 1] = y[i];
+  aos[u + 2] = z[i];
+}
+
+__global__ void k_load_scalar(int n, const int *id, const double *src, double *dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[id[i]];
+}
+
+__global__ void k_copy_d(int n, const double *src, double *dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_iota(int n, int *id) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) id[i] = i;
+}
+
+__global__ void k_zero_i(int n, int *p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+void launch_cell_assign(int n, const double *rx, const double *ry, const double *rz,
+                        const CellGrid &G, int *cell, int *count, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_cell_assign, dim3(nblocks(n)), dim3(kBlock), 0, st, n, rx, ry, rz, G, cell, count);
+}
+void launch_scan(const int *in, int *out, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, in, out, n);
+}
+void launch_bucket_scatter(int n, const int *key, const int *start, int *fill, int *out,
+                           hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks(n)), dim3(kBlock), 0, st, n, key, start, fill, out);
+}
+void launch_bucket_sort(int nbucket, const int *start, int *items, hipStream_t st) {
+  if (nbucket > 0) hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks(nbucket)), dim3(kBlock), 0, st, nbucket, start, items);
+}
+void launch_nbr_build(const NbrBuildArgs &A, hipStream_t st) {
+  if (A.n > 0) hipLaunchKernelGGL(k_nbr_build, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A);
+}
+void launch_keys(int n, const double *rx, const double *ry, const double *rz, const double L[3],
+                 double *kx, double *ky, double *kz, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_keys, dim3(nblocks(n)), dim3(kBlock), 0, st, n, rx, ry, rz, L[0], L[1], L[2], kx, ky, kz);
+}
+void launch_colour_fill(int n, int *colour, int value, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_colour_fill, dim3(nblocks(n)), dim3(kBlock), 0, st, n, colour, value);
+}
+void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st) {
+  if (A.n > 0) hipLaunchKernelGGL(k_colour_mark, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, colour_out);
+}
+void launch_colour_round(const ColourArgs &A, int *remaining, int *reset_next, hipStream_t st) {
+  hipLaunchKernelGGL(k_colour_round, dim3(nblocks(A.n > 0 ? A.n : 1)), dim3(kBlock), 0, st, A, remaining, reset_next);
+}
+void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st) {
+  if (A.n > 0) hipLaunchKernelGGL(k_colour_stats, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, maxc, err);
+}
+void launch_sort_key(int n, const int *colour, const int *cell, int ncell, int *key, int *count,
+                     hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_sort_key, dim3(nblocks(n)), dim3(kBlock), 0, st, n, colour, cell, ncell, key, count);
+}
+void launch_inverse(int n, const int *perm, int *inv, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_inverse, dim3(nblocks(n)), dim3(kBlock), 0, st, n, perm, inv);
+}
+void launch_permute_atoms(const PermuteArgs &A, hipStream_t st) {
+  if (A.n > 0) hipLaunchKernelGGL(k_permute_atoms, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A);
+}
+void launch_permute_nbr(int n, int ld, const int *perm, const int *inv, const int *nbr_old,
+                        const int *nspin_old, const int *nall_old, int *nbr_new, int *nspin_new,
+                        int *nall_new, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_permute_nbr, dim3(nblocks(n)), dim3(kBlock), 0, st, n, ld, perm, inv, nbr_old, nspin_old, nall_old, nbr_new, nspin_new, nall_new);
+}
+void launch_csr_to_ell(const CsrArgs &A, hipStream_t st) {
+  if (A.n > 0) hipLaunchKernelGGL(k_csr_to_ell, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A);
+}
+void launch_user_inverse(int n, const int *id, int *uinv, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_user_inverse, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id, uinv);
+}
+void launch_load_vec(int n, const int *id, const double *aos, double *x, double *y, double *z,
+                     hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_load_vec, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id, aos, x, y, z);
+}
+void launch_load_vec_f(int n, const int *id, const double *aos, float *x, float *y, float *z,
+                       hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_load_vec_f, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id, aos, x, y, z);
+}
+void launch_store_vec(int n, const int *id, const double *x, const double *y, const double *z,
+                      double *aos, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_store_vec, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id, x, y, z, aos);
+}
+void launch_store_vec_f(int n, const int *id, const float *x, const float *y, const float *z,
+                        double *aos, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_store_vec_f, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id, x, y, z, aos);
+}
+void launch_load_scalar(int n, const int *id, const double *src, double *dst, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_load_scalar, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id, src, dst);
+}
+void launch_copy_d(int n, const double *src, double *dst, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_copy_d, dim3(nblocks(n)), dim3(kBlock), 0, st, n, src, dst);
+}
+void launch_iota(int n, int *id, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_iota, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id);
+}
+void launch_zero_i(int n, int *p, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_zero_i, dim3(nblocks(n)), dim3(kBlock), 0, st, n, p);
+}
+
+}  // namespace sl

@@ -1,0 +1,301 @@
+"""Thin ctypes binding of the C ABI in include/spinlat.h (libspinlat.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library. Importing this module does not need a GPU; calling
+into the library does. There is no CPU fallback: if the shared library is
+missing the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspinlat.so")
+
+SL_OK = 0
+SL_E_ARG = -1
+SL_E_BOX = -2
+SL_E_NONFINITE = -3
+SL_E_NBR_OVERFLOW = -4
+SL_E_COLOR = -5
+SL_E_HIP = -6
+SL_E_STATE = -7
+SL_E_NOMEM = -8
+SL_HOST = 0
+SL_DEVICE = 1
+SL_FP64 = 0
+SL_FP32 = 1
+
+PROF_SPIN, PROF_FORCE, PROF_REBUILD, PROF_REDUCE = 0, 1, 2, 3
+
+# Every function the header declares (checked by the tests).
+EXPORTS = [
+    "sl_create", "sl_destroy", "sl_set_state", "sl_get_state", "sl_set_potential",
+    "sl_set_neighbor", "sl_set_neighbor_list", "sl_get_neighbor_list",
+    "sl_set_coloring", "sl_get_coloring", "sl_set_step", "sl_step",
+    "sl_get_energy", "sl_get_magnetization", "sl_get_thermo", "sl_get_stats",
+    "sl_synchronize", "sl_set_profiling", "sl_get_profile", "sl_last_error",
+]
+
+
+class sl_params(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("box", C.c_double * 3), ("precision", C.c_int),
+                ("frozen", C.c_int), ("skin", C.c_double), ("max_nbr", C.c_int),
+                ("max_spin_nbr", C.c_int), ("seed", C.c_uint64), ("replica", C.c_uint32),
+                ("thermo_every", C.c_int), ("stream", C.c_void_p)]
+
+
+class sl_potential(C.Structure):
+    _fields_ = [("morse_on", C.c_int), ("morse_D", C.c_double), ("morse_alpha", C.c_double),
+                ("morse_r0", C.c_double), ("morse_rc", C.c_double), ("morse_shift", C.c_int),
+                ("ex_alpha", C.c_double), ("ex_gamma", C.c_double), ("ex_delta", C.c_double),
+                ("ex_rc", C.c_double), ("zeeman_g", C.c_double), ("B", C.c_double * 3),
+                ("aniso_K", C.c_double), ("aniso_n", C.c_double * 3), ("lam", C.c_double),
+                ("temperature", C.c_double)]
+
+
+class sl_energy(C.Structure):
+    _fields_ = [("kin", C.c_double), ("pair", C.c_double), ("exchange", C.c_double),
+                ("zeeman", C.c_double), ("aniso", C.c_double), ("total", C.c_double)]
+
+
+class sl_stats(C.Structure):
+    _fields_ = [("step", C.c_int64), ("rebuilds", C.c_int64), ("n_colours", C.c_int),
+                ("jp_rounds", C.c_int), ("max_spin_nbr_seen", C.c_int),
+                ("max_nbr_seen", C.c_int)]
+
+
+class SpinLatError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"spinlat error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libspinlat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip, i64 = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int64
+    sig = {
+        "sl_create": ([C.POINTER(sl_params), C.POINTER(C.c_void_p)], C.c_int),
+        "sl_destroy": ([vp], C.c_int),
+        "sl_set_state": ([vp, vp, vp, vp, vp, C.c_int], C.c_int),
+        "sl_get_state": ([vp, vp, vp, vp, C.c_int], C.c_int),
+        "sl_set_potential": ([vp, C.POINTER(sl_potential)], C.c_int),
+        "sl_set_neighbor": ([vp, C.c_double, C.c_int], C.c_int),
+        "sl_set_neighbor_list": ([vp, vp, vp, C.c_int], C.c_int),
+        "sl_get_neighbor_list": ([vp, ip, ip, ip, i64], i64),
+        "sl_set_coloring": ([vp, vp, C.c_int], C.c_int),
+        "sl_get_coloring": ([vp, ip, ip], C.c_int),
+        "sl_set_step": ([vp, i64], C.c_int),
+        "sl_step": ([vp, i64, C.c_double], C.c_int),
+        "sl_get_energy": ([vp, C.POINTER(sl_energy)], C.c_int),
+        "sl_get_magnetization": ([vp, dp], C.c_int),
+        "sl_get_thermo": ([vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(sl_energy), dp, ip],
+                          C.c_int),
+        "sl_get_stats": ([vp, C.POINTER(sl_stats)], C.c_int),
+        "sl_synchronize": ([vp], C.c_int),
+        "sl_set_profiling": ([vp, C.c_int], C.c_int),
+        "sl_get_profile": ([vp, C.c_int, C.POINTER(C.c_int64), dp, dp], C.c_int),
+        "sl_last_error": ([vp], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    """Host numpy array or device tensor -> (address, where)."""
+    if a is None:
+        return None, SL_HOST
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data, SL_HOST
+    # torch tensor (device or host)
+    dev = getattr(a, "is_cuda", False)
+    return a.data_ptr(), (SL_DEVICE if dev else SL_HOST)
+
+
+def make_potential(d: dict) -> sl_potential:
+    p = sl_potential()
+    for k, v in d.items():
+        if k in ("B", "aniso_n"):
+            setattr(p, k, (C.c_double * 3)(*v))
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class System:
+    """One system behind an sl_system handle."""
+
+    def __init__(self, n_atoms, box, precision=SL_FP64, frozen=False, skin=0.3,
+                 max_nbr=0, max_spin_nbr=0, seed=0, replica=0, thermo_every=0,
+                 stream=None):
+        L = lib()
+        p = sl_params()
+        p.n_atoms = int(n_atoms)
+        p.box = (C.c_double * 3)(*[float(x) for x in box])
+        p.precision = int(precision)
+        p.frozen = int(bool(frozen))
+        p.skin = float(skin)
+        p.max_nbr = int(max_nbr)
+        p.max_spin_nbr = int(max_spin_nbr)
+        p.seed = int(seed)
+        p.replica = int(replica)
+        p.thermo_every = int(thermo_every)
+        p.stream = stream
+        h = C.c_void_p()
+        rc = L.sl_create(C.byref(p), C.byref(h))
+        if rc != SL_OK:
+            raise SpinLatError(rc, L.sl_last_error(None).decode())
+        self.h = h
+        self.N = int(n_atoms)
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sl_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, rc):
+        if rc < 0:
+            raise SpinLatError(rc, lib().sl_last_error(self.h).decode())
+        return rc
+
+    def set_potential(self, pot: dict):
+        self._pot = make_potential(pot)
+        self._check(lib().sl_set_potential(self.h, C.byref(self._pot)))
+
+    def set_state(self, r=None, v=None, s=None, mass=None):
+        conv = []
+        where = SL_HOST
+        for a, shape in ((r, (self.N, 3)), (v, (self.N, 3)), (s, (self.N, 3)), (mass, (self.N,))):
+            if a is None:
+                conv.append(None)
+            elif isinstance(a, np.ndarray) or not hasattr(a, "data_ptr"):
+                conv.append(np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape)))
+            else:
+                conv.append(a.contiguous())
+        ptrs = []
+        for a in conv:
+            p, w = _ptr(a)
+            ptrs.append(p)
+            if a is not None:
+                where = w
+        self._check(lib().sl_set_state(self.h, *ptrs, where))
+
+    def get_state(self):
+        r = np.empty((self.N, 3)); v = np.empty((self.N, 3)); s = np.empty((self.N, 3))
+        self._check(lib().sl_get_state(self.h, r.ctypes.data, v.ctypes.data, s.ctypes.data,
+                                       SL_HOST))
+        return r, v, s
+
+    def get_state_device(self, r, v, s):
+        """Copy into device tensors (float64, N x 3)."""
+        self._check(lib().sl_get_state(self.h, r.data_ptr(), v.data_ptr(), s.data_ptr(),
+                                       SL_DEVICE))
+
+    def set_neighbor(self, skin, max_nbr=0):
+        self._check(lib().sl_set_neighbor(self.h, float(skin), int(max_nbr)))
+
+    def set_neighbor_list(self, offsets, idx):
+        o = np.ascontiguousarray(offsets, dtype=np.int32)
+        i = np.ascontiguousarray(idx, dtype=np.int32)
+        self._check(lib().sl_set_neighbor_list(self.h, o.ctypes.data, i.ctypes.data, SL_HOST))
+
+    def neighbor_list(self):
+        ns = np.zeros(self.N, dtype=np.int32)
+        na = np.zeros(self.N, dtype=np.int32)
+        ip = C.POINTER(C.c_int)
+        tot = self._check(lib().sl_get_neighbor_list(self.h, ns.ctypes.data_as(ip),
+                                                     na.ctypes.data_as(ip), None, 0))
+        idx = np.zeros(max(tot, 1), dtype=np.int32)
+        self._check(lib().sl_get_neighbor_list(self.h, ns.ctypes.data_as(ip),
+                                               na.ctypes.data_as(ip), idx.ctypes.data_as(ip),
+                                               tot))
+        off = np.concatenate([[0], np.cumsum(na)])
+        return ns, na, [idx[off[i]:off[i + 1]] for i in range(self.N)]
+
+    def set_coloring(self, colour):
+        c = np.ascontiguousarray(colour, dtype=np.int32)
+        self._check(lib().sl_set_coloring(self.h, c.ctypes.data, SL_HOST))
+
+    def coloring(self):
+        c = np.zeros(self.N, dtype=np.int32)
+        K = C.c_int()
+        self._check(lib().sl_get_coloring(self.h, c.ctypes.data_as(C.POINTER(C.c_int)),
+                                          C.byref(K)))
+        return c, K.value
+
+    def set_step(self, k):
+        self._check(lib().sl_set_step(self.h, int(k)))
+
+    def step(self, n, dt):
+        self._check(lib().sl_step(self.h, int(n), float(dt)))
+
+    def energy(self):
+        e = sl_energy()
+        self._check(lib().sl_get_energy(self.h, C.byref(e)))
+        return dict(kin=e.kin, pair=e.pair, exchange=e.exchange, zeeman=e.zeeman,
+                    aniso=e.aniso, total=e.total)
+
+    def magnetization(self):
+        M = (C.c_double * 3)()
+        self._check(lib().sl_get_magnetization(self.h, M))
+        return np.array(list(M))
+
+    def thermo(self, max_samples=1 << 16):
+        steps = (C.c_int64 * max_samples)()
+        es = (sl_energy * max_samples)()
+        M = np.zeros((max_samples, 3))
+        cnt = C.c_int()
+        self._check(lib().sl_get_thermo(self.h, max_samples, steps, es,
+                                        M.ctypes.data_as(C.POINTER(C.c_double)), C.byref(cnt)))
+        k = cnt.value
+        return (np.array(steps[:k], dtype=np.int64),
+                np.array([e.total for e in es[:k]]), M[:k])
+
+    def stats(self):
+        s = sl_stats()
+        self._check(lib().sl_get_stats(self.h, C.byref(s)))
+        return dict(step=s.step, rebuilds=s.rebuilds, n_colours=s.n_colours,
+                    jp_rounds=s.jp_rounds, max_spin_nbr_seen=s.max_spin_nbr_seen,
+                    max_nbr_seen=s.max_nbr_seen)
+
+    def synchronize(self):
+        self._check(lib().sl_synchronize(self.h))
+
+    def set_profiling(self, on=True):
+        self._check(lib().sl_set_profiling(self.h, int(bool(on))))
+
+    def profile(self, kind):
+        n = C.c_int64(); ms = C.c_double(); w = C.c_double()
+        self._check(lib().sl_get_profile(self.h, int(kind), C.byref(n), C.byref(ms),
+                                         C.byref(w)))
+        return n.value, ms.value, w.value
+
+
+def system_from_workload(w, precision=SL_FP64, thermo_every=0, **kw):
+    """Convenience: create a system, set the potential and the state of a
+    workloads.Workload."""
+    S = System(w.N, w.box, precision=precision, frozen=w.frozen, skin=w.skin, seed=w.seed,
+               replica=w.replica, thermo_every=thermo_every, **kw)
+    S.set_potential(w.pot)
+    S.set_state(w.r, w.v, w.s, w.mass)
+    return S

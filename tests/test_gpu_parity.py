@@ -1,0 +1,265 @@
+"""HIP path vs CPU oracle, element by element, on seeded workloads.
+
+FP64 bar: after 100 steps, unwrapped positions within 1e-10 L, spins within
+1e-10 and velocities within 1e-10 max|v|; neighbour sets, colourings and
+rebuild counts identical (integers compared exactly). Sizes span several
+kernel tiles (256 atoms) and ragged tails.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1801_10233_amd import workloads as W
+from tests.common import make_gpu, make_oracle, parity, row_sets
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def test_frozen_lattice_parity_and_exact_energy():
+    w = W.spin_frozen(10)                       # 2000 atoms, K = 4
+    o = make_oracle(w)
+    g = make_gpu(w)
+    g.step(0, w.dt)
+    o.build()
+    co, Ko = o.coloring()
+    cg, Kg = g.coloring()
+    assert Ko == Kg == 4 and np.array_equal(co, cg)
+    e0 = g.energy()["total"]
+    assert e0 == pytest.approx(o.energy()["total"], rel=1e-13)
+    o.step(100, w.dt)
+    g.step(100, w.dt)
+    p = parity(w, o, g)
+    _print("frozen parity", p)
+    assert p["ok"], p
+    e1 = g.energy()["total"]
+    assert abs((e1 - e0) / e0) < 1e-12
+    _, _, s = g.get_state()
+    assert np.abs(np.linalg.norm(s, axis=1) - 1).max() < 1e-13
+
+
+def test_frozen_odd_lattice_nine_colours():
+    w = W.spin_frozen(7)                        # 686 atoms: ragged tail, K = 9
+    o = make_oracle(w)
+    g = make_gpu(w)
+    o.step(50, w.dt)
+    g.step(50, w.dt)
+    assert g.coloring()[1] == o.coloring()[1] == 9
+    assert np.array_equal(g.coloring()[0], o.coloring()[0])
+    p = parity(w, o, g)
+    assert p["ok"], p
+
+
+@pytest.mark.parametrize("n", [6, 8])
+def test_coupled_nve_parity_100_steps(n):
+    w = W.coupled_nve(n=n)
+    o = make_oracle(w)
+    g = make_gpu(w)
+    o.step(100, w.dt)
+    g.step(100, w.dt)
+    p = parity(w, o, g)
+    _print("coupled parity", n, p)
+    assert p["ok"], p
+    assert g.stats()["rebuilds"] == o.num_rebuilds
+    assert np.array_equal(g.coloring()[0], o.coloring()[0])
+    eo, eg = o.energy(), g.energy()
+    for k in eo:
+        assert eg[k] == pytest.approx(eo[k], rel=1e-11, abs=1e-11), k
+
+
+def test_coupled_parity_through_rebuilds():
+    # hot lattice: several Verlet rebuilds (and colour checks) inside the run
+    w = W.coupled_nve(n=6, T=1500.0)
+    o = make_oracle(w)
+    g = make_gpu(w)
+    for chunk in (37, 63, 100):                 # call boundaries are part of it
+        o.step(chunk, 2e-4)
+        g.step(chunk, 2e-4)
+    _print("rebuilds", o.num_rebuilds, g.stats())
+    assert o.num_rebuilds >= 3
+    assert g.stats()["rebuilds"] == o.num_rebuilds
+    assert np.array_equal(g.coloring()[0], o.coloring()[0])
+    p = parity(w, o, g, rtol_r=1e-10, tol_s=1e-9, rtol_v=1e-9)
+    _print("hot parity", p)
+    assert p["ok"], p
+
+
+def test_langevin_anisotropy_parity():
+    w = W.large_langevin(n=7)                   # 686 atoms, K = 9, lambda = 0.01
+    o = make_oracle(w)
+    g = make_gpu(w)
+    o.set_step_counter(123456789012)            # high step word of the counter
+    g.set_step(123456789012)
+    o.step(60, w.dt)
+    g.step(60, w.dt)
+    p = parity(w, o, g)
+    _print("langevin parity", p)
+    assert p["ok"], p
+
+
+def test_neighbor_lists_and_colouring_exact_on_disordered_input():
+    r, box = W.bcc_lattice(9)
+    N = r.shape[0]
+    r = r + W.thermal_displacements(N, 0.2, 77)
+    w = W.coupled_nve(n=9)
+    w.r = r
+    o = make_oracle(w)
+    g = make_gpu(w)
+    o.build()
+    g.step(0, w.dt)
+    nso, _, ro = o.neighbor_list()
+    nsg, _, rg = g.neighbor_list()
+    assert row_sets(ro, nso, "spin") == row_sets(rg, nsg, "spin")
+    assert row_sets(ro, nso, "all") == row_sets(rg, nsg, "all")
+    co, Ko = o.coloring()
+    cg, Kg = g.coloring()
+    assert Ko == Kg and np.array_equal(co, cg)
+
+
+def test_user_supplied_list_and_colouring():
+    w = W.spin_frozen(6)
+    o = make_oracle(w)
+    o.build()
+    ns, na, rows = o.neighbor_list()
+    off = np.concatenate([[0], np.cumsum(na)]).astype(np.int32)
+    idx = np.concatenate(rows).astype(np.int32)
+    g = make_gpu(w)
+    g.set_neighbor_list(off, idx)
+    c, K = o.coloring()
+    g.set_coloring(c)
+    assert np.array_equal(g.coloring()[0], c)
+    o.step(40, 2e-4)
+    g.step(40, 2e-4)
+    p = parity(w, o, g)
+    assert p["ok"], p
+
+
+def test_reversibility_on_gpu():
+    w = W.coupled_nve(n=6)
+    g = make_gpu(w)
+    g.step(80, 1e-4)
+    g.step(80, -1e-4)
+    r, v, s = g.get_state()
+    assert g.stats()["rebuilds"] == 1
+    assert np.abs(r - w.r).max() / w.box[0] < 1e-10
+    assert np.abs(v - w.v).max() < 1e-10 * np.abs(w.v).max()
+    assert np.abs(s - w.s).max() < 1e-10
+
+
+def test_single_spin_larmor_on_gpu():
+    from paper_1801_10233_amd import spinlat as sl
+    g = sl.System(1, [20.0, 20.0, 20.0], frozen=True)
+    g.set_potential(dict(W._pot(B=(0.0, 0.0, 1.0))))
+    g.set_state(np.zeros((1, 3)), np.zeros((1, 3)), np.array([[1.0, 0, 0]]), np.ones(1))
+    g.step(500, 1e-2)
+    _, _, s = g.get_state()
+    om = 2.0 * O.MUB / O.HBAR
+    th = 500 * 8.0 * np.arctan(om * 1e-2 / 8.0)
+    assert np.abs(s[0] - [np.cos(th), np.sin(th), 0.0]).max() < 1e-12
+
+
+def test_deterministic_reruns():
+    w = W.large_langevin(n=6)
+    a = make_gpu(w)
+    b = make_gpu(w)
+    a.step(30, w.dt)
+    b.step(30, w.dt)
+    ra, va, sa = a.get_state()
+    rb, vb, sb = b.get_state()
+    assert np.array_equal(ra, rb) and np.array_equal(va, vb) and np.array_equal(sa, sb)
+
+
+def test_thermo_samples_match_oracle_energies():
+    w = W.coupled_nve(n=6)
+    o = make_oracle(w)
+    g = make_gpu(w, thermo_every=10)
+    Es = []
+    for _ in range(5):
+        o.step(10, w.dt)
+        Es.append(o.energy()["total"])
+    g.step(50, w.dt)
+    steps, Eg, M = g.thermo()
+    assert list(steps) == [10, 20, 30, 40, 50]
+    assert np.allclose(Eg, Es, rtol=1e-11, atol=1e-9)
+
+
+def test_checkpoint_resume():
+    w = W.large_langevin(n=6)
+    a = make_gpu(w)
+    a.step(20, w.dt)
+    b = make_gpu(w)
+    b.step(10, w.dt)
+    r, v, s = b.get_state()
+    c, _ = b.coloring()
+    k = b.stats()["step"]
+    b2 = make_gpu(w)
+    b2.set_state(r, v, s, w.mass)
+    b2.set_step(k)
+    b2.step(0, w.dt)
+    b2.set_coloring(c)
+    b2.step(10, w.dt)
+    ra, va, sa = a.get_state()
+    rb, vb, sb = b2.get_state()
+    assert np.abs(sa - sb).max() < 1e-12
+    assert np.abs(ra - rb).max() < 1e-12 * w.box[0]
+
+
+def test_error_paths():
+    from paper_1801_10233_amd import spinlat as sl
+    w = W.coupled_nve(n=5)
+    g = make_gpu(w)
+    s = w.s.copy(); s[3] *= 1.001
+    with pytest.raises(sl.SpinLatError) as e:
+        g.set_state(s=s)
+    assert e.value.code == sl.SL_E_ARG
+    r = w.r.copy(); r[2, 1] = np.nan
+    with pytest.raises(sl.SpinLatError) as e:
+        g.set_state(r=r)
+    assert e.value.code == sl.SL_E_NONFINITE
+    small = sl.System(16, [8.0, 8.0, 8.0], skin=0.3)
+    with pytest.raises(sl.SpinLatError) as e:
+        small.set_potential(w.pot)
+    assert e.value.code == sl.SL_E_BOX
+    tight = make_gpu(w, max_nbr=40)
+    with pytest.raises(sl.SpinLatError) as e:
+        tight.step(1, w.dt)
+    assert e.value.code == sl.SL_E_NBR_OVERFLOW
+    g2 = make_gpu(w)
+    g2.step(0, w.dt)
+    with pytest.raises(sl.SpinLatError) as e:
+        g2.set_coloring(np.zeros(w.N, dtype=np.int32))
+    assert e.value.code == sl.SL_E_COLOR
+    g2.step(2, w.dt)                     # still usable after the rejected call
+
+
+def test_fp32_form_error_vs_oracle():
+    from paper_1801_10233_amd import spinlat as sl
+    w = W.large_langevin(n=8, nve=True)
+    o = make_oracle(w)
+    g = make_gpu(w, precision=sl.SL_FP32)
+    o.step(100, w.dt)
+    g.step(100, w.dt)
+    p = parity(w, o, g)
+    _print("fp32 vs oracle", p)
+    assert p["ds"] < 1e-4 and p["dr"] < 1e-8 and p["dv"] < 1e-3
+    _, _, s = g.get_state()
+    assert np.abs(np.linalg.norm(s, axis=1) - 1).max() < 1e-6
+    eo, eg = o.energy()["total"], g.energy()["total"]
+    assert abs(eg - eo) / w.N < 1e-5
+
+
+def test_full_size_large_system_sampled_parity():
+    # the 432000-atom workload in the launch configuration of the benchmark:
+    # two FP64 steps on the GPU and in the oracle, every atom compared
+    w = W.large_langevin(n=60)
+    g = make_gpu(w)
+    g.step(2, w.dt)
+    o = make_oracle(w)
+    o.step(2, w.dt)
+    p = parity(w, o, g)
+    _print("432k parity", p)
+    assert p["ok"], p
+    assert g.coloring()[1] == o.coloring()[1] == 4
