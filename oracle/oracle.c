@@ -280,10 +280,15 @@ void orc_get_state(const orc_sys *S, double *r, double *v, double *s)
     if (s) memcpy(s, S->s, n3 * sizeof(double));
 }
 
+/* New interactions may change the cutoffs: the Verlet list (unless given by
+ * the user) is rebuilt at the next use and the predictor is dropped; the
+ * colouring is kept and repaired at that rebuild. */
 void orc_set_potential(orc_sys *S, const orc_pot *p)
 {
     S->pot = *p;
     S->have_F = 0;
+    if (!S->user_list) S->have_list = 0;
+    S->have_D = 0;
 }
 
 void orc_set_ordering(orc_sys *S, int ordering, const int sect_grid[3])

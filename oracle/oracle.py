@@ -26,12 +26,13 @@ COLOUR, SEQ, SECT, JACOBI = 0, 1, 2, 3
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc -O2 (IEEE semantics, no contraction)."""
-    src = os.path.join(HERE, "oracle.c")
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(src):
+    srcs = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "mlp.c")]
+    newest = max(os.path.getmtime(x) for x in srcs)
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
                                "-ffp-contract=off", "-fno-fast-math", "-o", tmp,
-                               src, "-lm"])
+                               *srcs, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -45,6 +46,11 @@ class Pot(C.Structure):
                 ("zeeman_g", C.c_double), ("B", C.c_double * 3),
                 ("aniso_K", C.c_double), ("aniso_n", C.c_double * 3),
                 ("lam", C.c_double), ("temperature", C.c_double)]
+
+
+class MlpCfg(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("mu_step", C.c_double), ("sJ", C.c_double),
+                ("sP", C.c_double), ("ex_rc", C.c_double), ("rc", C.c_double)]
 
 
 def make_pot(d: dict) -> Pot:
@@ -99,6 +105,12 @@ def lib():
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                         C.POINTER(C.c_uint32)]
         L.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32, C.c_int, dp]
+        L.mlp_nparam.restype = C.c_int
+        L.mlp_eval.argtypes = [C.POINTER(MlpCfg), dp, C.c_double, dp]
+        L.mlp_grad_linear.argtypes = [C.POINTER(MlpCfg), dp, C.c_int, dp, dp, dp, dp, dp, dp]
+        L.mlp_loss_grad.restype = C.c_double
+        L.mlp_loss_grad.argtypes = [C.POINTER(MlpCfg), dp, C.c_int, dp, dp, dp, C.c_int, ip, ip,
+                                    C.c_double, dp, dp, dp, dp]
         L.orc_brute_pairs.restype = C.c_long
         L.orc_brute_pairs.argtypes = [C.c_int, dp, dp, C.c_double, ip, ip, C.c_long]
         _lib = L
@@ -295,3 +307,44 @@ def brute_pairs(r, box, rcut):
     pi = np.zeros(max(n, 1), dtype=np.int32); pj = np.zeros(max(n, 1), dtype=np.int32)
     lib().orc_brute_pairs(N, _dp(box), _dp(r), float(rcut), _ip(pi), _ip(pj), n)
     return pi[:n], pj[:n]
+
+
+# --------------------------------------------------------------------------
+# Per-pair MLP (mlp.c): J(r), phi(r) and derivatives; training gradients.
+def mlp_cfg(sigma=0.4, mu_step=5.0 / 15.0, sJ=0.01, sP=1.0, ex_rc=3.5, rc=5.0):
+    return MlpCfg(sigma, mu_step, sJ, sP, ex_rc, rc)
+
+
+def mlp_nparam():
+    return lib().mlp_nparam()
+
+
+def mlp_eval(cfg, params, r):
+    p = _f64(params)
+    out = np.zeros(4)
+    res = []
+    for x in np.atleast_1d(r):
+        lib().mlp_eval(C.byref(cfg), _dp(p), float(x), _dp(out))
+        res.append(out.copy())
+    return np.array(res)          # columns J, dJ, phi, dphi
+
+
+def mlp_grad_linear(cfg, params, r, aJ, adJ, aP, adP):
+    p = _f64(params)
+    r = _f64(r); aJ = _f64(aJ); adJ = _f64(adJ); aP = _f64(aP); adP = _f64(adP)
+    g = np.zeros(p.size)
+    lib().mlp_grad_linear(C.byref(cfg), _dp(p), r.size, _dp(r), _dp(aJ), _dp(adJ), _dp(aP),
+                          _dp(adP), _dp(g))
+    return g
+
+
+def mlp_loss_grad(cfg, params, box, r, s, pi, pj, Eref, Fref, Wref, w=(1.0, 1.0, 1.0),
+                  grad=True):
+    p = _f64(params); box = _f64(box, (3,)); r = _f64(r, (-1, 3)); s = _f64(s, (-1, 3))
+    pi = np.ascontiguousarray(pi, dtype=np.int32); pj = np.ascontiguousarray(pj, dtype=np.int32)
+    Fref = _f64(Fref, (-1, 3)); Wref = _f64(Wref, (-1, 3)); wv = _f64(w, (3,))
+    g = np.zeros(p.size) if grad else None
+    loss = lib().mlp_loss_grad(C.byref(cfg), _dp(p), r.shape[0], _dp(box), _dp(r), _dp(s),
+                               pi.size, _ip(pi), _ip(pj), float(Eref), _dp(Fref), _dp(Wref),
+                               _dp(wv), _dp(g) if grad else None)
+    return loss, g
