@@ -1,0 +1,194 @@
+"""Benchmark: atom-steps/s of the coupled spin-lattice Suzuki-Trotter step on
+the 432000-atom bcc iron-like system (60^3 cells, Morse + Bethe-Slater
+exchange + uniaxial anisotropy + Philox Langevin spin bath at 300 K,
+dt = 0.1 fs), plain FP64 path, with the FP32 form and energy drift beside it.
+
+    python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
+
+Prints one JSON line. Only one GPU is used: --gpus above 1 is refused.
+Inputs are resident in HBM before the timed region starts; the timed region
+covers exactly --steps steps (including any neighbour-list rebuilds they
+trigger), bracketed by device synchronisation on both sides.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1801_10233_amd import spinlat as sl  # noqa: E402
+from paper_1801_10233_amd import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+# Algorithmic bytes per atom for one launch of each kernel (compulsory
+# traffic, neighbour gathers counted as cache hits; 14 spin and 58 force
+# neighbours per atom in bcc at these cutoffs):
+#   spin phase: own s read + write, own r read, 14 int32 indices
+#   force (fused with kicks and drift): r, s, 58 indices, v read + write,
+#   mass, reference position, next position write
+SPIN_BYTES = {sl.SL_FP64: 24 + 24 + 24 + 14 * 4, sl.SL_FP32: 12 + 12 + 24 + 14 * 4}
+FORCE_BYTES = {sl.SL_FP64: 24 + 24 + 58 * 4 + 48 + 8 + 24 + 24,
+               sl.SL_FP32: 24 + 12 + 58 * 4 + 48 + 8 + 24 + 24}
+KIND_NAME = {sl.PROF_SPIN: "k_spin_phase", sl.PROF_FORCE: "k_force"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def timed_run(S, steps, dt, profile=False):
+    S.synchronize()
+    sync()
+    if profile:
+        S.set_profiling(True)
+    t0 = time.perf_counter()
+    S.step(steps, dt)
+    S.synchronize()
+    sync()
+    t1 = time.perf_counter()
+    prof = None
+    if profile:
+        prof = {k: S.profile(k) for k in (sl.PROF_SPIN, sl.PROF_FORCE, sl.PROF_REBUILD)}
+        S.set_profiling(False)
+    return t1 - t0, prof
+
+
+def drift_per_10ps(w, precision, steps, every=10):
+    """Least-squares slope of E_total/N against time on the undamped twin,
+    scaled to 10 ps."""
+    S = sl.system_from_workload(w, precision=precision, thermo_every=every)
+    S.step(steps, w.dt)
+    st, E, _ = S.thermo()
+    t = st * w.dt
+    slope = np.polyfit(t, E / w.N, 1)[0]
+    S.close()
+    return float(slope * 10.0), float(np.std(E / w.N))
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The oracle as it stands on this host, single thread, on the same
+    workload: setup (list, colouring) excluded, then whole steps."""
+    from oracle import oracle as O
+    O.build(force=False)
+    o = O.Oracle(w.r, w.v, w.s, w.mass, w.box, w.pot, frozen=w.frozen, skin=w.skin,
+                 seed=w.seed)
+    o.build()
+    t0 = time.perf_counter()
+    o.step(1, w.dt)
+    t1 = time.perf_counter()
+    per = t1 - t0
+    extra = max(0, min(20, int(budget_s / max(per, 1e-6)) - 1))
+    if extra:
+        o.step(extra, w.dt)
+    t2 = time.perf_counter()
+    n = 1 + extra
+    return dict(value=w.N * n / (t2 - t0), unit="atom-steps/s", cores=1, kind="oracle",
+                sample=f"{w.N}-atom workload, {n} whole steps after list/colouring setup, "
+                       f"serial FP64 C oracle ({(t2 - t0):.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=60, help="bcc cells per side")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP32 form and drift")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this "
+              "build (see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+
+    prec = sl.SL_FP64 if args.precision == "fp64" else sl.SL_FP32
+    w = W.large_langevin(n=args.n)
+    log(f"workload {w.name}: N={w.N} box={w.box[0]:.3f} A dt={w.dt} ps")
+    t_setup = time.perf_counter()
+    S = sl.system_from_workload(w, precision=prec)
+    S.step(args.warmup, w.dt)           # includes the first list build and colouring
+    S.synchronize()
+    log(f"setup + warmup {time.perf_counter() - t_setup:.2f} s; stats {S.stats()}")
+
+    el, prof = timed_run(S, args.steps, w.dt, profile=True)
+    ms_step = el / args.steps * 1e3
+    value = w.N * args.steps / el
+    log(f"timed {args.steps} steps: {el:.4f} s, {ms_step:.4f} ms/step, {value:.4e} atom-steps/s")
+    st = S.stats()
+
+    # dominant kernel = largest summed event time in the timed region
+    kinds = {k: v for k, v in prof.items() if k in KIND_NAME}
+    dom = max(kinds, key=lambda k: kinds[k][1])
+    launches, ms, work = kinds[dom]
+    per_atom = SPIN_BYTES[prec] if dom == sl.PROF_SPIN else FORCE_BYTES[prec]
+    avg_ms = ms / launches
+    bytes_per_launch = per_atom * work / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    other = {KIND_NAME[k]: dict(launches=v[0], total_ms=round(v[1], 4),
+                                avg_us=round(v[1] / max(v[0], 1) * 1e3, 3),
+                                atoms_per_launch=round(v[2] / max(v[0], 1), 1))
+             for k, v in kinds.items()}
+    log("kernels:", json.dumps(other))
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel=KIND_NAME[dom], avg_launch_us=round(avg_ms * 1e3, 3),
+                    algorithmic_bytes_per_atom=per_atom,
+                    atoms_per_launch=round(work / launches, 1), kernels=other)
+
+    out = dict(metric="atom-steps/s, 432k-atom bcc spin-lattice, plain FP64 vs FP32/MLP form @ drift",
+               value=round(value, 1), unit="atom-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms_step, 5), higher_is_better=True,
+               scaling="weak", vs_baseline=None,
+               dtype="f64" if prec == sl.SL_FP64 else "f32",
+               data="synthetic",
+               config=dict(workload="large_langevin: bcc 60^3 cells, 432000 atoms, Morse + "
+                                    "Bethe-Slater exchange + uniaxial K=1e-4 eV + spin Langevin "
+                                    "lambda=0.01 at 300 K (Philox), dt=1e-4 ps",
+                           atoms=w.N, dt_ps=w.dt, colours=st["n_colours"],
+                           rebuilds_in_run=st["rebuilds"], parallelism="single GPU"),
+               roofline=roofline)
+    S.close()
+
+    if not args.no_extras:
+        # FP32 form on the same workload, and drift of both forms on the NVE twin
+        S32 = sl.system_from_workload(w, precision=sl.SL_FP32)
+        S32.step(args.warmup, w.dt)
+        el32, _ = timed_run(S32, args.steps, w.dt)
+        S32.close()
+        v32 = w.N * args.steps / el32
+        twin = W.large_langevin(n=args.n, nve=True)
+        d64, f64 = drift_per_10ps(twin, sl.SL_FP64, 1000)
+        d32, f32 = drift_per_10ps(twin, sl.SL_FP32, 1000)
+        out["forms"] = dict(
+            fp64=dict(value=round(value, 1), drift_eV_per_atom_per_10ps=d64, E_rms_eV_per_atom=f64),
+            fp32=dict(value=round(v32, 1), speedup_vs_fp64=round(v32 / value, 3),
+                      drift_eV_per_atom_per_10ps=d32, E_rms_eV_per_atom=f32),
+            drift_run="undamped twin, 1000 steps (0.1 ps), E sampled every 10 steps, "
+                      "least-squares slope scaled to 10 ps")
+        log("forms:", json.dumps(out["forms"]))
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
+        log("cpu:", json.dumps(out["cpu_baseline"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

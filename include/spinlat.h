@@ -183,6 +183,20 @@ int sl_get_stats(sl_system *sys, sl_stats *out);
 /* Wait for the system's stream; returns any sticky device error. */
 int sl_synchronize(sl_system *sys);
 
+/* Launch shape of the per-step kernels. Changes speed only: the results
+ * differ at most by summation-order roundoff. lanes = 1, 2, 4 or 8
+ * consecutive wavefront lanes cooperate on one atom (0 = default 4).
+ * Runs of consecutive colour classes of at most small_class atoms each are
+ * applied by one single-workgroup launch (0 = default 512, -1 = never). */
+typedef struct {
+    int spin_lanes;
+    int force_lanes;
+    int small_class;
+} sl_tuning;
+
+int sl_set_tuning(sl_system *sys, const sl_tuning *t);
+int sl_get_tuning(sl_system *sys, sl_tuning *t);
+
 /* Per-kernel timing with HIP events on the system's stream. When on, every
  * launch of the spin-phase, force and rebuild kernels is bracketed by a
  * pair of events; sl_get_profile returns, per kernel kind, the launch count
@@ -191,6 +205,90 @@ int sl_synchronize(sl_system *sys);
 int sl_set_profiling(sl_system *sys, int on);
 int sl_get_profile(sl_system *sys, int kind, int64_t *launches, double *ms,
                    double *work_items);
+
+/* ------------------------------------------------------------------------
+ * Learned pair potential: a per-pair MLP that stands in for the exchange
+ * J(r) (appendix A.1) and the mechanical pair energy phi(r) of
+ * Eq. sl_hamiltonian. r -> 16 Gaussian radial basis functions
+ * b_k = exp(-((r - k mu_step)/sigma)^2) -> silu(64) -> silu(64) -> (y0, y1);
+ * J(r) = sJ y0 for r < ex_rc, phi(r) = sP [y1(r) - y1(rc) - (r - rc) y1'(rc)]
+ * for r < rc. Evaluated on BF16 matrix cores with FP32 accumulation; the
+ * r-derivatives go through the network as a forward-mode tangent.
+ * Parameters (FP32 master copy, SL_MLP_NPARAM values): W1[64][16], c1[64],
+ * W2[64][64], c2[64], W3[2][64], c3[2], row-major.
+ */
+#define SL_MLP_NPARAM 5378
+
+typedef struct sl_mlp sl_mlp;
+
+typedef struct {
+    double sigma;     /* RBF width, A (0: 0.4)                          */
+    double mu_step;   /* RBF centre spacing, A (0: 5/15)                */
+    double sJ, sP;    /* output scales of J and phi, eV (0: 0.01, 1)    */
+    double ex_rc;     /* exchange cutoff, A (0: 3.5)                    */
+    double rc;        /* mechanical cutoff, A (0: 5)                    */
+    void *stream;     /* hipStream_t; NULL: own stream                  */
+} sl_mlp_spec;
+
+int sl_mlp_create(const sl_mlp_spec *spec, sl_mlp **out);
+int sl_mlp_destroy(sl_mlp *m);
+/* Copy in/out the FP32 master parameters (n must be SL_MLP_NPARAM). */
+int sl_mlp_set_weights(sl_mlp *m, const float *params, int n, int where);
+int sl_mlp_get_weights(sl_mlp *m, float *params, int n, int where);
+/* out[P][4] = (J, dJ/dr, phi, dphi/dr) at the P distances r (tests). */
+int sl_mlp_eval(sl_mlp *m, const double *r, int64_t P, double *out, int where);
+const char *sl_mlp_last_error(const sl_mlp *m);
+
+/* Use the learned potential for J and the mechanical pair energy of this
+ * system (replacing Morse and Bethe-Slater; Zeeman, anisotropy and the bath
+ * are kept); NULL restores the analytic potential. FP32 form only. After
+ * every drift the network is evaluated once per unordered pair of the list
+ * and the spin phases and the force kernel read that table. The handle must
+ * outlive its use; its weights may be changed between sl_step calls. */
+int sl_set_mlp(sl_system *sys, sl_mlp *m);
+
+/* Per-atom force F_i = sum_j [-phi'(r) + J'(r) s_i.s_j] e_ij (Eq. p_advance)
+ * and exchange part of hbar omega_i = sum_j J(r_ij) s_j (Sec. 2) of the
+ * current state, double[N][3] each in user order (NULL: skipped), from the
+ * analytic potential or the learned one. Synchronises. */
+int sl_get_fields(sl_system *sys, double *F, double *hw, int where);
+
+/* Training data: S snapshots of one N-atom periodic box, host arrays.
+ * Labels come from the analytic path: E = pair + exchange energy, F the
+ * force and hw the exchange part of hbar omega (see sl_get_fields). */
+typedef struct {
+    int n_snapshots;
+    int64_t n_atoms;
+    double box[3];
+    const double *r;     /* [S][N][3] positions, A           */
+    const double *s;     /* [S][N][3] unit spins             */
+    const double *E;     /* [S] pair + exchange energy, eV   */
+    const double *F;     /* [S][N][3] forces, eV/A           */
+    const double *hw;    /* [S][N][3] exchange hbar omega, eV */
+} sl_dataset;
+
+/* Loss of one snapshot (learned potential in place of J and phi):
+ *   w_E ((E - E_ref)/N)^2 + w_F |F - F_ref|^2/(3N) + w_W |hw - hw_ref|^2/(3N)
+ * and its gradient with respect to the SL_MLP_NPARAM master parameters
+ * (grad may be NULL), by the BF16-MFMA forward/tangent and reverse kernels
+ * with FP32 accumulation. */
+int sl_mlp_loss_grad(sl_mlp *m, const sl_dataset *d, int snapshot, const double w[3],
+                     double *loss, float *grad);
+
+typedef struct {
+    int epochs;                  /* passes over the snapshots              */
+    double lr, beta1, beta2, eps;/* Adam (0: 1e-3, 0.9, 0.999, 1e-8)       */
+    double w_E, w_F, w_W;        /* loss weights                           */
+    uint64_t seed;               /* snapshot order                         */
+} sl_train_opts;
+
+typedef struct {
+    double loss_first, loss_last;   /* mean loss of the first / last epoch */
+    int64_t updates;
+} sl_train_log;
+
+/* Adam on the FP32 master parameters, one update per snapshot. */
+int sl_mlp_train(sl_mlp *m, const sl_dataset *d, const sl_train_opts *o, sl_train_log *log);
 
 /* Message of the last failed call on this handle (or of the last failed
  * sl_create when sys is NULL). Never NULL. */

@@ -23,17 +23,12 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include "mlp.h"
+
 #define NB 16
 #define NH 64
 #define NO 2
 #define NPARAM (NH * NB + NH + NH * NH + NH + NO * NH + NO)
-
-typedef struct {
-    double sigma;    /* RBF width, A */
-    double mu_step;  /* RBF spacing, A */
-    double sJ, sP;   /* output scales, eV */
-    double ex_rc, rc;
-} mlp_cfg;
 
 int mlp_nparam(void) { return NPARAM; }
 

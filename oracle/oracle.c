@@ -15,6 +15,7 @@
  * colouring, rebuild rule, Philox layout).
  */
 #include "oracle.h"
+#include "mlp.h"
 
 #include <math.h>
 #include <stdlib.h>
@@ -55,6 +56,10 @@ struct orc_sys {
     /* rebuild predictor of the previous step boundary */
     double D_prev;
     int have_D;
+
+    /* learned pair potential standing in for J and V (NULL: analytic) */
+    mlp_cfg mcfg;
+    double *mparams;
 
     /* scratch */
     double *w_tmp;
@@ -113,6 +118,21 @@ double orc_V(const orc_pot *p, double r, double *dVdr)
     double Mc = morse_raw(p, p->morse_rc, &dMc);
     if (dVdr) *dVdr = dM - dMc;
     return M - Mc - (r - p->morse_rc) * dMc;
+}
+
+/* J(r), J'(r), V(r), V'(r) of one pair: the analytic forms, or the learned
+ * pair potential when one is set (it replaces both the exchange and the
+ * mechanical pair term). */
+static void pair_terms(const orc_sys *S, double r, double *J, double *dJ, double *V, double *dV)
+{
+    if (S->mparams) {
+        double o[4];
+        mlp_eval(&S->mcfg, S->mparams, r, o);
+        *J = o[0]; *dJ = o[1]; *V = o[2]; *dV = o[3];
+        return;
+    }
+    *J = orc_J(&S->pot, r, dJ);
+    *V = orc_V(&S->pot, r, dV);
 }
 
 /* Minimum-image displacement d = r_i - r_j in an orthorhombic periodic box. */
@@ -248,9 +268,23 @@ orc_sys *orc_create(int N, const double L[3], int frozen, double skin,
     return S;
 }
 
+void orc_set_mlp(orc_sys *S, const mlp_cfg *c, const double *params)
+{
+    free(S->mparams);
+    S->mparams = NULL;
+    if (params) {
+        int n = mlp_nparam();
+        S->mparams = (double *)malloc((size_t)n * sizeof(double));
+        memcpy(S->mparams, params, (size_t)n * sizeof(double));
+        S->mcfg = *c;
+    }
+    S->have_F = 0;
+}
+
 void orc_destroy(orc_sys *S)
 {
     if (!S) return;
+    free(S->mparams);
     free(S->r); free(S->v); free(S->s); free(S->F); free(S->rbuild);
     free(S->w_tmp); free(S->m); free(S->off); free(S->idx); free(S->nspin);
     free(S->colour); free(S->cls); free(S->cls_off);
@@ -637,7 +671,8 @@ static void omega_i(const orc_sys *S, int i, double w[3])
         double d[3];
         min_image(S->L, S->r + 3 * i, S->r + 3 * j, d);
         double r = norm3(d);
-        double J = orc_J(p, r, NULL);
+        double J, dJ, V, dV;
+        pair_terms(S, r, &J, &dJ, &V, &dV);
         for (int a = 0; a < 3; ++a) acc[a] += J * S->s[3 * j + a];
     }
     const double *si = S->s + 3 * i;
@@ -657,7 +692,6 @@ void orc_omega_all(orc_sys *S, double *w)
  * with e_ij = (r_i - r_j)/r_ij, so that F_i = -dH/dr_i. */
 static void forces(orc_sys *S)
 {
-    const orc_pot *p = &S->pot;
     for (int i = 0; i < S->N; ++i) {
         double f[3] = {0.0, 0.0, 0.0};
         for (int k = S->off[i]; k < S->off[i + 1]; ++k) {
@@ -665,9 +699,8 @@ static void forces(orc_sys *S)
             double d[3];
             min_image(S->L, S->r + 3 * i, S->r + 3 * j, d);
             double r = norm3(d);
-            double dV, dJ;
-            orc_V(p, r, &dV);
-            orc_J(p, r, &dJ);
+            double J, dJ, V, dV;
+            pair_terms(S, r, &J, &dJ, &V, &dV);
             double c = -dV + dJ * dot3(S->s + 3 * i, S->s + 3 * j);
             for (int a = 0; a < 3; ++a) f[a] += c * d[a] / r;
         }
@@ -910,8 +943,10 @@ void orc_energy(orc_sys *S, double e[6])
             double d[3];
             min_image(S->L, S->r + 3 * i, S->r + 3 * j, d);
             double r = norm3(d);
-            if (!S->frozen) pair += orc_V(p, r, NULL);
-            ex -= orc_J(p, r, NULL) * dot3(S->s + 3 * i, S->s + 3 * j);
+            double J, dJ, V, dV;
+            pair_terms(S, r, &J, &dJ, &V, &dV);
+            if (!S->frozen) pair += V;
+            ex -= J * dot3(S->s + 3 * i, S->s + 3 * j);
         }
         const double *si = S->s + 3 * i;
         zee -= p->zeeman_g * ORC_MUB * dot3(p->B, si);

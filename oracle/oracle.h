@@ -14,6 +14,8 @@
 
 #include <stdint.h>
 
+#include "mlp.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -84,6 +86,9 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
                        uint32_t out[4]);
 void orc_gauss3(uint64_t seed, uint32_t atom_id, int64_t step,
                 uint32_t replica, int sub, double out[3]);
+
+/* Use the FP64 learned pair potential for J and V (params NULL: analytic). */
+void orc_set_mlp(orc_sys *S, const mlp_cfg *c, const double *params);
 
 /* Brute-force O(N^2) neighbour sets for pinning the cell-list build. */
 long orc_brute_pairs(int N, const double L[3], const double *r, double rcut,

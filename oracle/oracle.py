@@ -111,6 +111,7 @@ def lib():
         L.mlp_loss_grad.restype = C.c_double
         L.mlp_loss_grad.argtypes = [C.POINTER(MlpCfg), dp, C.c_int, dp, dp, dp, C.c_int, ip, ip,
                                     C.c_double, dp, dp, dp, dp]
+        L.orc_set_mlp.argtypes = [C.c_void_p, C.POINTER(MlpCfg), dp]
         L.orc_brute_pairs.restype = C.c_long
         L.orc_brute_pairs.argtypes = [C.c_int, dp, dp, C.c_double, ip, ip, C.c_long]
         _lib = L
@@ -159,6 +160,15 @@ class Oracle:
     def set_potential(self, pot: dict):
         self._pot = make_pot(pot)
         lib().orc_set_potential(self.h, C.byref(self._pot))
+
+    def set_mlp(self, cfg, params):
+        """Use the FP64 learned pair potential for J and V (None: analytic)."""
+        if params is None:
+            lib().orc_set_mlp(self.h, None, None)
+        else:
+            self._mp = _f64(params)
+            self._mcfg = cfg
+            lib().orc_set_mlp(self.h, C.byref(cfg), _dp(self._mp))
 
     def set_ordering(self, ordering, sect_grid=(1, 1, 1)):
         g = np.ascontiguousarray(sect_grid, dtype=np.int32)

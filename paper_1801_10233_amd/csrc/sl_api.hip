@@ -14,6 +14,7 @@
 #include "../../include/spinlat.h"
 #include "sl_device.h"
 #include "sl_kernels.h"
+#include "sl_mlp_host.h"
 
 using namespace sl;
 
@@ -57,6 +58,8 @@ struct sl_system {
   double L[3] = {0, 0, 0}, invL[3] = {0, 0, 0};
   double skin = 0.3;
   int max_nbr = 80, max_spin = 32;
+  int spin_lanes = 4, force_lanes = 4;  // lanes per atom (tuning only)
+  int small_class = 512;                // fused small-class threshold (-1: off)
   hipStream_t st = nullptr;
   bool own_stream = false;
 
@@ -93,6 +96,15 @@ struct sl_system {
   int sticky = 0;
   std::vector<int64_t> thermo_steps;
   int thermo_read = 0;
+
+  // learned potential (FP32 form): unordered pairs of the list with their
+  // mirror slots, and one (J, J', phi, phi') table per position buffer
+  sl_mlp *mlp = nullptr;
+  int2 *mpairs = nullptr;
+  int *mirror = nullptr, *mcnt = nullptr, *mstart = nullptr;
+  int npair = 0, mpair_cap = 0;
+  float4 *tab[2] = {nullptr, nullptr};
+  bool tab_ok[2] = {false, false};
 
   bool prof = false;
   std::vector<ProfRec> prof_recs;
@@ -209,6 +221,7 @@ SysView<real> view(sl_system *S, int posbuf) {
   v.nspin = A.nspin;
   v.nall = A.nall;
   v.id = A.id;
+  v.tab = S->mlp ? S->tab[posbuf] : nullptr;
   return v;
 }
 
@@ -408,6 +421,54 @@ int jp_rounds(sl_system *S, const ColourArgs &C) {
   return SL_OK;
 }
 
+// Unordered pairs of the current list for the learned-potential table.
+int mlp_pairs(sl_system *S) {
+  Atoms &A = S->a[S->cur];
+  const int n = S->n;
+  launch_mlp_pair_count(n, S->ld, A.nbr, A.nall, S->mcnt, S->st);
+  launch_scan(S->mcnt, S->mstart, n, S->st);
+  int tot = 0;
+  HIPCHK(S, hipMemcpyAsync(&tot, S->mstart + n, sizeof(int), hipMemcpyDeviceToHost, S->st));
+  HIPCHK(S, hipStreamSynchronize(S->st));
+  if (tot > S->mpair_cap) {
+    dfree(S->mpairs);
+    dfree(S->mirror);
+    S->mpair_cap = tot + tot / 4 + 64;
+    HIPCHK(S, dalloc(&S->mpairs, S->mpair_cap));
+    HIPCHK(S, dalloc(&S->mirror, S->mpair_cap));
+  }
+  launch_mlp_pair_fill(n, S->ld, A.nbr, A.nall, S->mstart, S->mpairs, S->mirror, S->err, S->st);
+  S->npair = tot;
+  S->tab_ok[0] = S->tab_ok[1] = false;
+  return SL_OK;
+}
+
+// Table of the learned potential at the positions of buffer b.
+int ensure_table(sl_system *S, int b) {
+  if (!S->mlp || S->tab_ok[b]) return SL_OK;
+  Atoms &A = S->a[S->cur];
+  MlpTableArgs T;
+  T.npair = S->npair;
+  T.ld = S->ld;
+  T.pairs = S->mpairs;
+  T.mirror = S->mirror;
+  T.nbr = A.nbr;
+  T.rx = A.rx[b];
+  T.ry = A.ry[b];
+  T.rz = A.rz[b];
+  for (int d = 0; d < 3; ++d) {
+    T.L[d] = S->L[d];
+    T.invL[d] = S->invL[d];
+  }
+  T.tab = S->tab[b];
+  {
+    ProfScope ps(S, 3, (double)S->npair);
+    launch_mlp_table(T, S->mlp->w, S->mlp->cfg(), S->mlp->yc, S->st);
+  }
+  S->tab_ok[b] = true;
+  return SL_OK;
+}
+
 // Colour classes (repairing the previous colouring when there is one) and
 // permutation of all per-atom arrays into (colour, cell) order.
 int colour_and_permute(sl_system *S, bool repair) {
@@ -497,6 +558,7 @@ int colour_and_permute(sl_system *S, bool repair) {
   HIPCHK(S, hipStreamSynchronize(S->st));
   S->class_off.assign(S->K + 1, 0);
   for (int c = 0; c <= S->K; ++c) S->class_off[c] = bs[(size_t)c * S->ncell];
+  if (S->mlp) CHK(mlp_pairs(S));
   return SL_OK;
 }
 
@@ -558,6 +620,8 @@ int ensure_ready(sl_system *S) {
 }
 
 // --- launches ---------------------------------------------------------------
+double noise_amp(const sl_system *S, double h);
+
 template <typename real>
 void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps, const int *subs,
                  double h) {
@@ -567,11 +631,7 @@ void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps
   A.end = S->class_off[c + 1];
   A.nrep = nrep;
   A.h = h;
-  if (S->pc.langevin) {
-    const double lam = S->pot.lambda;
-    const double DS = lam * (1.0 + lam * lam) * kKb * S->pot.temperature / kHbar;
-    A.amp = std::sqrt(2.0 * DS / std::fabs(h));
-  }
+  A.amp = noise_amp(S, h);
   for (int r = 0; r < nrep; ++r) {
     A.step[r] = steps[r];
     A.sub[r] = subs[r];
@@ -580,32 +640,86 @@ void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps
   A.replica = S->prm.replica;
   A.rs2 = S->pot.ex_rc * S->pot.ex_rc;
   ProfScope ps(S, 0, (double)(A.end - A.begin));
-  launch_spin_phase<real>(view<real>(S, posbuf), S->pc, A, S->st);
+  launch_spin_phase<real>(view<real>(S, posbuf), S->pc, A, S->spin_lanes, S->st);
 }
 
-// A run of dt/4 updates (class, step, sub) applied in order with merging of
-// consecutive updates of one class.
+// A run of dt/4 updates (class, step, sub) applied in order. Consecutive
+// updates of one class are merged into one launch (up to kMaxRep); runs of
+// consecutive small classes go to one single-workgroup launch.
 struct Upd {
   int c;
   int64_t step;
   int sub;
 };
 
+constexpr int kTailTotalMax = 4096;  // atoms of one fused run
+
+struct Item {
+  int c, nrep;
+  int64_t steps[kMaxRep];
+  int subs[kMaxRep];
+};
+
+double noise_amp(const sl_system *S, double h) {
+  if (!S->pc.langevin) return 0.0;
+  const double lam = S->pot.lambda;
+  const double DS = lam * (1.0 + lam * lam) * kKb * S->pot.temperature / kHbar;
+  return std::sqrt(2.0 * DS / std::fabs(h));
+}
+
 template <typename real>
 void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) {
-  size_t i = 0;
-  while (i < u.size()) {
-    int64_t steps[kMaxRep];
-    int subs[kMaxRep];
-    int nrep = 0;
-    const int c = u[i].c;
-    while (i < u.size() && u[i].c == c && nrep < kMaxRep) {
-      steps[nrep] = u[i].step;
-      subs[nrep] = u[i].sub;
-      ++nrep;
+  (void)ensure_table(S, posbuf);
+  std::vector<Item> items;
+  for (size_t i = 0; i < u.size();) {
+    Item it;
+    it.c = u[i].c;
+    it.nrep = 0;
+    while (i < u.size() && u[i].c == it.c && it.nrep < kMaxRep) {
+      it.steps[it.nrep] = u[i].step;
+      it.subs[it.nrep] = u[i].sub;
+      ++it.nrep;
       ++i;
     }
-    spin_launch<real>(S, posbuf, c, nrep, steps, subs, h);
+    items.push_back(it);
+  }
+  auto size_of = [&](int c) { return S->class_off[c + 1] - S->class_off[c]; };
+  size_t q = 0;
+  while (q < items.size()) {
+    size_t r = q;
+    long tot = 0;
+    while (r < items.size() && (int)(r - q) < kMaxTail) {
+      const int sz = size_of(items[r].c);
+      if (sz > S->small_class || tot + sz > kTailTotalMax) break;
+      tot += sz;
+      ++r;
+    }
+    if (r - q >= 2) {
+      TailArgs T;
+      std::memset(&T, 0, sizeof(T));
+      T.nitems = (int)(r - q);
+      for (size_t k = q; k < r; ++k) {
+        TailItem &ti = T.item[k - q];
+        ti.begin = S->class_off[items[k].c];
+        ti.end = S->class_off[items[k].c + 1];
+        ti.nrep = items[k].nrep;
+        for (int e = 0; e < items[k].nrep; ++e) {
+          ti.step[e] = items[k].steps[e];
+          ti.sub[e] = items[k].subs[e];
+        }
+      }
+      T.h = h;
+      T.amp = noise_amp(S, h);
+      T.seed = S->prm.seed;
+      T.replica = S->prm.replica;
+      T.rs2 = S->pot.ex_rc * S->pot.ex_rc;
+      ProfScope ps(S, 0, (double)tot);
+      launch_spin_tail<real>(view<real>(S, posbuf), S->pc, T, S->spin_lanes, S->st);
+      q = r;
+    } else {
+      spin_launch<real>(S, posbuf, items[q].c, items[q].nrep, items[q].steps, items[q].subs, h);
+      ++q;
+    }
   }
 }
 
@@ -638,6 +752,8 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   F.done = S->done;
   F.err = S->err;
   F.frozen = S->prm.frozen;
+  CHK(ensure_table(S, posbuf));
+  if (mode & kModeNext) S->tab_ok[1 - posbuf] = false;
   const int slot = (int)(boundary & 3);
   F.host_out = S->ring_dev + 4 * slot;
   if (mode & (kModeFinal | kModeNext)) {
@@ -648,14 +764,14 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   }
   {
     ProfScope ps(S, 1, (double)S->n);
-    launch_force<real>(view<real>(S, posbuf), S->pc, F, S->st);
+    launch_force<real>(view<real>(S, posbuf), S->pc, F, S->force_lanes, S->st);
   }
   if (mode & (kModeFinal | kModeNext)) HIPCHK(S, hipEventRecord(S->ev[slot], S->st));
   return SL_OK;
 }
 
 int record_thermo(sl_system *S, int64_t boundary) {
-  const int nb = (S->n + kBlock - 1) / kBlock;
+  const int nb = force_blocks(S->n, S->force_lanes);
   const int k = (int)S->thermo_steps.size();
   if (k >= kThermoCap) return SL_OK;
   launch_reduce8(S->partial, nb, S->thermo + (size_t)k * 8, S->st);
@@ -666,7 +782,7 @@ int record_thermo(sl_system *S, int64_t boundary) {
 template <typename real>
 int energy_now(sl_system *S, double out[8]) {
   CHK(force_launch<real>(S, S->pos, kModeEnergy, 0.0, -1));
-  const int nb = (S->n + kBlock - 1) / kBlock;
+  const int nb = force_blocks(S->n, S->force_lanes);
   launch_reduce8(S->partial, nb, S->red_out, S->st);
   HIPCHK(S, hipMemcpyAsync(out, S->red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, S->st));
   CHK(read_err(S));
@@ -819,7 +935,7 @@ int sl_create(const sl_params *p, sl_system **out) {
   }
   if ((rc = alloc_atoms(S, S->a[0])) || (rc = alloc_atoms(S, S->a[1]))) return bail(rc == SL_E_HIP ? SL_E_NOMEM : rc);
   const int n = S->n;
-  const int nb = (n + kBlock - 1) / kBlock;
+  const int nb = force_blocks(n, 8);
 #define A_(x) if (hipSuccess != (x)) { S->last_err = #x; return bail(SL_E_NOMEM); }
   A_(dalloc(&S->catoms, n));
   A_(dalloc(&S->skey, n));
@@ -874,7 +990,9 @@ int sl_destroy(sl_system *S) {
                   (void *)S->perm, (void *)S->inv, (void *)S->uinv, (void *)S->ctmp,
                   (void *)S->kx, (void *)S->ky, (void *)S->kz, (void *)S->stage, (void *)S->err,
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
-                  (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo})
+                  (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo,
+                  (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
+                  (void *)S->tab[0], (void *)S->tab[1]})
     dfree(p);
   if (S->ring) (void)hipHostFree(S->ring);
   if (S->own_stream && S->st) (void)hipStreamDestroy(S->st);
@@ -958,6 +1076,7 @@ int sl_set_state(sl_system *S, const double *r, const double *v, const double *s
   if (!S->user_list) S->have_list = false;
   S->have_colour = false;
   S->have_D = false;
+  S->tab_ok[0] = S->tab_ok[1] = false;
   S->sticky = 0;
   HIPCHK(S, hipMemsetAsync(S->err, 0, sizeof(int), S->st));
   return SL_OK;
@@ -997,6 +1116,12 @@ int sl_set_neighbor(sl_system *S, double skin, int max_nbr) {
     if (S->max_spin > max_nbr) S->max_spin = max_nbr;
     HIPCHK(S, dalloc(&S->a[0].nbr, (size_t)S->ld * S->max_nbr));
     HIPCHK(S, dalloc(&S->a[1].nbr, (size_t)S->ld * S->max_nbr));
+    for (int b = 0; b < 2; ++b)
+      if (S->tab[b]) {
+        dfree(S->tab[b]);
+        S->tab[b] = nullptr;
+        HIPCHK(S, dalloc(&S->tab[b], (size_t)S->ld * S->max_nbr));
+      }
   }
   S->user_list = false;
   S->have_list = false;
@@ -1237,6 +1362,46 @@ int sl_synchronize(sl_system *S) {
   return sticky_code(S);
 }
 
+int sl_set_mlp(sl_system *S, sl_mlp *m) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  CHK(sl_synchronize(S));
+  if (m) {
+    if (S->prec != SL_FP32) return fail(S, SL_E_ARG, "the learned potential runs in the FP32 form");
+    if (!m->have_weights) return fail(S, SL_E_STATE, "the MLP has no weights");
+    (void)hipStreamSynchronize(m->st);
+    for (int b = 0; b < 2; ++b)
+      if (!S->tab[b]) HIPCHK(S, dalloc(&S->tab[b], (size_t)S->ld * S->max_nbr));
+    if (!S->mcnt) {
+      HIPCHK(S, dalloc(&S->mcnt, S->n));
+      HIPCHK(S, dalloc(&S->mstart, S->n + 1));
+    }
+  }
+  S->mlp = m;
+  S->tab_ok[0] = S->tab_ok[1] = false;
+  if (m && S->have_list && S->have_colour) CHK(mlp_pairs(S));
+  return SL_OK;
+}
+
+int sl_set_tuning(sl_system *S, const sl_tuning *t) {
+  if (!S || !t) return fail(S, SL_E_ARG, "NULL argument");
+  auto ok = [](int x) { return x == 0 || x == 1 || x == 2 || x == 4 || x == 8; };
+  if (!ok(t->spin_lanes) || !ok(t->force_lanes)) return fail(S, SL_E_ARG, "lanes must be 1, 2, 4 or 8");
+  if (t->small_class < -1) return fail(S, SL_E_ARG, "small_class must be >= -1");
+  CHK(sl_synchronize(S));
+  S->spin_lanes = t->spin_lanes ? t->spin_lanes : 4;
+  S->force_lanes = t->force_lanes ? t->force_lanes : 4;
+  S->small_class = t->small_class == 0 ? 512 : t->small_class;
+  return SL_OK;
+}
+
+int sl_get_tuning(sl_system *S, sl_tuning *t) {
+  if (!S || !t) return fail(S, SL_E_ARG, "NULL argument");
+  t->spin_lanes = S->spin_lanes;
+  t->force_lanes = S->force_lanes;
+  t->small_class = S->small_class;
+  return SL_OK;
+}
+
 int sl_set_profiling(sl_system *S, int on) {
   if (!S) return fail(S, SL_E_ARG, "NULL system");
   if (S->prof && !on) prof_collect(S);
@@ -1261,6 +1426,244 @@ int sl_get_profile(sl_system *S, int kind, int64_t *launches, double *ms, double
 const char *sl_last_error(const sl_system *S) {
   if (!S) return g_create_err.c_str();
   return S->last_err.c_str();
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Fields and learned-potential training.
+int mfail_str(sl_mlp *m, int code, const std::string &msg);
+
+namespace {
+
+template <typename real>
+int fields_now(sl_system *S, double *F, double *hw, int where) {
+  const int n = S->n;
+  double *dF = nullptr, *dW = nullptr;
+  HIPCHK(S, dalloc(&dF, 3 * (size_t)n));
+  HIPCHK(S, dalloc(&dW, 3 * (size_t)n));
+  CHK(ensure_table(S, S->pos));
+  FieldArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.F = dF;
+  A.hw = dW;
+  launch_fields<real>(view<real>(S, S->pos), S->pc, A, S->st);
+  Atoms &At = S->a[S->cur];
+  for (int q = 0; q < 2; ++q) {
+    double *src = q ? dW : dF, *dst = q ? hw : F;
+    if (!dst) continue;
+    launch_store_vec(n, At.id, src, src + n, src + 2 * (size_t)n, S->stage, S->st);
+    HIPCHK(S, hipMemcpyAsync(dst, S->stage, sizeof(double) * 3 * n,
+                             where == SL_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, S->st));
+    HIPCHK(S, hipStreamSynchronize(S->st));
+  }
+  dfree(dF);
+  dfree(dW);
+  return sticky_code(S);
+}
+
+int mlp_trainer(sl_mlp *m, const sl_dataset *d) {
+  sl_system *S = m->trainer;
+  if (S && (S->n != d->n_atoms || S->L[0] != d->box[0] || S->L[1] != d->box[1] || S->L[2] != d->box[2])) {
+    sl_destroy(S);
+    m->trainer = S = nullptr;
+  }
+  if (!S) {
+    sl_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.n_atoms = d->n_atoms;
+    for (int k = 0; k < 3; ++k) p.box[k] = d->box[k];
+    p.precision = SL_FP32;
+    p.skin = 0.0;
+    p.stream = m->st;
+    int rc = sl_create(&p, &S);
+    if (rc) return mfail_str(m, rc, std::string("trainer: ") + sl_last_error(nullptr));
+    sl_potential pot;
+    std::memset(&pot, 0, sizeof(pot));
+    pot.morse_on = 1;
+    pot.morse_rc = m->rc;
+    pot.morse_shift = 1;
+    pot.ex_alpha = 1.0;
+    pot.ex_delta = 1.0;
+    pot.ex_rc = m->ex_rc;
+    pot.zeeman_g = 2.0;
+    pot.aniso_n[2] = 1.0;
+    rc = sl_set_potential(S, &pot);
+    if (rc) {
+      std::string e = S->last_err;
+      sl_destroy(S);
+      return mfail_str(m, rc, "trainer: " + e);
+    }
+    m->trainer = S;
+  }
+  return SL_OK;
+}
+
+}  // namespace
+
+int mfail_str(sl_mlp *m, int code, const std::string &msg) {
+  if (m) m->last_err = msg;
+  return code;
+}
+
+extern "C" {
+
+int sl_get_fields(sl_system *S, double *F, double *hw, int where) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  CHK(sl_synchronize(S));
+  CHK(ensure_ready(S));
+  return S->prec == SL_FP64 ? fields_now<double>(S, F, hw, where) : fields_now<float>(S, F, hw, where);
+}
+
+int sl_mlp_loss_grad(sl_mlp *m, const sl_dataset *d, int snap, const double w[3], double *loss,
+                     float *grad) {
+  if (!m || !d || !w || !loss) return mfail_str(m, SL_E_ARG, "NULL argument");
+  if (!m->have_weights) return mfail_str(m, SL_E_STATE, "no weights set");
+  if (snap < 0 || snap >= d->n_snapshots || d->n_atoms < 2) return mfail_str(m, SL_E_ARG, "bad snapshot");
+  CHK(mlp_trainer(m, d));
+  sl_system *S = m->trainer;
+  const int n = S->n;
+  const size_t off = (size_t)snap * n * 3;
+  std::vector<double> zeros(3 * (size_t)n, 0.0), ones(n, 1.0);
+  int rc = sl_set_state(S, d->r + off, zeros.data(), d->s + off, ones.data(), SL_HOST);
+  if (rc) return mfail_str(m, rc, std::string("snapshot state: ") + S->last_err);
+  rc = sl_set_mlp(S, m);
+  if (rc) return mfail_str(m, rc, S->last_err);
+  rc = ensure_ready(S);
+  if (rc) return mfail_str(m, rc, S->last_err);
+  rc = ensure_table(S, S->pos);
+  if (rc) return mfail_str(m, rc, S->last_err);
+  // references in internal order
+  Atoms &A = S->a[S->cur];
+  double *ref = nullptr, *out = nullptr;
+  float *gbuf = nullptr, *rp = nullptr, *part = nullptr;
+  float4 *yb = nullptr, *s4 = nullptr;
+  float2 *sh = nullptr;
+  const int P = S->npair;
+  const int nw = mlp_backward_waves(P);
+  auto cleanup = [&]() {
+    for (void *q : {(void *)ref, (void *)out, (void *)gbuf, (void *)rp, (void *)part, (void *)yb, (void *)s4, (void *)sh})
+      dfree(q);
+  };
+#define TCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { cleanup(); return mfail_str(m, SL_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); } } while (0)
+  TCHK(dalloc(&ref, 6 * (size_t)n));
+  TCHK(dalloc(&out, 8 * (size_t)n + 8));
+  TCHK(dalloc(&gbuf, 6 * (size_t)n));
+  TCHK(dalloc(&rp, (size_t)P + 1));
+  TCHK(dalloc(&yb, (size_t)P + 1));
+  TCHK(dalloc(&sh, (size_t)P + 1));
+  TCHK(dalloc(&s4, 4));
+  TCHK(dalloc(&part, (size_t)nw * SL_MLP_NPARAM));
+  for (int q = 0; q < 2; ++q) {
+    const double *src = (q ? d->hw : d->F) + off;
+    TCHK(hipMemcpyAsync(S->stage, src, sizeof(double) * 3 * n, hipMemcpyHostToDevice, S->st));
+    double *dst = ref + (size_t)q * 3 * n;
+    launch_load_vec(n, A.id, S->stage, dst, dst + n, dst + 2 * (size_t)n, S->st);
+  }
+  FieldArgs Fa;
+  std::memset(&Fa, 0, sizeof(Fa));
+  double *e_at = out, *lossp = out + n, *sums = out + 8 * (size_t)n;
+  Fa.e = e_at;
+  Fa.Fref = ref;
+  Fa.hwref = ref + 3 * (size_t)n;
+  Fa.wF = w[1];
+  Fa.wW = w[2];
+  Fa.gF = gbuf;
+  Fa.gW = gbuf + 3 * (size_t)n;
+  Fa.lossp = lossp;
+  launch_fields<float>(view<float>(S, S->pos), S->pc, Fa, S->st);
+  launch_sum_d(e_at, n, sums, S->st);
+  launch_sum_d(lossp, n, sums + 1, S->st);
+  double hs[2];
+  TCHK(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, S->st));
+  TCHK(hipStreamSynchronize(S->st));
+  const double eres = (hs[0] - d->E[snap]) / n;
+  *loss = w[0] * eres * eres + hs[1];
+  if (grad) {
+    PairAdjArgs Pa;
+    std::memset(&Pa, 0, sizeof(Pa));
+    Pa.npair = P;
+    Pa.ld = S->ld;
+    Pa.n = n;
+    Pa.pairs = S->mpairs;
+    Pa.nbr = A.nbr;
+    Pa.rx = A.rx[S->pos];
+    Pa.ry = A.ry[S->pos];
+    Pa.rz = A.rz[S->pos];
+    for (int k = 0; k < 3; ++k) {
+      Pa.L[k] = S->L[k];
+      Pa.invL[k] = S->invL[k];
+    }
+    Pa.sx = (const float *)A.sx;
+    Pa.sy = (const float *)A.sy;
+    Pa.sz = (const float *)A.sz;
+    Pa.gF = Fa.gF;
+    Pa.gW = Fa.gW;
+    Pa.dE = (float)(2.0 * w[0] * eres / n);
+    Pa.sJ = (float)m->sJ;
+    Pa.sP = (float)m->sP;
+    Pa.ex_rc = (float)m->ex_rc;
+    Pa.rc = (float)m->rc;
+    Pa.rp = rp;
+    Pa.ybar = yb;
+    Pa.shift = sh;
+    launch_pair_adjoint(Pa, S->st);
+    launch_mlp_backward(rp, yb, P, m->w, m->wt, m->cfg(), part, S->st);
+    launch_mlp_grad_reduce(part, nw, m->grad, 0, S->st);
+    // the shifted-force constants y1(rc), y1'(rc): one more point
+    launch_sum_f2(sh, P, s4, S->st);
+    float rcf = (float)m->rc;
+    TCHK(hipMemcpyAsync(rp + P, &rcf, sizeof(float), hipMemcpyHostToDevice, S->st));
+    launch_mlp_backward(rp + P, s4, 1, m->w, m->wt, m->cfg(), part, S->st);
+    launch_mlp_grad_reduce(part, 1, m->grad, 1, S->st);
+    TCHK(hipMemcpyAsync(grad, m->grad, sizeof(float) * SL_MLP_NPARAM, hipMemcpyDeviceToHost, S->st));
+    TCHK(hipStreamSynchronize(S->st));
+  }
+#undef TCHK
+  cleanup();
+  return SL_OK;
+}
+
+int sl_mlp_train(sl_mlp *m, const sl_dataset *d, const sl_train_opts *o, sl_train_log *log) {
+  if (!m || !d || !o) return mfail_str(m, SL_E_ARG, "NULL argument");
+  if (o->epochs < 0) return mfail_str(m, SL_E_ARG, "negative epochs");
+  const float lr = (float)(o->lr > 0 ? o->lr : 1e-3), b1 = (float)(o->beta1 > 0 ? o->beta1 : 0.9);
+  const float b2 = (float)(o->beta2 > 0 ? o->beta2 : 0.999), eps = (float)(o->eps > 0 ? o->eps : 1e-8);
+  const double w[3] = {o->w_E, o->w_F, o->w_W};
+  std::vector<int> order(d->n_snapshots);
+  for (int k = 0; k < d->n_snapshots; ++k) order[k] = k;
+  uint64_t x = o->seed * 6364136223846793005ull + 1442695040888963407ull;
+  std::vector<float> g(SL_MLP_NPARAM);
+  double first = 0.0, last = 0.0;
+  int64_t updates = 0;
+  for (int ep = 0; ep < o->epochs; ++ep) {
+    for (int k = d->n_snapshots - 1; k > 0; --k) {  // Fisher-Yates with an LCG
+      x = x * 6364136223846793005ull + 1442695040888963407ull;
+      const int q = (int)((x >> 33) % (uint64_t)(k + 1));
+      std::swap(order[k], order[q]);
+    }
+    double sum = 0.0;
+    for (int k = 0; k < d->n_snapshots; ++k) {
+      double L = 0.0;
+      CHK(sl_mlp_loss_grad(m, d, order[k], w, &L, g.data()));
+      sum += L;
+      m->adam_t += 1;
+      launch_adam(m->master, m->adam_m, m->adam_v, m->grad, SL_MLP_NPARAM, lr, b1, b2, eps,
+                  (int)m->adam_t, m->trainer->st);
+      (void)hipStreamSynchronize(m->trainer->st);
+      CHK(mlp_refresh(m));
+      ++updates;
+    }
+    const double mean = d->n_snapshots ? sum / d->n_snapshots : 0.0;
+    if (ep == 0) first = mean;
+    last = mean;
+  }
+  if (log) {
+    log->loss_first = first;
+    log->loss_last = last;
+    log->updates = updates;
+  }
+  return SL_OK;
 }
 
 }  // extern "C"

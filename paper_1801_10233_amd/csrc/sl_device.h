@@ -51,6 +51,8 @@ struct SysView {
   const int *nbr;              // ELL neighbour indices
   const int *nspin, *nall;     // segment lengths
   const int *id;               // user id of each internal atom
+  const float4 *tab;           // learned-potential table (J, J', phi, phi') per
+                               // list entry at these positions, or null
 };
 
 struct SpinPhaseArgs {
@@ -63,6 +65,23 @@ struct SpinPhaseArgs {
   uint64_t seed;
   uint32_t replica;
   double rs2;                 // exchange cutoff squared
+};
+
+// Fused run of small colour classes (one workgroup).
+constexpr int kMaxTail = 16;
+constexpr int kTailBlock = 1024;
+struct TailItem {
+  int begin, end, nrep;
+  int64_t step[kMaxRep];
+  int sub[kMaxRep];
+};
+struct TailArgs {
+  int nitems;
+  TailItem item[kMaxTail];
+  double h, amp;
+  uint64_t seed;
+  uint32_t replica;
+  double rs2;
 };
 
 struct ForceArgs {

@@ -23,34 +23,56 @@ namespace sl {
 // (Sec. 4.1, Eq. sLLG). nrep > 1 applies consecutive updates of the same
 // class in one launch (nothing else changes in between); the exchange sum
 // does not depend on s_i, so it is gathered once.
-template <typename real, bool LANGEVIN, bool ANISO>
-__global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst P,
-                                                       SpinPhaseArgs A) {
-  const int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  const int i = A.begin + t;
-  if (i >= A.end) return;
-  const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
+// One spin update (or nrep successive ones) of atom i, shared by the
+// per-class launch and the fused small-class launch. All LANES lanes of an
+// atom must call it (cross-lane shuffles); `valid` masks the tail.
+template <typename real, bool LANGEVIN, bool ANISO, int LANES, bool MLP>
+__device__ __forceinline__ void spin_update(const SysView<real> &S, const PotConst &P, int i,
+                                            bool valid, int l, int nrep, const int64_t *step,
+                                            const int *sub, double hd, double ampd,
+                                            uint64_t seed, uint32_t replica, double rs2) {
   real ax = 0, ay = 0, az = 0;
-  const int ns = S.nspin[i];
-  const int ld = S.ld;
-  for (int k = 0; k < ns; ++k) {
-    const int j = S.nbr[(size_t)k * ld + i];
-    const double dx = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
-    const double dy = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
-    const double dz = min_image(riz - S.rz[j], S.L[2], S.invL[2]);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < A.rs2) {
-      const real u = (real)(r2 * P.eInvD2);
-      const real J = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+  if (valid && MLP) {
+    // learned J(r_ij) from the per-entry table at these positions
+    const int ns = S.nspin[i];
+    const int ld = S.ld;
+    for (int k = l; k < ns; k += LANES) {
+      const int j = S.nbr[(size_t)k * ld + i];
+      const real J = (real)S.tab[(size_t)k * ld + i].x;
       ax += J * S.sx[j];
       ay += J * S.sy[j];
       az += J * S.sz[j];
     }
+  } else if (valid) {
+    const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
+    const int ns = S.nspin[i];
+    const int ld = S.ld;
+    for (int k = l; k < ns; k += LANES) {
+      const int j = S.nbr[(size_t)k * ld + i];
+      const double dx = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
+      const double dy = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
+      const double dz = min_image(riz - S.rz[j], S.L[2], S.invL[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < rs2) {
+        const real u = (real)(r2 * P.eInvD2);
+        const real J = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+        ax += J * S.sx[j];
+        ay += J * S.sy[j];
+        az += J * S.sz[j];
+      }
+    }
   }
+#pragma unroll
+  for (int o = LANES / 2; o > 0; o >>= 1) {
+    ax += __shfl_xor(ax, o, 64);
+    ay += __shfl_xor(ay, o, 64);
+    az += __shfl_xor(az, o, 64);
+  }
+  if (!valid || l != 0) return;
   real sx = S.sx[i], sy = S.sy[i], sz = S.sz[i];
-  const real h = (real)A.h;
+  const real h = (real)hd;
   const real ih = (real)(1.0 / kHbar);
-  for (int rep = 0; rep < A.nrep; ++rep) {
+  for (int rep = 0; rep < nrep; ++rep) {
     real ex = ax + (real)P.zB[0], ey = ay + (real)P.zB[1], ez = az + (real)P.zB[2];
     if (ANISO) {
       const real sn2 = (real)2 * (real)P.aK * (sx * (real)P.an[0] + sy * (real)P.an[1] + sz * (real)P.an[2]);
@@ -58,41 +80,69 @@ __global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst
       ey += sn2 * (real)P.an[1];
       ez += sn2 * (real)P.an[2];
     }
-    real wx, wy, wz;
-    if (sizeof(real) == 8) {
-      wx = ex / (real)kHbar; wy = ey / (real)kHbar; wz = ez / (real)kHbar;
-    } else {
-      wx = ex * ih; wy = ey * ih; wz = ez * ih;
-    }
+    real wx = ex * ih, wy = ey * ih, wz = ez * ih;
     if (LANGEVIN) {
       real g[3];
-      gauss3(A.seed, (uint32_t)S.id[i], A.step[rep], A.replica, A.sub[rep], g);
-      const real lam = (real)P.lam, amp = (real)A.amp, den = (real)1 + lam * lam;
+      gauss3(seed, (uint32_t)S.id[i], step[rep], replica, sub[rep], g);
+      const real lam = (real)P.lam, amp = (real)ampd, f = (real)P.lamfac;
       const real cx = sy * wz - sz * wy, cy = sz * wx - sx * wz, cz = sx * wy - sy * wx;
-      wx = (wx + amp * g[0] + lam * cx) / den;
-      wy = (wy + amp * g[1] + lam * cy) / den;
-      wz = (wz + amp * g[2] + lam * cz) / den;
+      wx = (wx + amp * g[0] + lam * cx) * f;
+      wy = (wy + amp * g[1] + lam * cy) * f;
+      wz = (wz + amp * g[2] + lam * cz) * f;
     }
     // Cayley rotation of Sec. 3 (Omelyan): exact rotation about W by
     // 2 atan(h|W|/2); preserves |s| in exact arithmetic.
     const real cx = wy * sz - wz * sy, cy = wz * sx - wx * sz, cz = wx * sy - wy * sx;
     const real ws = wx * sx + wy * sy + wz * sz;
     const real w2 = wx * wx + wy * wy + wz * wz;
-    const real den = (real)1 + h * h * w2 / (real)4;
-    const real q = h * h / (real)4;
-    real nx = (sx + h * cx + q * ((real)2 * wx * ws - w2 * sx)) / den;
-    real ny = (sy + h * cy + q * ((real)2 * wy * ws - w2 * sy)) / den;
-    real nz = (sz + h * cz + q * ((real)2 * wz * ws - w2 * sz)) / den;
+    const real q = h * h * (real)0.25;
+    const real inv = (real)1 / ((real)1 + q * w2);
+    real nx = (sx + h * cx + q * ((real)2 * wx * ws - w2 * sx)) * inv;
+    real ny = (sy + h * cy + q * ((real)2 * wy * ws - w2 * sy)) * inv;
+    real nz = (sz + h * cz + q * ((real)2 * wz * ws - w2 * sz)) * inv;
     if (sizeof(real) == 4) {
       // FP32 form: renormalise after every rotation.
-      const real inv = (real)rsqrtf((float)(nx * nx + ny * ny + nz * nz));
-      nx *= inv; ny *= inv; nz *= inv;
+      const real rn = (real)rsqrtf((float)(nx * nx + ny * ny + nz * nz));
+      nx *= rn; ny *= rn; nz *= rn;
     }
     sx = nx; sy = ny; sz = nz;
   }
   S.sx[i] = sx;
   S.sy[i] = sy;
   S.sz[i] = sz;
+}
+
+template <typename real, bool LANGEVIN, bool ANISO, int LANES, bool MLP>
+__global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst P,
+                                                       SpinPhaseArgs A) {
+  // LANES consecutive lanes share one atom: each gathers every LANES-th
+  // neighbour, the partial sums are combined with cross-lane shuffles and
+  // the first lane rotates and stores the spin.
+  const int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int l = t & (LANES - 1);
+  const int i = A.begin + t / LANES;
+  spin_update<real, LANGEVIN, ANISO, LANES, MLP>(S, P, i, i < A.end, l, A.nrep, A.step, A.sub,
+                                                 A.h, A.amp, A.seed, A.replica, A.rs2);
+}
+
+// A run of small classes (a few atoms each, e.g. the extra colours a repair
+// adds) in one workgroup: the items are applied in order with a workgroup
+// barrier between them, which keeps the class order of the sweep while
+// paying one launch for the whole run.
+template <typename real, bool LANGEVIN, bool ANISO, int LANES, bool MLP>
+__global__ __launch_bounds__(kTailBlock) void k_spin_tail(SysView<real> S, PotConst P,
+                                                          TailArgs T) {
+  const int l = threadIdx.x & (LANES - 1);
+  const int per = kTailBlock / LANES;
+  for (int q = 0; q < T.nitems; ++q) {
+    const TailItem &it = T.item[q];
+    for (int base = it.begin; base < it.end; base += per) {
+      const int i = base + (int)threadIdx.x / LANES;
+      spin_update<real, LANGEVIN, ANISO, LANES, MLP>(S, P, i, i < it.end, l, it.nrep, it.step,
+                                                     it.sub, T.h, T.amp, T.seed, T.replica, T.rs2);
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -106,23 +156,28 @@ __global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst
 // Every launch with a kick also reduces max |r - r_build| and max |v| at
 // this boundary for the rebuild decision; the last block to finish hands
 // them, with the sticky error word, to pinned host memory.
-template <typename real, int MODE>
+template <typename real, int MODE, int LANES, bool MLP>
 __global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
   __shared__ double red[kBlock / 64][8];
   __shared__ double redm[kBlock / 64][2];
   __shared__ int last;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int i = tile * kBlock + threadIdx.x;
+  const int t = tile * kBlock + threadIdx.x;
+  const int l = t & (LANES - 1);
+  const int i = t / LANES;
+  const bool valid = i < S.n;
   double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double dm = 0.0, vm = 0.0;
-  if (i < S.n) {
-    const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
-    const real six = S.sx[i], siy = S.sy[i], siz = S.sz[i];
-    real fx = 0, fy = 0, fz = 0;
-    real ep = 0, ee = 0;
+  real fx = 0, fy = 0, fz = 0;
+  real ep = 0, ee = 0;
+  double rix = 0, riy = 0, riz = 0;
+  real six = 0, siy = 0, siz = 0;
+  if (valid) {
+    rix = S.rx[i]; riy = S.ry[i]; riz = S.rz[i];
+    six = S.sx[i]; siy = S.sy[i]; siz = S.sz[i];
     const int na = S.nall[i];
     const int ld = S.ld;
-    for (int k = 0; k < na; ++k) {
+    for (int k = l; k < na; k += LANES) {
       const int j = S.nbr[(size_t)k * ld + i];
       const double dxd = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
       const double dyd = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
@@ -131,6 +186,16 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, F
       const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd;
       const real r = (real)sqrt(r2d);
       real c = 0;
+      if (MLP) {
+        // learned phi'(r), J'(r) (and phi, J for energies) from the table
+        const float4 t = S.tab[(size_t)k * ld + i];
+        const real sisj = six * S.sx[j] + siy * S.sy[j] + siz * S.sz[j];
+        c = -(real)t.w + (real)t.y * sisj;
+        if (MODE & kModeEnergy) {
+          ep += (real)0.5 * (real)t.z;
+          ee -= (real)0.5 * (real)t.x * sisj;
+        }
+      } else {
       if (P.morse_on && r2d < P.mRc2) {
         const real ex = exp(-(real)P.mA * (r - (real)P.mR0));
         const real dM = -(real)2 * (real)P.mA * (real)P.mD * (ex * ex - ex);
@@ -149,10 +214,24 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, F
         if (MODE & kModeEnergy)
           ee -= (real)0.5 * (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * eu * sisj;
       }
-      fx += c * dx / r;
-      fy += c * dy / r;
-      fz += c * dz / r;
+      }
+      const real cr = c / r;
+      fx += cr * dx;
+      fy += cr * dy;
+      fz += cr * dz;
     }
+  }
+#pragma unroll
+  for (int o = LANES / 2; o > 0; o >>= 1) {
+    fx += __shfl_xor(fx, o, 64);
+    fy += __shfl_xor(fy, o, 64);
+    fz += __shfl_xor(fz, o, 64);
+    if (MODE & kModeEnergy) {
+      ep += __shfl_xor(ep, o, 64);
+      ee += __shfl_xor(ee, o, 64);
+    }
+  }
+  if (valid && l == 0) {
     if (!isfinite((double)fx) || !isfinite((double)fy) || !isfinite((double)fz))
       atomicOr(A.err, kErrNonFinite);
     if (MODE & (kModeFinal | kModeNext)) {
@@ -257,31 +336,102 @@ __global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, 
 }
 
 // ---------------------------------------------------------------------------
-// Host launchers.
-template <typename real>
-void launch_spin_phase(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
-                       hipStream_t st) {
-  const int cnt = A.end - A.begin;
-  if (cnt <= 0) return;
-  const int nb = (cnt + kBlock - 1) / kBlock;
+// Host launchers. The learned-potential variants (table lookups instead of
+// the analytic J and V) exist in the FP32 form only.
+template <typename real, int LANES, bool MLP>
+static void spin_phase_lanes2(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
+                              hipStream_t st) {
+  const long threads = (long)(A.end - A.begin) * LANES;
+  const int nb = (int)((threads + kBlock - 1) / kBlock);
   const bool lg = P.langevin != 0, an = P.aniso_on != 0;
-  if (lg && an) hipLaunchKernelGGL((k_spin_phase<real, true, true>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
-  else if (lg) hipLaunchKernelGGL((k_spin_phase<real, true, false>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
-  else if (an) hipLaunchKernelGGL((k_spin_phase<real, false, true>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
-  else hipLaunchKernelGGL((k_spin_phase<real, false, false>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  if (lg && an) hipLaunchKernelGGL((k_spin_phase<real, true, true, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  else if (lg) hipLaunchKernelGGL((k_spin_phase<real, true, false, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  else if (an) hipLaunchKernelGGL((k_spin_phase<real, false, true, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  else hipLaunchKernelGGL((k_spin_phase<real, false, false, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+}
+
+template <typename real, int LANES>
+static void spin_phase_lanes(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
+                             hipStream_t st) {
+  if (sizeof(real) == 4 && S.tab) spin_phase_lanes2<real, LANES, (sizeof(real) == 4)>(S, P, A, st);
+  else spin_phase_lanes2<real, LANES, false>(S, P, A, st);
 }
 
 template <typename real>
-void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, hipStream_t st) {
-  const int nb = (S.n + kBlock - 1) / kBlock;
-  if (nb <= 0) return;
+void launch_spin_phase(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
+                       int lanes, hipStream_t st) {
+  if (A.end - A.begin <= 0) return;
+  switch (lanes) {
+    case 1: spin_phase_lanes<real, 1>(S, P, A, st); break;
+    case 2: spin_phase_lanes<real, 2>(S, P, A, st); break;
+    case 8: spin_phase_lanes<real, 8>(S, P, A, st); break;
+    default: spin_phase_lanes<real, 4>(S, P, A, st); break;
+  }
+}
+
+template <typename real, int LANES, bool MLP>
+static void spin_tail_lanes2(const SysView<real> &S, const PotConst &P, const TailArgs &T,
+                             hipStream_t st) {
+  const bool lg = P.langevin != 0, an = P.aniso_on != 0;
+  if (lg && an) hipLaunchKernelGGL((k_spin_tail<real, true, true, LANES, MLP>), dim3(1), dim3(kTailBlock), 0, st, S, P, T);
+  else if (lg) hipLaunchKernelGGL((k_spin_tail<real, true, false, LANES, MLP>), dim3(1), dim3(kTailBlock), 0, st, S, P, T);
+  else if (an) hipLaunchKernelGGL((k_spin_tail<real, false, true, LANES, MLP>), dim3(1), dim3(kTailBlock), 0, st, S, P, T);
+  else hipLaunchKernelGGL((k_spin_tail<real, false, false, LANES, MLP>), dim3(1), dim3(kTailBlock), 0, st, S, P, T);
+}
+
+template <typename real, int LANES>
+static void spin_tail_lanes(const SysView<real> &S, const PotConst &P, const TailArgs &T,
+                            hipStream_t st) {
+  if (sizeof(real) == 4 && S.tab) spin_tail_lanes2<real, LANES, (sizeof(real) == 4)>(S, P, T, st);
+  else spin_tail_lanes2<real, LANES, false>(S, P, T, st);
+}
+
+template <typename real>
+void launch_spin_tail(const SysView<real> &S, const PotConst &P, const TailArgs &T, int lanes,
+                      hipStream_t st) {
+  if (T.nitems <= 0) return;
+  switch (lanes) {
+    case 1: spin_tail_lanes<real, 1>(S, P, T, st); break;
+    case 2: spin_tail_lanes<real, 2>(S, P, T, st); break;
+    case 8: spin_tail_lanes<real, 8>(S, P, T, st); break;
+    default: spin_tail_lanes<real, 4>(S, P, T, st); break;
+  }
+}
+
+template <typename real, int LANES, bool MLP>
+static void force_lanes2(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
+                         hipStream_t st) {
+  const long threads = (long)S.n * LANES;
+  const int nb = (int)((threads + kBlock - 1) / kBlock);
   switch (A.mode) {
 #define SL_FORCE_CASE(m) \
-  case m: hipLaunchKernelGGL((k_force<real, m>), dim3(nb), dim3(kBlock), 0, st, S, P, A); break;
+  case m: hipLaunchKernelGGL((k_force<real, m, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A); break;
     SL_FORCE_CASE(1) SL_FORCE_CASE(2) SL_FORCE_CASE(3) SL_FORCE_CASE(4)
     SL_FORCE_CASE(5) SL_FORCE_CASE(6) SL_FORCE_CASE(7)
 #undef SL_FORCE_CASE
     default: break;
+  }
+}
+
+template <typename real, int LANES>
+static void force_lanes(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
+                        hipStream_t st) {
+  if (sizeof(real) == 4 && S.tab) force_lanes2<real, LANES, (sizeof(real) == 4)>(S, P, A, st);
+  else force_lanes2<real, LANES, false>(S, P, A, st);
+}
+
+// Blocks needed by a force launch (rows of the partial-sum buffer).
+int force_blocks(int n, int lanes) { return (int)(((long)n * lanes + kBlock - 1) / kBlock); }
+
+template <typename real>
+void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
+                  hipStream_t st) {
+  if (S.n <= 0) return;
+  switch (lanes) {
+    case 1: force_lanes<real, 1>(S, P, A, st); break;
+    case 2: force_lanes<real, 2>(S, P, A, st); break;
+    case 8: force_lanes<real, 8>(S, P, A, st); break;
+    default: force_lanes<real, 4>(S, P, A, st); break;
   }
 }
 
@@ -290,12 +440,16 @@ void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st) 
 }
 
 template void launch_spin_phase<double>(const SysView<double> &, const PotConst &,
-                                        const SpinPhaseArgs &, hipStream_t);
+                                        const SpinPhaseArgs &, int, hipStream_t);
 template void launch_spin_phase<float>(const SysView<float> &, const PotConst &,
-                                       const SpinPhaseArgs &, hipStream_t);
+                                       const SpinPhaseArgs &, int, hipStream_t);
+template void launch_spin_tail<double>(const SysView<double> &, const PotConst &,
+                                       const TailArgs &, int, hipStream_t);
+template void launch_spin_tail<float>(const SysView<float> &, const PotConst &, const TailArgs &,
+                                      int, hipStream_t);
 template void launch_force<double>(const SysView<double> &, const PotConst &, const ForceArgs &,
-                                   hipStream_t);
-template void launch_force<float>(const SysView<float> &, const PotConst &, const ForceArgs &,
+                                   int, hipStream_t);
+template void launch_force<float>(const SysView<float> &, const PotConst &, const ForceArgs &, int,
                                   hipStream_t);
 
 }  // namespace sl

@@ -6,11 +6,17 @@
 namespace sl {
 
 // --- per-step kernels (sl_dyn.hip) ---
+// `lanes` (1, 2, 4 or 8) consecutive lanes cooperate on one atom.
 template <typename real>
 void launch_spin_phase(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
-                       hipStream_t st);
+                       int lanes, hipStream_t st);
 template <typename real>
-void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, hipStream_t st);
+void launch_spin_tail(const SysView<real> &S, const PotConst &P, const TailArgs &T, int lanes,
+                      hipStream_t st);
+template <typename real>
+void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
+                  hipStream_t st);
+int force_blocks(int n, int lanes);
 void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st);
 
 // --- rebuild kernels (sl_nbr.hip) ---

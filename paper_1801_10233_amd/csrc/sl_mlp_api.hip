@@ -1,0 +1,166 @@
+// sl_mlp_api.hip -- C ABI of the per-pair learned potential (sl_mlp_*).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/spinlat.h"
+#include "sl_mlp_host.h"
+
+using namespace sl;
+
+namespace {
+
+thread_local std::string g_mlp_err;
+
+int mfail(sl_mlp *m, int code, const std::string &msg) {
+  if (m) m->last_err = msg;
+  else g_mlp_err = msg;
+  return code;
+}
+
+#define MCHK(m, x)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) return mfail((m), SL_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int sl_mlp_create(const sl_mlp_spec *spec, sl_mlp **out) {
+  if (!out) return mfail(nullptr, SL_E_ARG, "out is NULL");
+  *out = nullptr;
+  sl_mlp *m = new sl_mlp();
+  if (spec) {
+    if (spec->sigma > 0) m->sigma = spec->sigma;
+    if (spec->mu_step > 0) m->mu_step = spec->mu_step;
+    if (spec->sJ != 0) m->sJ = spec->sJ;
+    if (spec->sP != 0) m->sP = spec->sP;
+    if (spec->ex_rc > 0) m->ex_rc = spec->ex_rc;
+    if (spec->rc > 0) m->rc = spec->rc;
+    m->st = (hipStream_t)spec->stream;
+  }
+  auto bail = [&](int code) {
+    g_mlp_err = m->last_err;
+    sl_mlp_destroy(m);
+    return code;
+  };
+  if (!m->st) {
+    if (hipStreamCreateWithFlags(&m->st, hipStreamNonBlocking) != hipSuccess) {
+      m->st = nullptr;
+      m->last_err = "hipStreamCreate failed";
+      return bail(SL_E_HIP);
+    }
+    m->own_stream = true;
+  }
+  if (hipMalloc((void **)&m->master, sizeof(float) * SL_MLP_NPARAM) != hipSuccess ||
+      hipMalloc((void **)&m->wt, sizeof(MlpDevWeightsT)) != hipSuccess ||
+      hipMalloc((void **)&m->grad, sizeof(float) * SL_MLP_NPARAM) != hipSuccess ||
+      hipMalloc((void **)&m->adam_m, sizeof(float) * SL_MLP_NPARAM) != hipSuccess ||
+      hipMalloc((void **)&m->adam_v, sizeof(float) * SL_MLP_NPARAM) != hipSuccess ||
+      hipMalloc((void **)&m->w, sizeof(MlpDevWeights)) != hipSuccess ||
+      hipMalloc((void **)&m->yc, sizeof(float) * 4) != hipSuccess ||
+      hipMalloc((void **)&m->scratch4, sizeof(float4) * 64) != hipSuccess) {
+    m->last_err = "device allocation failed";
+    return bail(SL_E_NOMEM);
+  }
+  *out = m;
+  return SL_OK;
+}
+
+int sl_mlp_destroy(sl_mlp *m) {
+  if (!m) return SL_OK;
+  if (m->st) (void)hipStreamSynchronize(m->st);
+  if (m->trainer) sl_destroy(m->trainer);
+  for (void *p : {(void *)m->master, (void *)m->w, (void *)m->yc, (void *)m->scratch4,
+                  (void *)m->wt, (void *)m->grad, (void *)m->adam_m, (void *)m->adam_v})
+    if (p) (void)hipFree(p);
+  if (m->own_stream && m->st) (void)hipStreamDestroy(m->st);
+  delete m;
+  return SL_OK;
+}
+
+}  // extern "C"
+
+// Refresh the BF16 operand copy and the shifted-force constants after the
+// FP32 master parameters changed (stream ordered).
+int mlp_refresh(sl_mlp *m) {
+  launch_mlp_swizzle(m->master, m->w, m->st);
+  launch_mlp_swizzle_t(m->master, m->wt, m->st);
+  // raw outputs at r = rc -> yc = (y1(rc), y1'(rc))
+  float rc = (float)m->rc;
+  float *d_r = (float *)(m->scratch4 + 32);
+  MCHK(m, hipMemcpyAsync(d_r, &rc, sizeof(float), hipMemcpyHostToDevice, m->st));
+  launch_mlp_eval(d_r, 1, m->w, m->cfg(), m->yc, 1, m->scratch4, m->st);
+  MCHK(m, hipMemcpyAsync(m->yc, (float *)m->scratch4 + 2, 2 * sizeof(float), hipMemcpyDeviceToDevice, m->st));
+  MCHK(m, hipStreamSynchronize(m->st));
+  m->have_weights = true;
+  return SL_OK;
+}
+
+extern "C" {
+
+int sl_mlp_set_weights(sl_mlp *m, const float *params, int n, int where) {
+  if (!m || !params) return mfail(m, SL_E_ARG, "NULL argument");
+  if (n != SL_MLP_NPARAM) return mfail(m, SL_E_ARG, "expected SL_MLP_NPARAM parameters");
+  if (where == SL_HOST) {
+    for (int k = 0; k < n; ++k)
+      if (!std::isfinite(params[k])) return mfail(m, SL_E_NONFINITE, "non-finite weight");
+  }
+  MCHK(m, hipMemcpyAsync(m->master, params, sizeof(float) * n,
+                         where == SL_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, m->st));
+  MCHK(m, hipMemsetAsync(m->adam_m, 0, sizeof(float) * n, m->st));
+  MCHK(m, hipMemsetAsync(m->adam_v, 0, sizeof(float) * n, m->st));
+  m->adam_t = 0;
+  return mlp_refresh(m);
+}
+
+int sl_mlp_get_weights(sl_mlp *m, float *params, int n, int where) {
+  if (!m || !params) return mfail(m, SL_E_ARG, "NULL argument");
+  if (n != SL_MLP_NPARAM) return mfail(m, SL_E_ARG, "expected SL_MLP_NPARAM parameters");
+  MCHK(m, hipMemcpyAsync(params, m->master, sizeof(float) * n,
+                         where == SL_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, m->st));
+  MCHK(m, hipStreamSynchronize(m->st));
+  return SL_OK;
+}
+
+int sl_mlp_eval(sl_mlp *m, const double *r, int64_t P, double *out, int where) {
+  if (!m || (P > 0 && (!r || !out))) return mfail(m, SL_E_ARG, "NULL argument");
+  if (!m->have_weights) return mfail(m, SL_E_STATE, "no weights set");
+  if (P <= 0) return SL_OK;
+  if (P > (1 << 28)) return mfail(m, SL_E_ARG, "too many distances");
+  std::vector<double> hr(P);
+  if (where == SL_DEVICE) MCHK(m, hipMemcpy(hr.data(), r, sizeof(double) * P, hipMemcpyDeviceToHost));
+  else std::memcpy(hr.data(), r, sizeof(double) * P);
+  std::vector<float> fr(P);
+  for (int64_t k = 0; k < P; ++k) fr[k] = (float)hr[k];
+  float *d_r = nullptr;
+  float4 *d_o = nullptr;
+  MCHK(m, hipMalloc((void **)&d_r, sizeof(float) * P));
+  MCHK(m, hipMalloc((void **)&d_o, sizeof(float4) * P));
+  MCHK(m, hipMemcpyAsync(d_r, fr.data(), sizeof(float) * P, hipMemcpyHostToDevice, m->st));
+  launch_mlp_eval(d_r, (int)P, m->w, m->cfg(), m->yc, 0, d_o, m->st);
+  std::vector<float4> ho(P);
+  MCHK(m, hipMemcpyAsync(ho.data(), d_o, sizeof(float4) * P, hipMemcpyDeviceToHost, m->st));
+  MCHK(m, hipStreamSynchronize(m->st));
+  (void)hipFree(d_r);
+  (void)hipFree(d_o);
+  std::vector<double> hout(4 * P);
+  for (int64_t k = 0; k < P; ++k) {
+    hout[4 * k] = ho[k].x;
+    hout[4 * k + 1] = ho[k].y;
+    hout[4 * k + 2] = ho[k].z;
+    hout[4 * k + 3] = ho[k].w;
+  }
+  if (where == SL_DEVICE) MCHK(m, hipMemcpy(out, hout.data(), sizeof(double) * 4 * P, hipMemcpyHostToDevice));
+  else std::memcpy(out, hout.data(), sizeof(double) * 4 * P);
+  return SL_OK;
+}
+
+const char *sl_mlp_last_error(const sl_mlp *m) { return m ? m->last_err.c_str() : g_mlp_err.c_str(); }
+
+}  // extern "C"

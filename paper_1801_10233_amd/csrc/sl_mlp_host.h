@@ -1,0 +1,36 @@
+// sl_mlp_host.h -- host-side state of an sl_mlp handle (internal).
+#pragma once
+
+#include <string>
+
+#include "sl_mlp.h"
+
+struct sl_mlp {
+  double sigma = 0.4, mu_step = 5.0 / 15.0, sJ = 0.01, sP = 1.0, ex_rc = 3.5, rc = 5.0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  float *master = nullptr;              // FP32 master parameters (device)
+  sl::MlpDevWeights *w = nullptr;       // BF16 operand copy (device)
+  float *yc = nullptr;                  // raw y1(rc), y1'(rc) (device)
+  float4 *scratch4 = nullptr;           // small staging
+  sl::MlpDevWeightsT *wt = nullptr;     // transposed layer-2 tiles (reverse pass)
+  float *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+  int64_t adam_t = 0;
+  struct sl_system *trainer = nullptr;  // geometry of the training snapshots
+  bool have_weights = false;
+  std::string last_err;
+  sl::MlpCfgDev cfg() const {
+    sl::MlpCfgDev c;
+    c.inv_sigma = (float)(1.0 / sigma);
+    c.mu_step = (float)mu_step;
+    c.sJ = (float)sJ;
+    c.sP = (float)sP;
+    c.ex_rc = (float)ex_rc;
+    c.rc = (float)rc;
+    return c;
+  }
+};
+
+// Refresh the BF16 copy and the shifted-force constants after the master
+// parameters changed.
+int mlp_refresh(sl_mlp *m);

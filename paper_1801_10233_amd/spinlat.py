@@ -37,8 +37,14 @@ EXPORTS = [
     "sl_set_neighbor", "sl_set_neighbor_list", "sl_get_neighbor_list",
     "sl_set_coloring", "sl_get_coloring", "sl_set_step", "sl_step",
     "sl_get_energy", "sl_get_magnetization", "sl_get_thermo", "sl_get_stats",
-    "sl_synchronize", "sl_set_profiling", "sl_get_profile", "sl_last_error",
+    "sl_synchronize", "sl_set_tuning", "sl_get_tuning", "sl_set_profiling",
+    "sl_get_profile", "sl_last_error",
+    "sl_mlp_create", "sl_mlp_destroy", "sl_mlp_set_weights", "sl_mlp_get_weights",
+    "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
+    "sl_mlp_loss_grad", "sl_mlp_train",
 ]
+
+SL_MLP_NPARAM = 5378
 
 
 class sl_params(C.Structure):
@@ -66,6 +72,32 @@ class sl_stats(C.Structure):
     _fields_ = [("step", C.c_int64), ("rebuilds", C.c_int64), ("n_colours", C.c_int),
                 ("jp_rounds", C.c_int), ("max_spin_nbr_seen", C.c_int),
                 ("max_nbr_seen", C.c_int)]
+
+
+class sl_tuning(C.Structure):
+    _fields_ = [("spin_lanes", C.c_int), ("force_lanes", C.c_int), ("small_class", C.c_int)]
+
+
+class sl_mlp_spec(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("mu_step", C.c_double), ("sJ", C.c_double),
+                ("sP", C.c_double), ("ex_rc", C.c_double), ("rc", C.c_double),
+                ("stream", C.c_void_p)]
+
+
+class sl_dataset(C.Structure):
+    _fields_ = [("n_snapshots", C.c_int), ("n_atoms", C.c_int64), ("box", C.c_double * 3),
+                ("r", C.c_void_p), ("s", C.c_void_p), ("E", C.c_void_p), ("F", C.c_void_p),
+                ("hw", C.c_void_p)]
+
+
+class sl_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("w_E", C.c_double),
+                ("w_F", C.c_double), ("w_W", C.c_double), ("seed", C.c_uint64)]
+
+
+class sl_train_log(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("updates", C.c_int64)]
 
 
 class SpinLatError(RuntimeError):
@@ -106,9 +138,22 @@ def lib():
                           C.c_int),
         "sl_get_stats": ([vp, C.POINTER(sl_stats)], C.c_int),
         "sl_synchronize": ([vp], C.c_int),
+        "sl_set_tuning": ([vp, C.POINTER(sl_tuning)], C.c_int),
+        "sl_get_tuning": ([vp, C.POINTER(sl_tuning)], C.c_int),
         "sl_set_profiling": ([vp, C.c_int], C.c_int),
         "sl_get_profile": ([vp, C.c_int, C.POINTER(C.c_int64), dp, dp], C.c_int),
         "sl_last_error": ([vp], C.c_char_p),
+        "sl_mlp_create": ([C.POINTER(sl_mlp_spec), C.POINTER(C.c_void_p)], C.c_int),
+        "sl_mlp_destroy": ([vp], C.c_int),
+        "sl_mlp_set_weights": ([vp, vp, C.c_int, C.c_int], C.c_int),
+        "sl_mlp_get_weights": ([vp, vp, C.c_int, C.c_int], C.c_int),
+        "sl_mlp_eval": ([vp, vp, C.c_int64, vp, C.c_int], C.c_int),
+        "sl_mlp_last_error": ([vp], C.c_char_p),
+        "sl_set_mlp": ([vp, vp], C.c_int),
+        "sl_get_fields": ([vp, vp, vp, C.c_int], C.c_int),
+        "sl_mlp_loss_grad": ([vp, C.POINTER(sl_dataset), C.c_int, dp, dp, vp], C.c_int),
+        "sl_mlp_train": ([vp, C.POINTER(sl_dataset), C.POINTER(sl_train_opts),
+                          C.POINTER(sl_train_log)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -281,6 +326,26 @@ class System:
     def synchronize(self):
         self._check(lib().sl_synchronize(self.h))
 
+    def set_tuning(self, spin_lanes=0, force_lanes=0, small_class=0):
+        t = sl_tuning(int(spin_lanes), int(force_lanes), int(small_class))
+        self._check(lib().sl_set_tuning(self.h, C.byref(t)))
+
+    def tuning(self):
+        t = sl_tuning()
+        self._check(lib().sl_get_tuning(self.h, C.byref(t)))
+        return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
+                    small_class=t.small_class)
+
+    def set_mlp(self, mlp):
+        self._mlp = mlp
+        self._check(lib().sl_set_mlp(self.h, mlp.h if mlp is not None else None))
+
+    def fields(self):
+        """(F[N,3], exchange hbar*omega[N,3]) of the current state."""
+        F = np.zeros((self.N, 3)); hw = np.zeros((self.N, 3))
+        self._check(lib().sl_get_fields(self.h, F.ctypes.data, hw.ctypes.data, SL_HOST))
+        return F, hw
+
     def set_profiling(self, on=True):
         self._check(lib().sl_set_profiling(self.h, int(bool(on))))
 
@@ -289,6 +354,76 @@ class System:
         self._check(lib().sl_get_profile(self.h, int(kind), C.byref(n), C.byref(ms),
                                          C.byref(w)))
         return n.value, ms.value, w.value
+
+
+class Mlp:
+    """Per-pair learned potential behind an sl_mlp handle."""
+
+    def __init__(self, sigma=0.0, mu_step=0.0, sJ=0.0, sP=0.0, ex_rc=0.0, rc=0.0, stream=None):
+        spec = sl_mlp_spec(sigma, mu_step, sJ, sP, ex_rc, rc, stream)
+        h = C.c_void_p()
+        rc_ = lib().sl_mlp_create(C.byref(spec), C.byref(h))
+        if rc_ != SL_OK:
+            raise SpinLatError(rc_, lib().sl_mlp_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sl_mlp_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, rc):
+        if rc < 0:
+            raise SpinLatError(rc, lib().sl_mlp_last_error(self.h).decode())
+        return rc
+
+    def set_weights(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(lib().sl_mlp_set_weights(self.h, p.ctypes.data, p.size, SL_HOST))
+
+    def weights(self):
+        p = np.zeros(SL_MLP_NPARAM, dtype=np.float32)
+        self._check(lib().sl_mlp_get_weights(self.h, p.ctypes.data, p.size, SL_HOST))
+        return p
+
+    def eval(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64).ravel()
+        out = np.zeros((r.size, 4))
+        self._check(lib().sl_mlp_eval(self.h, r.ctypes.data, r.size, out.ctypes.data, SL_HOST))
+        return out
+
+
+class Dataset:
+    """Snapshots (host arrays kept alive) for sl_mlp_loss_grad / sl_mlp_train."""
+
+    def __init__(self, box, r, s, E, F, hw):
+        self.r = np.ascontiguousarray(r, dtype=np.float64)
+        self.s = np.ascontiguousarray(s, dtype=np.float64)
+        self.E = np.ascontiguousarray(E, dtype=np.float64)
+        self.F = np.ascontiguousarray(F, dtype=np.float64)
+        self.hw = np.ascontiguousarray(hw, dtype=np.float64)
+        S, N = self.r.shape[0], self.r.shape[1]
+        self.c = sl_dataset(S, N, (C.c_double * 3)(*box), self.r.ctypes.data, self.s.ctypes.data,
+                            self.E.ctypes.data, self.F.ctypes.data, self.hw.ctypes.data)
+
+
+def mlp_loss_grad(mlp, ds, snapshot, w=(1.0, 1.0, 1.0)):
+    wv = (C.c_double * 3)(*w)
+    loss = C.c_double()
+    g = np.zeros(SL_MLP_NPARAM, dtype=np.float32)
+    mlp._check(lib().sl_mlp_loss_grad(mlp.h, C.byref(ds.c), int(snapshot), wv, C.byref(loss),
+                                      g.ctypes.data))
+    return loss.value, g
+
+
+def mlp_train(mlp, ds, epochs, lr=1e-3, w=(1.0, 1.0, 1.0), seed=0):
+    o = sl_train_opts(int(epochs), float(lr), 0.0, 0.0, 0.0, float(w[0]), float(w[1]),
+                      float(w[2]), int(seed))
+    log = sl_train_log()
+    mlp._check(lib().sl_mlp_train(mlp.h, C.byref(ds.c), C.byref(o), C.byref(log)))
+    return dict(loss_first=log.loss_first, loss_last=log.loss_last, updates=log.updates)
 
 
 def system_from_workload(w, precision=SL_FP64, thermo_every=0, **kw):

@@ -1,0 +1,142 @@
+"""BF16-MFMA MLP kernels vs the FP64 MLP oracle (outputs and tangents).
+
+BF16 operands with FP32 accumulation: outputs agree with the FP64 oracle
+to about 1e-2 of their scale."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+CFG = O.mlp_cfg()
+
+
+def params(seed, scale=0.3):
+    return np.random.default_rng(seed).standard_normal(5378) * scale
+
+
+def test_mlp_eval_matches_oracle():
+    from paper_1801_10233_amd import spinlat as sl
+    m = sl.Mlp()
+    p = params(1)
+    m.set_weights(p.astype(np.float32))
+    assert np.array_equal(m.weights(), p.astype(np.float32))
+    r = np.concatenate([np.linspace(1.8, 5.2, 997), [3.5, 5.0, 2.4825, 2.8665]])
+    g = m.eval(r)
+    o = O.mlp_eval(CFG, p.astype(np.float32).astype(np.float64), r)
+    for col, name in enumerate(["J", "dJ", "phi", "dphi"]):
+        scale = np.abs(o[:, col]).max()
+        err = np.abs(g[:, col] - o[:, col]).max()
+        print(name, "scale", scale, "max err", err, flush=True)
+        assert err <= 2.5e-2 * scale, name
+    # cut rules hold exactly
+    assert np.all(g[r >= 3.5, :2] == 0.0) and np.all(g[r >= 5.0, 2:] == 0.0)
+
+
+def test_mlp_tangent_is_derivative_of_value():
+    from paper_1801_10233_amd import spinlat as sl
+    m = sl.Mlp()
+    m.set_weights(params(2).astype(np.float32))
+    r = np.linspace(2.0, 4.9, 300)
+    g = m.eval(r)
+    # integrate the tangent and compare with the value (phi, smooth part)
+    dphi = g[:, 3]
+    integ = np.concatenate([[0], np.cumsum(0.5 * (dphi[1:] + dphi[:-1]) * np.diff(r))])
+    span = np.abs(g[:, 2] - g[0, 2]).max()
+    assert np.abs((g[:, 2] - g[0, 2]) - integ).max() < 3e-2 * max(span, 1e-3)
+
+
+def _small_weights(seed):
+    # a network of the size and output scale of a trained one
+    p = np.random.default_rng(seed).standard_normal(5378) * 0.15
+    return p.astype(np.float32).astype(np.float64)
+
+
+def test_mlp_dynamics_matches_fp64_mlp_oracle():
+    """FP32 form with the learned potential (BF16 MFMA table) against the
+    oracle driven by the same network in FP64."""
+    from paper_1801_10233_amd import spinlat as sl
+    from paper_1801_10233_amd import workloads as W
+    from tests.common import make_oracle
+    w = W.large_langevin(n=8, nve=True)
+    p = _small_weights(3)
+    m = sl.Mlp()
+    m.set_weights(p.astype(np.float32))
+    g = sl.system_from_workload(w, precision=sl.SL_FP32)
+    g.set_mlp(m)
+    o = make_oracle(w)
+    o.set_mlp(CFG, p)
+    eg, eo = g.energy(), o.energy()
+    print("E gpu", eg, "oracle", eo, flush=True)
+    for k in ("pair", "exchange"):
+        assert abs(eg[k] - eo[k]) <= 2e-2 * abs(eo[k]) + 1e-3 * w.N * 1e-3, k
+    g.step(20, w.dt)
+    o.step(20, w.dt)
+    rg, vg, sg = g.get_state()
+    ro, vo, so = o.get_state()
+    dr, dv, ds = np.abs(rg - ro).max(), np.abs(vg - vo).max(), np.abs(sg - so).max()
+    print("mlp dynamics diff: r", dr, "v", dv, "s", ds, "vmax", np.abs(vo).max(), flush=True)
+    assert dr < 1e-5 and ds < 2e-3 and dv < 2e-2 * np.abs(vo).max()
+
+
+def test_fields_match_oracle_forces_and_omega():
+    from paper_1801_10233_amd import spinlat as sl
+    from paper_1801_10233_amd import workloads as W
+    from tests.common import make_oracle
+    w = W.coupled_nve(n=6)
+    w.r = w.r + W.thermal_displacements(w.N, 0.08, 5)
+    g = sl.system_from_workload(w)
+    F, hw = g.fields()
+    o = make_oracle(w)
+    Fo = o.forces()
+    Wo = o.omega() * O.HBAR           # B = 0, K = 0: exchange part only
+    assert np.abs(F - Fo).max() <= 1e-11 * np.abs(Fo).max()
+    assert np.abs(hw - Wo).max() <= 1e-13
+
+
+def _dataset(n=4, S=3, seed=0):
+    from paper_1801_10233_amd import spinlat as sl
+    from paper_1801_10233_amd import workloads as W
+    rs, ss, Es, Fs, hws = [], [], [], [], []
+    for k in range(S):
+        w = W.coupled_nve(n=n, spin_seed=seed + 10 * k)
+        w.r = w.r + W.thermal_displacements(w.N, 0.1, seed + 10 * k + 1)
+        g = sl.system_from_workload(w)
+        F, hw = g.fields()
+        e = g.energy()
+        rs.append(w.r); ss.append(w.s); Es.append(e["pair"] + e["exchange"]); Fs.append(F)
+        hws.append(hw)
+    return w.box, np.array(rs), np.array(ss), np.array(Es), np.array(Fs), np.array(hws)
+
+
+def test_mlp_loss_gradient_matches_fp64_oracle():
+    from paper_1801_10233_amd import spinlat as sl
+    box, rs, ss, Es, Fs, hws = _dataset()
+    ds = sl.Dataset(box, rs, ss, Es, Fs, hws)
+    p = _small_weights(7)
+    m = sl.Mlp()
+    m.set_weights(p.astype(np.float32))
+    wts = (1.0, 0.5, 30.0)
+    loss_g, grad_g = sl.mlp_loss_grad(m, ds, 1, wts)
+    pi, pj = O.brute_pairs(rs[1], box, 5.0)
+    keep = pi < pj
+    loss_o, grad_o = O.mlp_loss_grad(CFG, p, box, rs[1], ss[1], pi[keep], pj[keep], Es[1],
+                                     Fs[1], hws[1], wts)
+    rel = np.linalg.norm(grad_g - grad_o) / np.linalg.norm(grad_o)
+    cos = grad_g @ grad_o / (np.linalg.norm(grad_g) * np.linalg.norm(grad_o))
+    print("loss gpu", loss_g, "oracle", loss_o, "grad rel err", rel, "cos", cos, flush=True)
+    assert abs(loss_g - loss_o) <= 3e-2 * loss_o
+    assert rel < 6e-2 and cos > 0.998
+
+
+def test_mlp_training_reduces_loss():
+    from paper_1801_10233_amd import spinlat as sl
+    box, rs, ss, Es, Fs, hws = _dataset(S=4, seed=3)
+    ds = sl.Dataset(box, rs, ss, Es, Fs, hws)
+    m = sl.Mlp()
+    m.set_weights(_small_weights(8).astype(np.float32))
+    log = sl.mlp_train(m, ds, epochs=25, lr=3e-3, w=(1.0, 1.0, 30.0), seed=1)
+    print("train", log, flush=True)
+    assert log["updates"] == 100
+    assert log["loss_last"] < 0.5 * log["loss_first"]
