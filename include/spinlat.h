@@ -290,6 +290,37 @@ typedef struct {
 /* Adam on the FP32 master parameters, one update per snapshot. */
 int sl_mlp_train(sl_mlp *m, const sl_dataset *d, const sl_train_opts *o, sl_train_log *log);
 
+/* ------------------------------------------------------------------------
+ * Batched replicas: R independent coupled systems (each with its own box,
+ * size, list, colouring, Philox key/replica index, bath temperature and
+ * field) advanced together. A step of every replica is the step of
+ * sl_step; the replicas run in one persistent kernel launch (replayed from
+ * a captured hipGraph), one workgroup per replica, which stops a replica
+ * before a step that needs a neighbour-list rebuild; the library rebuilds
+ * it and replays the launch until every replica has done n steps.
+ * Results per replica equal those of a single sl_system up to summation
+ * order. All replicas share one precision; frozen lattices are not batched.
+ */
+typedef struct sl_batch sl_batch;
+
+/* params[R], pots[R]: per-replica creation parameters and interactions
+ * (params[r].stream is ignored: the batch owns one stream). */
+int sl_batch_create(int R, const sl_params *params, const sl_potential *pots,
+                    sl_batch **out);
+int sl_batch_destroy(sl_batch *b);
+/* State of replica r (same contract as sl_set_state / sl_get_state). */
+int sl_batch_set_state(sl_batch *b, int r, const double *x, const double *v,
+                       const double *s, const double *mass, int where);
+int sl_batch_get_state(sl_batch *b, int r, double *x, double *v, double *s,
+                       int where);
+int sl_batch_get_energy(sl_batch *b, int r, sl_energy *out);
+/* n steps of length dt for every replica. */
+int sl_batch_step(sl_batch *b, int64_t n, double dt);
+/* Lanes per atom inside the persistent kernel (1, 2 or 4; speed only). */
+int sl_batch_set_lanes(sl_batch *b, int lanes);
+int sl_batch_get_stats(sl_batch *b, int64_t *launches, int64_t *rebuilds, int *lanes);
+const char *sl_batch_last_error(const sl_batch *b);
+
 /* Message of the last failed call on this handle (or of the last failed
  * sl_create when sys is NULL). Never NULL. */
 const char *sl_last_error(const sl_system *sys);

@@ -1667,3 +1667,267 @@ int sl_mlp_train(sl_mlp *m, const sl_dataset *d, const sl_train_opts *o, sl_trai
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Batched replicas.
+namespace {
+struct BatchRep {
+  double cur_dm = 0, cur_vm = 0, cur_dt = 0, prev_dm = 0, prev_vm = 0, prev_dt = 0;
+  int cur_rebuilt = 0, prev_rebuilt = 0, have_prev = 0;
+  bool valid = false;
+};
+}  // namespace
+
+struct sl_batch {
+  int R = 0, prec = SL_FP64;
+  std::vector<sl_system *> sys;
+  std::vector<BatchRep> rep;
+  hipStream_t st = nullptr;
+  void *d_desc = nullptr;
+  std::vector<char> h_desc;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_lanes = -1;
+  int lanes = 2;
+  int64_t launches = 0, rebuilds = 0;
+  std::string last_err;
+};
+
+namespace {
+
+thread_local std::string g_batch_err;
+
+int bfail(sl_batch *B, int code, const std::string &msg) {
+  if (B) B->last_err = msg;
+  else g_batch_err = msg;
+  return code;
+}
+
+#define BCHK(B, x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return bfail((B), SL_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define BSYS(B, r, x)                                                         \
+  do {                                                                       \
+    int rc_ = (x);                                                           \
+    if (rc_) return bfail((B), rc_, "replica " + std::to_string(r) + ": " + (B)->sys[r]->last_err); \
+  } while (0)
+
+template <typename real>
+int batch_launch(sl_batch *B) {
+  if (!B->exec || B->graph_lanes != B->lanes) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    BCHK(B, hipStreamBeginCapture(B->st, hipStreamCaptureModeThreadLocal));
+    launch_batch_run<real>((RepDesc<real> *)B->d_desc, B->R, B->lanes, B->st);
+    BCHK(B, hipStreamEndCapture(B->st, &B->graph));
+    BCHK(B, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    B->graph_lanes = B->lanes;
+  }
+  BCHK(B, hipGraphLaunch(B->exec, B->st));
+  B->launches++;
+  return SL_OK;
+}
+
+template <typename real>
+int batch_step(sl_batch *B, int64_t n, double dt) {
+  const int R = B->R;
+  std::vector<int64_t> k0(R);
+  // call start of every replica: rebuild decision, first kick and drift
+  for (int r = 0; r < R; ++r) {
+    sl_system *S = B->sys[r];
+    BSYS(B, r, ensure_ready(S));
+    BatchRep &q = B->rep[r];
+    if (!S->user_list && S->have_D && q.valid && q.have_prev) {
+      const double D = (q.prev_rebuilt ? 0.0 : q.prev_dm) + 2.0 * std::fabs(q.prev_dt) * q.prev_vm;
+      if (D >= S->skin / 2.0 - 0.01) {
+        BSYS(B, r, rebuild(S));
+        B->rebuilds++;
+      }
+    }
+    k0[r] = S->step;
+    BSYS(B, r, force_launch<real>(S, S->pos, kModeNext, dt, S->step));
+    double Dn;
+    BSYS(B, r, wait_predictor(S, S->step, &Dn));
+    const double *o = S->ring + 4 * (int)(S->step & 3);
+    q.prev_dm = q.cur_dm; q.prev_vm = q.cur_vm; q.prev_dt = q.cur_dt;
+    q.prev_rebuilt = q.cur_rebuilt; q.have_prev = q.valid ? 1 : 0;
+    q.cur_dm = o[0]; q.cur_vm = o[1]; q.cur_dt = dt; q.cur_rebuilt = 0;
+    q.valid = true;
+    S->have_D = true;
+  }
+  const size_t dsz = sizeof(RepDesc<real>);
+  for (;;) {
+    bool any = false;
+    for (int r = 0; r < R; ++r) {
+      sl_system *S = B->sys[r];
+      RepDesc<real> d;
+      std::memset(&d, 0, sizeof(d));
+      d.V[0] = view<real>(S, 0);
+      d.V[1] = view<real>(S, 1);
+      d.P = S->pc;
+      Atoms &A = S->a[S->cur];
+      d.F.ftm2v = 1.0 / kMvv2e;
+      d.F.mass = A.mass;
+      d.F.vx = A.vx; d.F.vy = A.vy; d.F.vz = A.vz;
+      d.F.bx = A.bx; d.F.by = A.by; d.F.bz = A.bz;
+      d.F.err = S->err;
+      if (S->K > kMaxClass) return bfail(B, SL_E_COLOR, "replica " + std::to_string(r) + " has too many colours");
+      d.K = S->K;
+      for (int c = 0; c <= S->K; ++c) d.off[c] = S->class_off[c];
+      d.pos = S->pos;
+      d.step = S->step;
+      d.target = k0[r] + n;
+      d.dt = dt;
+      d.h = dt / 4.0;
+      d.amp = noise_amp(S, dt / 4.0);
+      d.rs2 = S->pot.ex_rc * S->pot.ex_rc;
+      d.thr = S->skin / 2.0 - 0.01;
+      d.seed = S->prm.seed;
+      d.replica = S->prm.replica;
+      d.user_list = S->user_list ? 1 : 0;
+      const BatchRep &q = B->rep[r];
+      d.cur_dm = q.cur_dm; d.cur_vm = q.cur_vm; d.cur_dt = q.cur_dt; d.cur_rebuilt = q.cur_rebuilt;
+      d.prev_dm = q.prev_dm; d.prev_vm = q.prev_vm; d.prev_dt = q.prev_dt;
+      d.prev_rebuilt = q.prev_rebuilt; d.have_prev = q.have_prev;
+      std::memcpy(B->h_desc.data() + r * dsz, &d, dsz);
+      if (d.step < d.target) any = true;
+    }
+    if (!any) break;
+    BCHK(B, hipMemcpyAsync(B->d_desc, B->h_desc.data(), dsz * R, hipMemcpyHostToDevice, B->st));
+    CHK(batch_launch<real>(B));
+    BCHK(B, hipMemcpyAsync(B->h_desc.data(), B->d_desc, dsz * R, hipMemcpyDeviceToHost, B->st));
+    BCHK(B, hipStreamSynchronize(B->st));
+    for (int r = 0; r < R; ++r) {
+      sl_system *S = B->sys[r];
+      RepDesc<real> d;
+      std::memcpy(&d, B->h_desc.data() + r * dsz, dsz);
+      S->pos = d.pos;
+      S->step = d.step;
+      BatchRep &q = B->rep[r];
+      q.cur_dm = d.cur_dm; q.cur_vm = d.cur_vm; q.cur_dt = d.cur_dt; q.cur_rebuilt = d.cur_rebuilt;
+      q.prev_dm = d.prev_dm; q.prev_vm = d.prev_vm; q.prev_dt = d.prev_dt;
+      q.prev_rebuilt = d.prev_rebuilt; q.have_prev = d.have_prev;
+      if (d.stopped) {
+        BSYS(B, r, rebuild(S));
+        q.cur_rebuilt = 1;
+        B->rebuilds++;
+      }
+    }
+  }
+  for (int r = 0; r < R; ++r) BSYS(B, r, sl_synchronize(B->sys[r]));
+  return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sl_batch_create(int R, const sl_params *params, const sl_potential *pots, sl_batch **out) {
+  if (!out || R < 1 || !params || !pots) return bfail(nullptr, SL_E_ARG, "bad arguments");
+  *out = nullptr;
+  for (int r = 0; r < R; ++r) {
+    if (params[r].precision != params[0].precision)
+      return bfail(nullptr, SL_E_ARG, "all replicas must share one precision");
+    if (params[r].frozen) return bfail(nullptr, SL_E_ARG, "batched replicas are coupled systems");
+  }
+  sl_batch *B = new sl_batch();
+  B->R = R;
+  B->prec = params[0].precision;
+  auto bail = [&](int code) {
+    g_batch_err = B->last_err;
+    sl_batch_destroy(B);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&B->st, hipStreamNonBlocking) != hipSuccess) {
+    B->st = nullptr;
+    B->last_err = "hipStreamCreate failed";
+    return bail(SL_E_HIP);
+  }
+  B->sys.assign(R, nullptr);
+  B->rep.assign(R, BatchRep());
+  for (int r = 0; r < R; ++r) {
+    sl_params p = params[r];
+    p.stream = B->st;
+    int rc = sl_create(&p, &B->sys[r]);
+    if (rc) {
+      B->last_err = "replica " + std::to_string(r) + ": " + sl_last_error(nullptr);
+      return bail(rc);
+    }
+    rc = sl_set_potential(B->sys[r], &pots[r]);
+    if (rc) {
+      B->last_err = "replica " + std::to_string(r) + ": " + B->sys[r]->last_err;
+      return bail(rc);
+    }
+  }
+  const size_t dsz = B->prec == SL_FP64 ? sizeof(RepDesc<double>) : sizeof(RepDesc<float>);
+  B->h_desc.assign(dsz * R, 0);
+  if (hipMalloc(&B->d_desc, dsz * R) != hipSuccess) {
+    B->last_err = "descriptor allocation failed";
+    return bail(SL_E_NOMEM);
+  }
+  *out = B;
+  return SL_OK;
+}
+
+int sl_batch_destroy(sl_batch *B) {
+  if (!B) return SL_OK;
+  if (B->st) (void)hipStreamSynchronize(B->st);
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  for (auto *S : B->sys)
+    if (S) sl_destroy(S);
+  if (B->d_desc) (void)hipFree(B->d_desc);
+  if (B->st) (void)hipStreamDestroy(B->st);
+  delete B;
+  return SL_OK;
+}
+
+int sl_batch_set_state(sl_batch *B, int r, const double *x, const double *v, const double *s,
+                       const double *mass, int where) {
+  if (!B || r < 0 || r >= B->R) return bfail(B, SL_E_ARG, "bad replica");
+  BSYS(B, r, sl_set_state(B->sys[r], x, v, s, mass, where));
+  B->rep[r] = BatchRep();
+  return SL_OK;
+}
+
+int sl_batch_get_state(sl_batch *B, int r, double *x, double *v, double *s, int where) {
+  if (!B || r < 0 || r >= B->R) return bfail(B, SL_E_ARG, "bad replica");
+  BSYS(B, r, sl_get_state(B->sys[r], x, v, s, where));
+  return SL_OK;
+}
+
+int sl_batch_get_energy(sl_batch *B, int r, sl_energy *e) {
+  if (!B || r < 0 || r >= B->R) return bfail(B, SL_E_ARG, "bad replica");
+  BSYS(B, r, sl_get_energy(B->sys[r], e));
+  return SL_OK;
+}
+
+int sl_batch_step(sl_batch *B, int64_t n, double dt) {
+  if (!B) return bfail(B, SL_E_ARG, "NULL batch");
+  if (n < 0 || !std::isfinite(dt)) return bfail(B, SL_E_ARG, "bad step count or dt");
+  if (n == 0) return SL_OK;
+  return B->prec == SL_FP64 ? batch_step<double>(B, n, dt) : batch_step<float>(B, n, dt);
+}
+
+int sl_batch_set_lanes(sl_batch *B, int lanes) {
+  if (!B || !(lanes == 1 || lanes == 2 || lanes == 4)) return bfail(B, SL_E_ARG, "lanes must be 1, 2 or 4");
+  B->lanes = lanes;
+  return SL_OK;
+}
+
+int sl_batch_get_stats(sl_batch *B, int64_t *launches, int64_t *rebuilds, int *lanes) {
+  if (!B) return bfail(B, SL_E_ARG, "NULL batch");
+  if (launches) *launches = B->launches;
+  if (rebuilds) *rebuilds = B->rebuilds;
+  if (lanes) *lanes = B->lanes;
+  return SL_OK;
+}
+
+const char *sl_batch_last_error(const sl_batch *B) { return B ? B->last_err.c_str() : g_batch_err.c_str(); }
+
+}  // extern "C"

@@ -18,7 +18,10 @@ constexpr double kMuB = 5.7883818060e-5;       // eV/T
 constexpr double kMvv2e = 1.0364269652680506e-4;  // eV per amu A^2/ps^2
 
 constexpr int kMaxRep = 4;        // consecutive updates one spin launch can do
+constexpr int kSpinChunk = 4;     // neighbours per lane gathered together (spin phase)
+constexpr int kForceChunk = 8;    // neighbours per lane gathered together (force)
 constexpr int kBlock = 256;       // threads per block of the per-atom kernels
+constexpr int kBatchBlock = 512;  // threads of the workgroup that runs one replica
 
 // Sticky device error bits.
 enum : int { kErrNbrOverflow = 1, kErrNonFinite = 2, kErrColour = 4 };
@@ -101,6 +104,29 @@ struct ForceArgs {
 };
 
 enum : int { kModeFinal = 1, kModeNext = 2, kModeEnergy = 4 };
+
+// One replica of a batch, as seen by the persistent kernel.
+constexpr int kMaxClass = 32;
+template <typename real>
+struct RepDesc {
+  SysView<real> V[2];          // views with position buffer 0 / 1
+  PotConst P;
+  ForceArgs F;                 // mass, velocities, reference positions, error word
+  int K;
+  int off[kMaxClass + 1];      // class offsets
+  int pos;                     // buffer holding the positions of the current boundary
+  int64_t step, target;
+  double dt, h, amp, rs2, thr;
+  uint64_t seed;
+  uint32_t replica;
+  int user_list;
+  // rebuild predictor terms (max |r - r_build|, max |v|, dt of the step)
+  // of the current boundary and of the one before, and whether a rebuild
+  // happened at the current boundary after its terms were taken
+  double cur_dm, cur_vm, cur_dt, prev_dm, prev_vm, prev_dt;
+  int cur_rebuilt, prev_rebuilt, have_prev;
+  int stopped;                 // out: the step at `step` needs a rebuild first
+};
 
 // -------------------------------------------------------------------------
 // Block index -> work tile. Consecutive blocks are dispatched round robin

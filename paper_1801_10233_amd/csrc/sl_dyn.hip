@@ -31,34 +31,54 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
                                             bool valid, int l, int nrep, const int64_t *step,
                                             const int *sub, double hd, double ampd,
                                             uint64_t seed, uint32_t replica, double rs2) {
+  // The neighbour loop runs in chunks: the chunk's list entries are loaded
+  // first, then every position and spin of the chunk (no branch between
+  // them, so all loads are in flight together), then the arithmetic.
+  // Entries past the end of the row point at the atom itself and are
+  // masked out.
   real ax = 0, ay = 0, az = 0;
-  if (valid && MLP) {
-    // learned J(r_ij) from the per-entry table at these positions
+  if (valid) {
     const int ns = S.nspin[i];
     const int ld = S.ld;
-    for (int k = l; k < ns; k += LANES) {
-      const int j = S.nbr[(size_t)k * ld + i];
-      const real J = (real)S.tab[(size_t)k * ld + i].x;
-      ax += J * S.sx[j];
-      ay += J * S.sy[j];
-      az += J * S.sz[j];
-    }
-  } else if (valid) {
     const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
-    const int ns = S.nspin[i];
-    const int ld = S.ld;
-    for (int k = l; k < ns; k += LANES) {
-      const int j = S.nbr[(size_t)k * ld + i];
-      const double dx = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
-      const double dy = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
-      const double dz = min_image(riz - S.rz[j], S.L[2], S.invL[2]);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < rs2) {
-        const real u = (real)(r2 * P.eInvD2);
-        const real J = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
-        ax += J * S.sx[j];
-        ay += J * S.sy[j];
-        az += J * S.sz[j];
+    for (int base = l; base < ns; base += LANES * kSpinChunk) {
+      int jj[kSpinChunk];
+#pragma unroll
+      for (int c = 0; c < kSpinChunk; ++c) {
+        const int k = base + LANES * c;
+        jj[c] = k < ns ? S.nbr[(size_t)k * ld + i] : i;
+      }
+      real qx[kSpinChunk], qy[kSpinChunk], qz[kSpinChunk], J[kSpinChunk];
+      if (MLP) {
+#pragma unroll
+        for (int c = 0; c < kSpinChunk; ++c) {
+          const int k = base + LANES * c;
+          J[c] = k < ns ? (real)S.tab[(size_t)k * ld + i].x : (real)0;
+          qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
+        }
+      } else {
+        double px[kSpinChunk], py[kSpinChunk], pz[kSpinChunk];
+#pragma unroll
+        for (int c = 0; c < kSpinChunk; ++c) {
+          px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
+          qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
+        }
+#pragma unroll
+        for (int c = 0; c < kSpinChunk; ++c) {
+          const double dx = min_image(rix - px[c], S.L[0], S.invL[0]);
+          const double dy = min_image(riy - py[c], S.L[1], S.invL[1]);
+          const double dz = min_image(riz - pz[c], S.L[2], S.invL[2]);
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const real u = (real)(r2 * P.eInvD2);
+          const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+          J[c] = (base + LANES * c < ns && r2 < rs2) ? Jc : (real)0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kSpinChunk; ++c) {
+        ax += J[c] * qx[c];
+        ay += J[c] * qy[c];
+        az += J[c] * qz[c];
       }
     }
   }
@@ -156,18 +176,15 @@ __global__ __launch_bounds__(kTailBlock) void k_spin_tail(SysView<real> S, PotCo
 // Every launch with a kick also reduces max |r - r_build| and max |v| at
 // this boundary for the rebuild decision; the last block to finish hands
 // them, with the sticky error word, to pinned host memory.
+// Per-atom part of the force launch (shared with the batched persistent
+// kernel): force on atom i over its list row, split over LANES lanes, then on
+// the first lane the kicks, the drift into the other position buffer, the
+// energy terms e[8] = (kin, pair, exchange, Zeeman, aniso, Mx, My, Mz) and
+// the rebuild predictor terms |r - r_build| and |v|.
 template <typename real, int MODE, int LANES, bool MLP>
-__global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
-  __shared__ double red[kBlock / 64][8];
-  __shared__ double redm[kBlock / 64][2];
-  __shared__ int last;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int t = tile * kBlock + threadIdx.x;
-  const int l = t & (LANES - 1);
-  const int i = t / LANES;
-  const bool valid = i < S.n;
-  double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double dm = 0.0, vm = 0.0;
+__device__ __forceinline__ void force_atom(const SysView<real> &S, const PotConst &P,
+                                           const ForceArgs &A, int i, bool valid, int l,
+                                           double e[8], double &dm, double &vm) {
   real fx = 0, fy = 0, fz = 0;
   real ep = 0, ee = 0;
   double rix = 0, riy = 0, riz = 0;
@@ -175,50 +192,88 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, F
   if (valid) {
     rix = S.rx[i]; riy = S.ry[i]; riz = S.rz[i];
     six = S.sx[i]; siy = S.sy[i]; siz = S.sz[i];
-    const int na = S.nall[i];
+    const int ns = S.nspin[i], na = S.nall[i];
     const int ld = S.ld;
-    for (int k = l; k < na; k += LANES) {
-      const int j = S.nbr[(size_t)k * ld + i];
-      const double dxd = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
-      const double dyd = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
-      const double dzd = min_image(riz - S.rz[j], S.L[2], S.invL[2]);
-      const double r2d = dxd * dxd + dyd * dyd + dzd * dzd;
-      const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd;
-      const real r = (real)sqrt(r2d);
-      real c = 0;
-      if (MLP) {
-        // learned phi'(r), J'(r) (and phi, J for energies) from the table
-        const float4 t = S.tab[(size_t)k * ld + i];
-        const real sisj = six * S.sx[j] + siy * S.sy[j] + siz * S.sz[j];
-        c = -(real)t.w + (real)t.y * sisj;
-        if (MODE & kModeEnergy) {
-          ep += (real)0.5 * (real)t.z;
-          ee -= (real)0.5 * (real)t.x * sisj;
+    // Two segments of the row, each gathered in chunks (all loads of a
+    // chunk in flight together): the spin segment [0, ns) needs positions
+    // and spins, the rest [ns, na) lies beyond the exchange cutoff (its
+    // build-time distance exceeds ex_rc + skin, and no atom has moved more
+    // than skin/2) and needs positions only.
+    for (int seg = 0; seg < 2; ++seg) {
+      const int beg = seg == 0 ? 0 : ns, end = seg == 0 ? ns : na;
+      for (int base = beg + l; base < end; base += LANES * kForceChunk) {
+        int jj[kForceChunk];
+#pragma unroll
+        for (int c = 0; c < kForceChunk; ++c) {
+          const int k = base + LANES * c;
+          jj[c] = k < end ? S.nbr[(size_t)k * ld + i] : i;
         }
-      } else {
-      if (P.morse_on && r2d < P.mRc2) {
-        const real ex = exp(-(real)P.mA * (r - (real)P.mR0));
-        const real dM = -(real)2 * (real)P.mA * (real)P.mD * (ex * ex - ex);
-        c -= dM - (real)P.mdMc;
-        if (MODE & kModeEnergy)
-          ep += (real)0.5 * ((real)P.mD * (ex * ex - (real)2 * ex) - (real)P.mMc -
-                             (r - (real)P.mRc) * (real)P.mdMc);
+        double px[kForceChunk], py[kForceChunk], pz[kForceChunk];
+        real sij[kForceChunk];
+        float4 tt[kForceChunk];
+#pragma unroll
+        for (int c = 0; c < kForceChunk; ++c) {
+          px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
+        }
+        if (seg == 0) {
+#pragma unroll
+          for (int c = 0; c < kForceChunk; ++c)
+            sij[c] = six * S.sx[jj[c]] + siy * S.sy[jj[c]] + siz * S.sz[jj[c]];
+        } else {
+#pragma unroll
+          for (int c = 0; c < kForceChunk; ++c) sij[c] = 0;
+        }
+        if (MLP) {
+#pragma unroll
+          for (int c = 0; c < kForceChunk; ++c) {
+            const int k = base + LANES * c;
+            tt[c] = k < end ? S.tab[(size_t)k * ld + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < kForceChunk; ++c) {
+          const bool use = base + LANES * c < end;
+          const double dxd = min_image(rix - px[c], S.L[0], S.invL[0]);
+          const double dyd = min_image(riy - py[c], S.L[1], S.invL[1]);
+          const double dzd = min_image(riz - pz[c], S.L[2], S.invL[2]);
+          const double r2d = use ? dxd * dxd + dyd * dyd + dzd * dzd : 1.0;
+          const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd;
+          const real r = (real)sqrt(r2d);
+          real cc = 0;
+          if (MLP) {
+            // learned phi'(r), J'(r) (and phi, J for energies) from the table
+            cc = -(real)tt[c].w + (real)tt[c].y * sij[c];
+            if (MODE & kModeEnergy) {
+              ep += (real)0.5 * (real)tt[c].z;
+              ee -= (real)0.5 * (real)tt[c].x * sij[c];
+            }
+          } else {
+            if (P.morse_on && r2d < P.mRc2) {
+              const real ex = exp(-(real)P.mA * (r - (real)P.mR0));
+              const real dM = -(real)2 * (real)P.mA * (real)P.mD * (ex * ex - ex);
+              cc -= dM - (real)P.mdMc;
+              if (MODE & kModeEnergy)
+                ep += use ? (real)0.5 * ((real)P.mD * (ex * ex - (real)2 * ex) - (real)P.mMc -
+                                         (r - (real)P.mRc) * (real)P.mdMc)
+                          : (real)0;
+            }
+            if (seg == 0 && P.ex_on && r2d < P.eRc2) {
+              const real u = (real)(r2d * P.eInvD2);
+              const real eu = exp(-u);
+              const real dJ = (real)P.eA8InvD2 * r * eu *
+                              ((real)1 - ((real)1 + (real)2 * (real)P.eG) * u + (real)P.eG * u * u);
+              cc += dJ * sij[c];
+              if (MODE & kModeEnergy)
+                ee -= use ? (real)0.5 * (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * eu * sij[c]
+                          : (real)0;
+            }
+          }
+          const real cr = use ? cc / r : (real)0;
+          fx += cr * dx;
+          fy += cr * dy;
+          fz += cr * dz;
+        }
       }
-      if (P.ex_on && r2d < P.eRc2) {
-        const real u = (real)(r2d * P.eInvD2);
-        const real eu = exp(-u);
-        const real sisj = six * S.sx[j] + siy * S.sy[j] + siz * S.sz[j];
-        const real dJ = (real)P.eA8InvD2 * r * eu *
-                        ((real)1 - ((real)1 + (real)2 * (real)P.eG) * u + (real)P.eG * u * u);
-        c += dJ * sisj;
-        if (MODE & kModeEnergy)
-          ee -= (real)0.5 * (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * eu * sisj;
-      }
-      }
-      const real cr = c / r;
-      fx += cr * dx;
-      fy += cr * dy;
-      fz += cr * dz;
     }
   }
 #pragma unroll
@@ -269,6 +324,20 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, F
       e[5] = (double)six; e[6] = (double)siy; e[7] = (double)siz;
     }
   }
+}
+
+template <typename real, int MODE, int LANES, bool MLP>
+__global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
+  __shared__ double red[kBlock / 64][8];
+  __shared__ double redm[kBlock / 64][2];
+  __shared__ int last;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int t = tile * kBlock + threadIdx.x;
+  const int l = t & (LANES - 1);
+  const int i = t / LANES;
+  double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double dm = 0.0, vm = 0.0;
+  force_atom<real, MODE, LANES, MLP>(S, P, A, i, i < S.n, l, e, dm, vm);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (MODE & kModeEnergy) {
 #pragma unroll
@@ -315,6 +384,111 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, F
     A.host_out[3] = 1.0;  // written marker
   }
 }
+
+// ---------------------------------------------------------------------------
+// Batched replicas in one persistent launch: workgroup b owns replica b and
+// runs its steps one after another -- the colour classes of both spin
+// half-steps separated by workgroup barriers, then force, kicks and drift --
+// with the same per-step rebuild rule as the single-system path: before a
+// step (other than the first of a launch) the predictor of the boundary
+// before the previous one decides; if a rebuild is due the replica stops
+// and the host rebuilds it before the next launch. Replicas are
+// independent, so no two workgroups ever wait on each other.
+template <typename real, int LANES>
+__global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
+  __shared__ double redm[kBatchBlock / 64][2];
+  __shared__ double bcast[2];
+  RepDesc<real> &d = D[blockIdx.x];
+  const int t = threadIdx.x, l = t & (LANES - 1), per = kBatchBlock / LANES;
+  int pos = d.pos;
+  int64_t step = d.step;
+  const int64_t target = d.target;
+  double cdm = d.cur_dm, cvm = d.cur_vm, cdt = d.cur_dt;
+  double pdm = d.prev_dm, pvm = d.prev_vm, pdt = d.prev_dt;
+  int crb = d.cur_rebuilt, prb = d.prev_rebuilt, havep = d.have_prev;
+  int stopped = 0;
+  bool first = true;
+  const int K = d.K;
+  while (step < target) {
+    if (!first && !d.user_list && havep) {
+      const double Dp = (prb ? 0.0 : pdm) + 2.0 * fabs(pdt) * pvm;
+      if (Dp >= d.thr) { stopped = 1; break; }
+    }
+    first = false;
+    for (int half = 0; half < 2; ++half) {
+      const SysView<real> &V = d.V[half == 0 ? pos : 1 - pos];
+      const int subf = 2 * half;
+      for (int q = 0; q < 2 * K - 1; ++q) {
+        const int c = q < K ? q : 2 * K - 2 - q;
+        int64_t st[kMaxRep] = {step, step, step, step};
+        int sb[kMaxRep] = {subf, subf + 1, 0, 0};
+        int nrep = 1;
+        if (q == K - 1) nrep = 2;
+        else if (q > K - 1) sb[0] = subf + 1;
+        const int b0 = d.off[c], b1 = d.off[c + 1];
+        for (int base = b0; base < b1; base += per) {
+          const int i = base + t / LANES;
+          spin_update<real, true, true, LANES, false>(V, d.P, i, i < b1, l, nrep, st, sb, d.h, d.amp,
+                                                     d.seed, d.replica, d.rs2);
+        }
+        __syncthreads();
+      }
+    }
+    // force at the boundary after this step (positions 1 - pos); the drift
+    // of the next step goes to buffer pos
+    ForceArgs F = d.F;
+    F.dt = d.dt;
+    F.nx = d.V[pos].rx == nullptr ? nullptr : const_cast<double *>(d.V[pos].rx);
+    F.ny = const_cast<double *>(d.V[pos].ry);
+    F.nz = const_cast<double *>(d.V[pos].rz);
+    const SysView<real> &W = d.V[1 - pos];
+    const bool next = step + 1 < target;
+    double bdm = 0.0, bvm = 0.0;
+    for (int base = 0; base < W.n; base += per) {
+      const int i = base + t / LANES;
+      double e[8], dm = 0.0, vm = 0.0;
+      if (next) force_atom<real, kModeFinal | kModeNext, LANES, false>(W, d.P, F, i, i < W.n, l, e, dm, vm);
+      else force_atom<real, kModeFinal, LANES, false>(W, d.P, F, i, i < W.n, l, e, dm, vm);
+      bdm = fmax(bdm, dm);
+      bvm = fmax(bvm, vm);
+    }
+    bdm = wave_max(bdm);
+    bvm = wave_max(bvm);
+    if ((t & 63) == 0) { redm[t >> 6][0] = bdm; redm[t >> 6][1] = bvm; }
+    __syncthreads();
+    if (t == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < kBatchBlock / 64; ++w) { a = fmax(a, redm[w][0]); b = fmax(b, redm[w][1]); }
+      bcast[0] = a;
+      bcast[1] = b;
+    }
+    __syncthreads();
+    pdm = cdm; pvm = cvm; pdt = cdt; prb = crb; havep = 1;
+    cdm = bcast[0]; cvm = bcast[1]; cdt = d.dt; crb = 0;
+    pos = 1 - pos;
+    ++step;
+    __syncthreads();
+  }
+  if (t == 0) {
+    d.pos = pos;
+    d.step = step;
+    d.cur_dm = cdm; d.cur_vm = cvm; d.cur_dt = cdt; d.cur_rebuilt = crb;
+    d.prev_dm = pdm; d.prev_vm = pvm; d.prev_dt = pdt; d.prev_rebuilt = prb; d.have_prev = havep;
+    d.stopped = stopped;
+  }
+}
+
+template <typename real>
+void launch_batch_run(RepDesc<real> *D, int R, int lanes, hipStream_t st) {
+  if (R <= 0) return;
+  switch (lanes) {
+    case 1: hipLaunchKernelGGL((k_batch_run<real, 1>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
+    case 2: hipLaunchKernelGGL((k_batch_run<real, 2>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
+    default: hipLaunchKernelGGL((k_batch_run<real, 4>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
+  }
+}
+template void launch_batch_run<double>(RepDesc<double> *, int, int, hipStream_t);
+template void launch_batch_run<float>(RepDesc<float> *, int, int, hipStream_t);
 
 // Fixed-order sum of nb partial rows of 8 doubles (deterministic result).
 __global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, double *out) {

@@ -17,6 +17,8 @@ template <typename real>
 void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
                   hipStream_t st);
 int force_blocks(int n, int lanes);
+template <typename real>
+void launch_batch_run(RepDesc<real> *D, int R, int lanes, hipStream_t st);
 void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st);
 
 // --- rebuild kernels (sl_nbr.hip) ---

@@ -42,6 +42,9 @@ EXPORTS = [
     "sl_mlp_create", "sl_mlp_destroy", "sl_mlp_set_weights", "sl_mlp_get_weights",
     "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
     "sl_mlp_loss_grad", "sl_mlp_train",
+    "sl_batch_create", "sl_batch_destroy", "sl_batch_set_state", "sl_batch_get_state",
+    "sl_batch_get_energy", "sl_batch_step", "sl_batch_set_lanes", "sl_batch_get_stats",
+    "sl_batch_last_error",
 ]
 
 SL_MLP_NPARAM = 5378
@@ -154,6 +157,16 @@ def lib():
         "sl_mlp_loss_grad": ([vp, C.POINTER(sl_dataset), C.c_int, dp, dp, vp], C.c_int),
         "sl_mlp_train": ([vp, C.POINTER(sl_dataset), C.POINTER(sl_train_opts),
                           C.POINTER(sl_train_log)], C.c_int),
+        "sl_batch_create": ([C.c_int, C.POINTER(sl_params), C.POINTER(sl_potential),
+                             C.POINTER(C.c_void_p)], C.c_int),
+        "sl_batch_destroy": ([vp], C.c_int),
+        "sl_batch_set_state": ([vp, C.c_int, vp, vp, vp, vp, C.c_int], C.c_int),
+        "sl_batch_get_state": ([vp, C.c_int, vp, vp, vp, C.c_int], C.c_int),
+        "sl_batch_get_energy": ([vp, C.c_int, C.POINTER(sl_energy)], C.c_int),
+        "sl_batch_step": ([vp, i64, C.c_double], C.c_int),
+        "sl_batch_set_lanes": ([vp, C.c_int], C.c_int),
+        "sl_batch_get_stats": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), ip], C.c_int),
+        "sl_batch_last_error": ([vp], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -213,7 +226,10 @@ class System:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().sl_destroy(self.h)
+            try:
+                lib().sl_destroy(self.h)
+            except Exception:
+                pass
             self.h = None
 
     __del__ = close
@@ -369,7 +385,10 @@ class Mlp:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().sl_mlp_destroy(self.h)
+            try:
+                lib().sl_mlp_destroy(self.h)
+            except Exception:
+                pass
             self.h = None
 
     __del__ = close
@@ -424,6 +443,79 @@ def mlp_train(mlp, ds, epochs, lr=1e-3, w=(1.0, 1.0, 1.0), seed=0):
     log = sl_train_log()
     mlp._check(lib().sl_mlp_train(mlp.h, C.byref(ds.c), C.byref(o), C.byref(log)))
     return dict(loss_first=log.loss_first, loss_last=log.loss_last, updates=log.updates)
+
+
+class Batch:
+    """Batched replicas behind an sl_batch handle (one workload per replica)."""
+
+    def __init__(self, workloads, precision=SL_FP32, max_nbr=0):
+        R = len(workloads)
+        P = (sl_params * R)()
+        Q = (sl_potential * R)()
+        for k, w in enumerate(workloads):
+            p = P[k]
+            p.n_atoms = w.N
+            p.box = (C.c_double * 3)(*[float(x) for x in w.box])
+            p.precision = int(precision)
+            p.frozen = 0
+            p.skin = float(w.skin)
+            p.max_nbr = int(max_nbr)
+            p.seed = int(w.seed)
+            p.replica = int(w.replica)
+            Q[k] = make_potential(w.pot)
+        h = C.c_void_p()
+        rc = lib().sl_batch_create(R, P, Q, C.byref(h))
+        if rc != SL_OK:
+            raise SpinLatError(rc, lib().sl_batch_last_error(None).decode())
+        self.h = h
+        self.R = R
+        self.N = [w.N for w in workloads]
+        for k, w in enumerate(workloads):
+            self.set_state(k, w.r, w.v, w.s, w.mass)
+
+    def close(self):
+        if getattr(self, "h", None):
+            try:
+                lib().sl_batch_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, rc):
+        if rc < 0:
+            raise SpinLatError(rc, lib().sl_batch_last_error(self.h).decode())
+        return rc
+
+    def set_state(self, r, x, v, s, mass):
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (x, v, s, mass)]
+        self._check(lib().sl_batch_set_state(self.h, int(r), *[a.ctypes.data for a in arrs],
+                                             SL_HOST))
+
+    def get_state(self, r):
+        n = self.N[r]
+        x = np.empty((n, 3)); v = np.empty((n, 3)); s = np.empty((n, 3))
+        self._check(lib().sl_batch_get_state(self.h, int(r), x.ctypes.data, v.ctypes.data,
+                                             s.ctypes.data, SL_HOST))
+        return x, v, s
+
+    def energy(self, r):
+        e = sl_energy()
+        self._check(lib().sl_batch_get_energy(self.h, int(r), C.byref(e)))
+        return dict(kin=e.kin, pair=e.pair, exchange=e.exchange, zeeman=e.zeeman,
+                    aniso=e.aniso, total=e.total)
+
+    def step(self, n, dt):
+        self._check(lib().sl_batch_step(self.h, int(n), float(dt)))
+
+    def set_lanes(self, lanes):
+        self._check(lib().sl_batch_set_lanes(self.h, int(lanes)))
+
+    def stats(self):
+        a = C.c_int64(); b = C.c_int64(); c = C.c_int()
+        self._check(lib().sl_batch_get_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(launches=a.value, rebuilds=b.value, lanes=c.value)
 
 
 def system_from_workload(w, precision=SL_FP64, thermo_every=0, **kw):
