@@ -101,6 +101,19 @@ def cpu_baseline(w, budget_s=12.0):
                        f"serial FP64 C oracle ({(t2 - t0):.1f} s)")
 
 
+def copy_probe(mib):
+    """A plain copy kernel of known size: each launch reads and writes
+    exactly mib MiB, so the memory counters of its dispatches give the
+    scale from counter units to bytes."""
+    import torch
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_probe_bytes=mib * (1 << 20), launches=5)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +123,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32 form and drift")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this "
@@ -117,6 +133,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     prec = sl.SL_FP64 if args.precision == "fp64" else sl.SL_FP32
     w = W.large_langevin(n=args.n)

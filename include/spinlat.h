@@ -185,7 +185,8 @@ int sl_synchronize(sl_system *sys);
 
 /* Launch shape of the per-step kernels. Changes speed only: the results
  * differ at most by summation-order roundoff. lanes = 1, 2, 4 or 8
- * consecutive wavefront lanes cooperate on one atom (0 = default 4).
+ * consecutive wavefront lanes cooperate on one atom (0 = default: 2 for
+ * the spin phase, 1 for forces).
  * Runs of consecutive colour classes of at most small_class atoms each are
  * applied by one single-workgroup launch (0 = default 512, -1 = never). */
 typedef struct {

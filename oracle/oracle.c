@@ -48,6 +48,7 @@ struct orc_sys {
     int *colour;
     int K;
     int have_colour;
+    int kbase;                   /* colours of the last full colouring */
 
     /* forces at the current positions and spins */
     double *F;
@@ -534,9 +535,11 @@ long orc_brute_pairs(int N, const double L[3], const double *r, double rcut,
  * first-fit greedy in ascending lexicographic key (z, y, x) of the wrapped
  * position at colouring time, ties broken by atom id. At later rebuilds a
  * colouring is kept where valid: for every edge whose ends share a colour,
- * the end with the later key is uncoloured, and the uncoloured atoms are
- * recoloured first-fit in ascending key order. More than 32 colours
- * triggers a full recolouring.
+ * the end with the later key is uncoloured; so is every atom whose colour
+ * lies outside the palette of the last full colouring (an atom moved there
+ * by an earlier repair goes back as soon as its conflict is gone). The
+ * uncoloured atoms are recoloured first-fit in ascending key order. More
+ * than 32 colours triggers a full recolouring.
  * ---------------------------------------------------------------------- */
 typedef struct { double z, y, x; int id; } key_t_;
 
@@ -575,10 +578,13 @@ static int first_free(const orc_sys *S, int i)
 static void colour_greedy(orc_sys *S, const key_t_ *sorted)
 {
     for (int i = 0; i < S->N; ++i) S->colour[i] = -1;
+    int K = 0;
     for (int t = 0; t < S->N; ++t) {
         int i = sorted[t].id;
         S->colour[i] = first_free(S, i);
+        if (S->colour[i] + 1 > K) K = S->colour[i] + 1;
     }
+    S->kbase = K;
 }
 
 static void colour_update(orc_sys *S)
@@ -593,12 +599,14 @@ static void colour_update(orc_sys *S)
         colour_greedy(S, sorted);
     } else {
         int *drop = (int *)calloc((size_t)(N > 0 ? N : 1), sizeof(int));
-        for (int i = 0; i < N; ++i)
+        for (int i = 0; i < N; ++i) {
+            if (S->colour[i] >= S->kbase) drop[i] = 1;
             for (int k = S->off[i]; k < S->off[i] + S->nspin[i]; ++k) {
                 int j = S->idx[k];
                 if (S->colour[j] == S->colour[i] && key_cmp(&keys[j], &keys[i]) < 0)
                     drop[i] = 1;
             }
+        }
         for (int i = 0; i < N; ++i)
             if (drop[i]) S->colour[i] = -1;
         for (int t = 0; t < N; ++t) {
@@ -626,6 +634,7 @@ int orc_set_coloring(orc_sys *S, const int *colour)
     }
     memcpy(S->colour, colour, (size_t)S->N * sizeof(int));
     S->K = K;
+    S->kbase = K;
     S->have_colour = 1;
     return 0;
 }

@@ -58,7 +58,8 @@ struct sl_system {
   double L[3] = {0, 0, 0}, invL[3] = {0, 0, 0};
   double skin = 0.3;
   int max_nbr = 80, max_spin = 32;
-  int spin_lanes = 4, force_lanes = 4;  // lanes per atom (tuning only)
+  int Kbase = 0;                        // palette of the last full colouring
+  int spin_lanes = 2, force_lanes = 1;  // lanes per atom (tuning only)
   int small_class = 512;                // fused small-class threshold (-1: off)
   hipStream_t st = nullptr;
   bool own_stream = false;
@@ -141,7 +142,9 @@ template <typename T>
 hipError_t dalloc(T **p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  return hipMalloc((void **)p, count * sizeof(T));
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e == hipSuccess) e = hipMemset(*p, 0, count * sizeof(T));
+  return e;
 }
 
 void dfree(void *p) {
@@ -207,6 +210,7 @@ SysView<real> view(sl_system *S, int posbuf) {
   SysView<real> v;
   v.n = S->n;
   v.ld = S->ld;
+  v.kcap = S->max_nbr;
   for (int d = 0; d < 3; ++d) {
     v.L[d] = S->L[d];
     v.invL[d] = S->invL[d];
@@ -403,6 +407,7 @@ ColourArgs colour_args(sl_system *S) {
   C.ky = S->ky;
   C.kz = S->kz;
   C.colour = A.colour;
+  C.kbase = S->Kbase;
   return C;
 }
 
@@ -484,6 +489,9 @@ int colour_and_permute(sl_system *S, bool repair) {
     launch_keys(n, A.rx[S->pos], A.ry[S->pos], A.rz[S->pos], S->L, S->kx, S->ky, S->kz, S->st);
   }
   ColourArgs C = colour_args(S);
+  // the palette of a full colouring (or of a colouring the caller set) is
+  // the base one; a repair drops atoms outside it so they can move back
+  bool set_base = !(repair && S->have_colour);
   if (!S->have_colour) {
     launch_colour_fill(n, C.colour, -1, S->st);
   } else if (repair) {
@@ -501,8 +509,10 @@ int colour_and_permute(sl_system *S, bool repair) {
     if (mc + 1 <= 32 || attempt == 1) break;
     launch_colour_fill(n, C.colour, -1, S->st);  // too many colours: start over
     CHK(jp_rounds(S, C));
+    set_base = true;
   }
   S->K = n > 0 ? mc + 1 : 0;
+  if (set_base) S->Kbase = S->K;
   S->have_colour = true;
 
   // permutation: counting sort by colour * ncell + cell, buckets in old order
@@ -1388,8 +1398,8 @@ int sl_set_tuning(sl_system *S, const sl_tuning *t) {
   if (!ok(t->spin_lanes) || !ok(t->force_lanes)) return fail(S, SL_E_ARG, "lanes must be 1, 2, 4 or 8");
   if (t->small_class < -1) return fail(S, SL_E_ARG, "small_class must be >= -1");
   CHK(sl_synchronize(S));
-  S->spin_lanes = t->spin_lanes ? t->spin_lanes : 4;
-  S->force_lanes = t->force_lanes ? t->force_lanes : 4;
+  S->spin_lanes = t->spin_lanes ? t->spin_lanes : 2;
+  S->force_lanes = t->force_lanes ? t->force_lanes : 1;
   S->small_class = t->small_class == 0 ? 512 : t->small_class;
   return SL_OK;
 }

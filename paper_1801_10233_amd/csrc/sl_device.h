@@ -19,7 +19,14 @@ constexpr double kMvv2e = 1.0364269652680506e-4;  // eV per amu A^2/ps^2
 
 constexpr int kMaxRep = 4;        // consecutive updates one spin launch can do
 constexpr int kSpinChunk = 4;     // neighbours per lane gathered together (spin phase)
-constexpr int kForceChunk = 8;    // neighbours per lane gathered together (force)
+#ifndef SL_FORCE_CHUNK
+#define SL_FORCE_CHUNK 8
+#endif
+constexpr int kForceChunk = SL_FORCE_CHUNK;  // neighbours per lane gathered together (force)
+#ifndef SL_FORCE_WAVES
+#define SL_FORCE_WAVES 1
+#endif
+constexpr int kForceWaves = SL_FORCE_WAVES;  // minimum waves per SIMD asked of the force kernel
 constexpr int kBlock = 256;       // threads per block of the per-atom kernels
 constexpr int kBatchBlock = 512;  // threads of the workgroup that runs one replica
 
@@ -48,6 +55,7 @@ template <typename real>
 struct SysView {
   int n;          // atoms
   int ld;         // leading dimension of the ELL lists (>= n, padded)
+  int kcap;       // slots per ELL row (list capacity)
   double L[3], invL[3];
   const double *rx, *ry, *rz;  // positions used by this launch
   real *sx, *sy, *sz;          // spins
@@ -72,7 +80,7 @@ struct SpinPhaseArgs {
 
 // Fused run of small colour classes (one workgroup).
 constexpr int kMaxTail = 16;
-constexpr int kTailBlock = 1024;
+constexpr int kTailBlock = 512;   // 2 waves per SIMD: room for 256 VGPRs, no spills
 struct TailItem {
   int begin, end, nrep;
   int64_t step[kMaxRep];
@@ -142,6 +150,18 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 __device__ __forceinline__ double min_image(double d, double L, double invL) {
   return d - L * rint(d * invL);
+}
+
+// 1/sqrt(x), x > 0, to about one ulp in FP64: the hardware estimate
+// (relative error near 2^-23) refined by two Newton steps
+// y <- y + (y/2)(1 - x y^2), each of which squares the relative error.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  return y;
 }
 
 // -------------------------------------------------------------------------

@@ -26,56 +26,77 @@ namespace sl {
 // One spin update (or nrep successive ones) of atom i, shared by the
 // per-class launch and the fused small-class launch. All LANES lanes of an
 // atom must call it (cross-lane shuffles); `valid` masks the tail.
+// Neighbour slots one lane gathers per round of the spin phase: with one or
+// two lanes per atom the first round covers 16 list slots (the whole spin
+// segment of bcc at the exchange cutoff, 14 entries) in one go.
+template <int LANES>
+struct SpinChunk {
+  static constexpr int value = LANES >= 8 ? 2 : (LANES >= 4 ? 4 : 8);
+};
+
 template <typename real, bool LANGEVIN, bool ANISO, int LANES, bool MLP>
 __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotConst &P, int i,
                                             bool valid, int l, int nrep, const int64_t *step,
                                             const int *sub, double hd, double ampd,
                                             uint64_t seed, uint32_t replica, double rs2) {
-  // The neighbour loop runs in chunks: the chunk's list entries are loaded
-  // first, then every position and spin of the chunk (no branch between
-  // them, so all loads are in flight together), then the arithmetic.
-  // Entries past the end of the row point at the atom itself and are
-  // masked out.
+  // Latency is what bounds this update, so every load that does not depend
+  // on another is issued at once: the row length, the own position, spin
+  // and id, and the list entries of the first round (taken unconditionally
+  // up to the list capacity; a slot past the row end is masked afterwards,
+  // and any index outside [0, n) is replaced by i before it is used). The
+  // gathers of positions and spins follow in one batch, and the Philox
+  // noise of the first update is computed while they are in flight.
+  constexpr int CH = SpinChunk<LANES>::value;
   real ax = 0, ay = 0, az = 0;
+  real sx = 0, sy = 0, sz = 0;
+  real g0[3] = {0, 0, 0};
+  uint32_t aid = 0;
   if (valid) {
-    const int ns = S.nspin[i];
     const int ld = S.ld;
+    const int ns = S.nspin[i];
     const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
-    for (int base = l; base < ns; base += LANES * kSpinChunk) {
-      int jj[kSpinChunk];
+    sx = S.sx[i]; sy = S.sy[i]; sz = S.sz[i];
+    if (LANGEVIN) aid = (uint32_t)S.id[i];
+    for (int base = l, round = 0; round == 0 || base < ns; base += LANES * CH, ++round) {
+      int jj[CH];
 #pragma unroll
-      for (int c = 0; c < kSpinChunk; ++c) {
+      for (int c = 0; c < CH; ++c) {
         const int k = base + LANES * c;
-        jj[c] = k < ns ? S.nbr[(size_t)k * ld + i] : i;
+        const int j = k < S.kcap ? S.nbr[(size_t)k * ld + i] : i;
+        jj[c] = (unsigned)j < (unsigned)S.n ? j : i;
       }
-      real qx[kSpinChunk], qy[kSpinChunk], qz[kSpinChunk], J[kSpinChunk];
-      if (MLP) {
+      real qx[CH], qy[CH], qz[CH], J[CH];
+      double px[CH], py[CH], pz[CH];
+      float jt[CH];
 #pragma unroll
-        for (int c = 0; c < kSpinChunk; ++c) {
+      for (int c = 0; c < CH; ++c) {
+        if (MLP) {
           const int k = base + LANES * c;
-          J[c] = k < ns ? (real)S.tab[(size_t)k * ld + i].x : (real)0;
-          qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
-        }
-      } else {
-        double px[kSpinChunk], py[kSpinChunk], pz[kSpinChunk];
-#pragma unroll
-        for (int c = 0; c < kSpinChunk; ++c) {
+          jt[c] = k < S.kcap ? S.tab[(size_t)k * ld + i].x : 0.f;
+        } else {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
-          qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
         }
+        qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
+      }
+      if (LANGEVIN && round == 0 && l == 0)
+        gauss3(seed, aid, step[0], replica, sub[0], g0);
 #pragma unroll
-        for (int c = 0; c < kSpinChunk; ++c) {
+      for (int c = 0; c < CH; ++c) {
+        const bool in = base + LANES * c < ns;
+        if (MLP) {
+          J[c] = in ? (real)jt[c] : (real)0;
+        } else {
           const double dx = min_image(rix - px[c], S.L[0], S.invL[0]);
           const double dy = min_image(riy - py[c], S.L[1], S.invL[1]);
           const double dz = min_image(riz - pz[c], S.L[2], S.invL[2]);
           const double r2 = dx * dx + dy * dy + dz * dz;
           const real u = (real)(r2 * P.eInvD2);
           const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
-          J[c] = (base + LANES * c < ns && r2 < rs2) ? Jc : (real)0;
+          J[c] = (in && r2 < rs2) ? Jc : (real)0;
         }
       }
 #pragma unroll
-      for (int c = 0; c < kSpinChunk; ++c) {
+      for (int c = 0; c < CH; ++c) {
         ax += J[c] * qx[c];
         ay += J[c] * qy[c];
         az += J[c] * qz[c];
@@ -89,7 +110,6 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
     az += __shfl_xor(az, o, 64);
   }
   if (!valid || l != 0) return;
-  real sx = S.sx[i], sy = S.sy[i], sz = S.sz[i];
   const real h = (real)hd;
   const real ih = (real)(1.0 / kHbar);
   for (int rep = 0; rep < nrep; ++rep) {
@@ -102,8 +122,8 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
     }
     real wx = ex * ih, wy = ey * ih, wz = ez * ih;
     if (LANGEVIN) {
-      real g[3];
-      gauss3(seed, (uint32_t)S.id[i], step[rep], replica, sub[rep], g);
+      real g[3] = {g0[0], g0[1], g0[2]};
+      if (rep > 0) gauss3(seed, aid, step[rep], replica, sub[rep], g);
       const real lam = (real)P.lam, amp = (real)ampd, f = (real)P.lamfac;
       const real cx = sy * wz - sz * wy, cy = sz * wx - sx * wz, cz = sx * wy - sy * wx;
       wx = (wx + amp * g[0] + lam * cx) * f;
@@ -238,7 +258,8 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           const double dzd = min_image(riz - pz[c], S.L[2], S.invL[2]);
           const double r2d = use ? dxd * dxd + dyd * dyd + dzd * dzd : 1.0;
           const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd;
-          const real r = (real)sqrt(r2d);
+          const double rinvd = rsqrt_nr(r2d);
+          const real r = (real)(r2d * rinvd), rinv = (real)rinvd;
           real cc = 0;
           if (MLP) {
             // learned phi'(r), J'(r) (and phi, J for energies) from the table
@@ -268,7 +289,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
                           : (real)0;
             }
           }
-          const real cr = use ? cc / r : (real)0;
+          const real cr = use ? cc * rinv : (real)0;
           fx += cr * dx;
           fy += cr * dy;
           fz += cr * dz;
@@ -327,11 +348,15 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
 }
 
 template <typename real, int MODE, int LANES, bool MLP>
-__global__ __launch_bounds__(kBlock) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
+__global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
   __shared__ double red[kBlock / 64][8];
   __shared__ double redm[kBlock / 64][2];
   __shared__ int last;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  // Tiles are taken from the end of the atom order first: the last colour
+  // classes may hold a few atoms scattered over the whole box (repairs),
+  // whose gathers miss the caches; starting them first hides their latency
+  // behind the bulk instead of leaving them as the tail of the launch.
+  const int tile = gridDim.x - 1 - xcd_tile(blockIdx.x, gridDim.x);
   const int t = tile * kBlock + threadIdx.x;
   const int l = t & (LANES - 1);
   const int i = t / LANES;

@@ -60,9 +60,11 @@ struct ColourArgs {
   const int *nbr, *nspin, *id;
   const double *kx, *ky, *kz;
   int *colour;
+  int kbase;  // colours >= kbase are dropped by a repair
 };
 void launch_colour_fill(int n, int *colour, int value, hipStream_t st);
-// Uncolour every atom that shares its colour with an earlier-key neighbour.
+// Uncolour every atom that shares its colour with an earlier-key neighbour,
+// and every atom whose colour lies outside the base palette.
 void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st);
 // One Jones-Plassmann round with key priority, first-fit colour choice.
 void launch_colour_round(const ColourArgs &A, int *remaining, int *reset_next, hipStream_t st);

@@ -158,7 +158,7 @@ __global__ void k_colour_mark(ColourArgs A, int *out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
   const int c = A.colour[i];
-  bool drop = false;
+  bool drop = c >= A.kbase;
   for (int k = 0; k < A.nspin[i]; ++k) {
     const int j = A.nbr[(size_t)k * A.ld + i];
     if (A.colour[j] == c && key_less(A, j, i)) drop = true;

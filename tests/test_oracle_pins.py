@@ -473,11 +473,12 @@ def test_colouring_valid_and_greedy():
             assert K == (4 if n % 2 == 0 else 9)
 
 
-def _py_repair(r, box, rows, ns, old):
+def _py_repair(r, box, rows, ns, old, kbase):
     w = r - box * np.floor(r / box)
     key = {i: (w[i, 2], w[i, 1], w[i, 0], i) for i in range(len(r))}
     col = list(old)
-    drop = [any(old[j] == old[i] and key[j] < key[i] for j in rows[i][:ns[i]])
+    drop = [old[i] >= kbase or
+            any(old[j] == old[i] and key[j] < key[i] for j in rows[i][:ns[i]])
             for i in range(len(r))]
     for i in range(len(r)):
         if drop[i]:
@@ -512,9 +513,45 @@ def test_colouring_repair_keeps_valid_and_local():
     ns, _, rows = o.neighbor_list()
     for i in range(N):
         assert np.all(c1[rows[i][:ns[i]]] != c1[i])
-    assert np.array_equal(c1, _py_repair(r2, box, rows, ns, c0))
+    assert np.array_equal(c1, _py_repair(r2, box, rows, ns, c0, K0))
     changed = np.nonzero(c1 != c0)[0]
     assert 0 < len(changed) <= 12
     d = r2[changed] - r2[0]
     d -= box * np.round(d / box)
     assert np.linalg.norm(d, axis=1).max() < 8.0     # repair stays local
+
+
+def test_colouring_repair_rule_through_dynamics():
+    # A hot lattice makes conflicts (third-shell pairs entering the spin
+    # radius) appear and vanish. At every rebuild the kept colouring must be
+    # exactly what the rule gives written out, with the palette of the first
+    # full colouring (4 colours) as the base: overflow colours appear and are
+    # emptied again once their conflicts are gone.
+    n = 6
+    r, box = W.bcc_lattice(n)
+    N = r.shape[0]
+    p = dict(W.EXCHANGE_BJ, **W.MORSE_BJ)
+    mass = np.full(N, 55.845)
+    v = W.maxwell_velocities(mass, 3000.0, 17)
+    o = O.Oracle(r, v, W.random_unit_spins(N, 1), mass, box, p, frozen=False, skin=0.3)
+    o.build()
+    c_prev, K0 = o.coloring()
+    assert K0 == 4
+    r_prev = o.get_state()[0]
+    nreb = o.num_rebuilds
+    seen_overflow = seen_return = checked = 0
+    for _ in range(400):
+        o.step(1, 1e-3)
+        if o.num_rebuilds != nreb:
+            nreb = o.num_rebuilds
+            c, K = o.coloring()
+            ns, _, rows = o.neighbor_list()
+            assert np.array_equal(c, _py_repair(r_prev, box, rows, ns, c_prev, K0))
+            checked += 1
+            if c.max() >= K0:
+                seen_overflow += 1
+            if np.any((c_prev >= K0) & (c < K0)):
+                seen_return += 1
+            c_prev = c
+        r_prev = o.get_state()[0]
+    assert checked >= 5 and seen_overflow >= 1 and seen_return >= 1, (checked, seen_overflow, seen_return)
