@@ -136,10 +136,19 @@ int sl_set_potential(sl_system *sys, const sl_potential *pot);
 /* Device cell-list neighbour build with Verlet skin `skin` and row capacity
  * max_nbr (0 keeps the current values). Rows hold every j closer than
  * max(cutoffs) + skin, the entries closer than ex_rc + skin first (the
- * spin segment, which is also the graph the colouring must respect).
- * Rebuild rule: before step k the list is rebuilt when
- * max_i |r_i - r_i^build| + 2|dt| max_i |v_i|, taken at the boundary before
- * step k-1, reaches skin/2 - 0.01 A. */
+ * spin segment). Two spins may not share a colour class (Sec. 5.1: spins
+ * updated together must not interact) when they are closer than
+ * ex_rc + skin/3 at colouring time; same-class pairs of the spin segment
+ * that are farther apart are watched instead.
+ * Rebuild rule: before step k the list is rebuilt when, at the boundary
+ * before step k-1,
+ *   max_i |r_i - r_i^build| + 2|dt| max_i |v_i| >= skin/2 - 0.01 A, or
+ *   min over watched pairs |r_i - r_j| - 4|dt| max_i |v_i| < ex_rc + 0.01 A
+ * (a boundary that rebuilt counts its build positions and the colour
+ * radius ex_rc + skin/3 instead). A rebuild keeps the colouring where
+ * valid: ends of conflicting edges with the later key (z, y, x, id), and
+ * atoms outside the palette of the last full colouring, are recoloured
+ * first-fit in key order. */
 int sl_set_neighbor(sl_system *sys, double skin, int max_nbr);
 
 /* User-supplied full list in CSR form over user ids: offsets[N+1], idx[].
@@ -155,7 +164,9 @@ int64_t sl_get_neighbor_list(sl_system *sys, int *nspin, int *nall, int *idx,
                              int64_t cap);
 
 /* Override the colouring (colour[N] in user order, values 0..63); validated
- * against the spin segment of the list (SL_E_COLOR on conflict). */
+ * against the colouring graph (spin-segment entries closer than
+ * ex_rc + skin/3; every spin-segment entry for a user list), SL_E_COLOR on
+ * conflict. Its palette becomes the base palette of later repairs. */
 int sl_set_coloring(sl_system *sys, const int *colour, int where);
 
 /* Colouring in user order and the class count K. Synchronises. */
@@ -202,7 +213,7 @@ int sl_get_tuning(sl_system *sys, sl_tuning *t);
  * launch of the spin-phase, force and rebuild kernels is bracketed by a
  * pair of events; sl_get_profile returns, per kernel kind, the launch count
  * and the summed event time in ms. Kinds: 0 spin phase, 1 force,
- * 2 neighbour rebuild, 3 energy reduction. */
+ * 2 neighbour rebuild, 3 learned-potential table. */
 int sl_set_profiling(sl_system *sys, int on);
 int sl_get_profile(sl_system *sys, int kind, int64_t *launches, double *ms,
                    double *work_items);

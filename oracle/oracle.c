@@ -54,8 +54,10 @@ struct orc_sys {
     double *F;
     int have_F;
 
-    /* rebuild predictor of the previous step boundary */
-    double D_prev;
+    /* rebuild predictors of the previous step boundary: displacement D and
+     * the closest approach W of two same-colour spins, less the motion
+     * bound of the two drifts ahead */
+    double D_prev, W_prev;
     int have_D;
 
     /* learned pair potential standing in for J and V (NULL: analytic) */
@@ -352,6 +354,22 @@ static double list_radius(const orc_sys *S)
     return rc + S->skin;
 }
 
+/* Two spins conflict (may not share a colour) when their distance at
+ * colouring time is below the exchange cutoff plus a third of the skin. A
+ * same-colour pair farther apart is watched instead: the list is rebuilt
+ * before it can come within the exchange cutoff (see orc_step). With a user
+ * list there is no rebuild, so every spin-segment entry conflicts. */
+static double colour_radius(const orc_sys *S) { return S->pot.ex_rc + S->skin / 3.0; }
+
+static int conflict(const orc_sys *S, int i, int j)
+{
+    if (S->user_list) return 1;
+    double d[3];
+    min_image(S->L, S->r + 3 * i, S->r + 3 * j, d);
+    double rc = colour_radius(S);
+    return dot3(d, d) < rc * rc;
+}
+
 static void ensure_cap(orc_sys *S, long need)
 {
     if (need <= S->cap) return;
@@ -531,7 +549,8 @@ long orc_brute_pairs(int N, const double L[3], const double *r, double rcut,
  * Colour classes. The paper makes sectors -- groups of spins that do not
  * interact -- and updates each group in turn (Sec. 5.1, Eq.
  * spin_ST_sectoring). Here a group is a colour class of the spin graph
- * (edges: spin-radius entries of the list at build time). The colouring is
+ * (edges: spin-segment entries closer than the colour radius at colouring
+ * time, see conflict()). The colouring is
  * first-fit greedy in ascending lexicographic key (z, y, x) of the wrapped
  * position at colouring time, ties broken by atom id. At later rebuilds a
  * colouring is kept where valid: for every edge whose ends share a colour,
@@ -567,6 +586,7 @@ static int first_free(const orc_sys *S, int i)
     int used[MAXC];
     memset(used, 0, sizeof(used));
     for (int k = S->off[i]; k < S->off[i] + S->nspin[i]; ++k) {
+        if (!conflict(S, i, S->idx[k])) continue;
         int c = S->colour[S->idx[k]];
         if (c >= 0 && c < MAXC) used[c] = 1;
     }
@@ -603,7 +623,8 @@ static void colour_update(orc_sys *S)
             if (S->colour[i] >= S->kbase) drop[i] = 1;
             for (int k = S->off[i]; k < S->off[i] + S->nspin[i]; ++k) {
                 int j = S->idx[k];
-                if (S->colour[j] == S->colour[i] && key_cmp(&keys[j], &keys[i]) < 0)
+                if (S->colour[j] == S->colour[i] && key_cmp(&keys[j], &keys[i]) < 0 &&
+                    conflict(S, i, j))
                     drop[i] = 1;
             }
         }
@@ -864,8 +885,29 @@ static void prepare_classes(orc_sys *S)
  *   D_{k-1} = max_i |r_i - r_i^build| + 2 |dt| max_i |v_i| >= skin/2 - 0.01 A,
  * with D evaluated at the previous boundary (after that boundary's own
  * rebuild, if any). The extra 2|dt| max|v| covers the two drifts that can
- * happen before the next decision. The classes are frozen for the step.
+ * happen before the next decision. It is also rebuilt when
+ *   W_{k-1} = min |r_i - r_j| - 4 |dt| max|v| < ex_rc + 0.01 A
+ * over same-colour pairs of spin-segment entries at the previous boundary:
+ * such a pair must not come within the exchange cutoff before the next
+ * decision (each of the two ends moves at most 2|dt| max|v|). A boundary
+ * that rebuilt takes W = colour radius - 4|dt| max|v| (after a colouring no
+ * same-colour pair is closer). The classes are frozen for the step.
  * ---------------------------------------------------------------------- */
+static double watch_min(const orc_sys *S)
+{
+    double m = 1e300;
+    for (int i = 0; i < S->N; ++i)
+        for (int k = S->off[i]; k < S->off[i] + S->nspin[i]; ++k) {
+            int j = S->idx[k];
+            if (S->colour[j] != S->colour[i]) continue;
+            double d[3];
+            min_image(S->L, S->r + 3 * i, S->r + 3 * j, d);
+            double r = norm3(d);
+            if (r < m) m = r;
+        }
+    return m;
+}
+
 static double max_disp(const orc_sys *S)
 {
     double m = 0.0;
@@ -908,13 +950,17 @@ int orc_step(orc_sys *S, int64_t n, double dt)
         if (!S->have_list) {
             int rc = orc_build_now(S); if (rc) return rc;
             rebuilt = 1;
-        } else if (!S->user_list && S->have_D && S->D_prev >= S->skin / 2.0 - 0.01) {
+        } else if (!S->user_list && S->have_D &&
+                   (S->D_prev >= S->skin / 2.0 - 0.01 ||
+                    (S->ordering == ORC_COLOUR && S->W_prev < S->pot.ex_rc + 0.01))) {
             int rc = rebuild(S); if (rc) return rc;
             rebuilt = 1;
         }
         if (S->ordering == ORC_COLOUR && !S->have_colour) colour_update(S);
-        (void)rebuilt;
-        S->D_prev = max_disp(S) + 2.0 * fabs(dt) * max_speed(S);
+        const double vmax = max_speed(S);
+        S->D_prev = max_disp(S) + 2.0 * fabs(dt) * vmax;
+        if (S->ordering == ORC_COLOUR)
+            S->W_prev = (rebuilt ? colour_radius(S) : watch_min(S)) - 4.0 * fabs(dt) * vmax;
         S->have_D = 1;
         prepare_classes(S);
         if (!S->have_F) forces(S);

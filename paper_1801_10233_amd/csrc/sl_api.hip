@@ -33,6 +33,7 @@ struct Atoms {
   void *sx = nullptr, *sy = nullptr, *sz = nullptr;
   int *id = nullptr, *colour = nullptr, *cell = nullptr;
   int *nspin = nullptr, *nall = nullptr, *nbr = nullptr;
+  unsigned long long *wmask = nullptr;  // same-colour spin-segment slots
 };
 
 struct ProfRec {
@@ -82,7 +83,7 @@ struct sl_system {
   unsigned int *done = nullptr;
   double *partial = nullptr, *red_out = nullptr;
   double *thermo = nullptr;
-  double *ring = nullptr;      // pinned host [4][4]
+  double *ring = nullptr;      // pinned host [4 boundaries][8]
   double *ring_dev = nullptr;  // device alias of ring
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   SlotMeta meta[4];
@@ -159,6 +160,13 @@ double list_radius(const sl_system *S) {
 
 double spin_radius(const sl_system *S) {
   return S->pot.ex_rc + (S->prm.frozen ? 0.0 : S->skin);
+}
+
+// Spins closer than this at colouring time may not share a colour; a
+// same-colour pair farther apart is watched by the rebuild rule instead.
+// With a user list (no rebuilds) every spin-segment entry conflicts.
+double colour_radius(const sl_system *S) {
+  return S->pot.ex_rc + (S->prm.frozen ? 0.0 : S->skin / 3.0);
 }
 
 int check_box(sl_system *S) {
@@ -317,6 +325,7 @@ int alloc_atoms(sl_system *S, Atoms &A) {
   HIPCHK(S, hipMalloc(&A.sz, rs * (n > 0 ? n : 1)));
   HIPCHK(S, dalloc(&A.id, n));
   HIPCHK(S, dalloc(&A.colour, n));
+  HIPCHK(S, dalloc(&A.wmask, n));
   HIPCHK(S, dalloc(&A.cell, n));
   HIPCHK(S, dalloc(&A.nspin, n));
   HIPCHK(S, dalloc(&A.nall, n));
@@ -333,7 +342,7 @@ void free_atoms(Atoms &A) {
   dfree(A.vx); dfree(A.vy); dfree(A.vz);
   dfree(A.bx); dfree(A.by); dfree(A.bz);
   dfree(A.mass); dfree(A.sx); dfree(A.sy); dfree(A.sz);
-  dfree(A.id); dfree(A.colour); dfree(A.cell);
+  dfree(A.id); dfree(A.colour); dfree(A.cell); dfree(A.wmask);
   dfree(A.nspin); dfree(A.nall); dfree(A.nbr);
   A = Atoms();
 }
@@ -408,6 +417,15 @@ ColourArgs colour_args(sl_system *S) {
   C.kz = S->kz;
   C.colour = A.colour;
   C.kbase = S->Kbase;
+  C.rx = A.rx[S->pos];
+  C.ry = A.ry[S->pos];
+  C.rz = A.rz[S->pos];
+  for (int d = 0; d < 3; ++d) {
+    C.L[d] = S->L[d];
+    C.invL[d] = S->invL[d];
+  }
+  const double rc = colour_radius(S);
+  C.cr2 = S->user_list ? 1e300 : rc * rc;
   return C;
 }
 
@@ -568,6 +586,10 @@ int colour_and_permute(sl_system *S, bool repair) {
   HIPCHK(S, hipStreamSynchronize(S->st));
   S->class_off.assign(S->K + 1, 0);
   for (int c = 0; c <= S->K; ++c) S->class_off[c] = bs[(size_t)c * S->ncell];
+  {
+    Atoms &N = S->a[S->cur];
+    launch_watch_mask(n, S->ld, N.nbr, N.nspin, N.colour, N.wmask, S->st);
+  }
   if (S->mlp) CHK(mlp_pairs(S));
   return SL_OK;
 }
@@ -761,13 +783,14 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   F.dslot = S->dslot;
   F.done = S->done;
   F.err = S->err;
+  F.wmask = A.wmask;
   F.frozen = S->prm.frozen;
   CHK(ensure_table(S, posbuf));
   if (mode & kModeNext) S->tab_ok[1 - posbuf] = false;
   const int slot = (int)(boundary & 3);
-  F.host_out = S->ring_dev + 4 * slot;
+  F.host_out = S->ring_dev + 8 * slot;
   if (mode & (kModeFinal | kModeNext)) {
-    S->ring[4 * slot + 3] = 0.0;
+    S->ring[8 * slot + 3] = 0.0;
     S->meta[slot].boundary = boundary;
     S->meta[slot].dt = dt;
     S->meta[slot].rebuilt_after = false;
@@ -799,19 +822,28 @@ int energy_now(sl_system *S, double out[8]) {
   return sticky_code(S);
 }
 
-// Wait until the force kernel of `boundary` finished and return its
-// rebuild predictor D (dmax + 2|dt| vmax), or -1 when not available.
-int wait_predictor(sl_system *S, int64_t boundary, double *D) {
-  *D = -1.0;
+// Wait until the force kernel of `boundary` finished and decide from its
+// predictor whether the list must be rebuilt before the step after next:
+//   D = max|r - r_build| + 2|dt| max|v|        >= skin/2 - 0.01, or
+//   W = min watched |r_i - r_j| - 4|dt| max|v| <  ex_rc + 0.01,
+// the watched pairs being same-colour spin-segment entries. When the list
+// was rebuilt at that boundary after the predictor was taken, the build
+// positions are that boundary's (D term 0) and no same-colour pair is
+// closer than the colour radius.
+int wait_predictor(sl_system *S, int64_t boundary, bool *due) {
+  *due = false;
   const int slot = (int)(boundary & 3);
   if (boundary < 0 || S->meta[slot].boundary != boundary) return SL_OK;
   HIPCHK(S, hipEventSynchronize(S->ev[slot]));
-  const double *o = S->ring + 4 * slot;
+  const double *o = S->ring + 8 * slot;
   if (o[3] != 1.0) return fail(S, SL_E_HIP, "rebuild predictor not written");
   S->sticky |= (int)o[2];
   CHK(sticky_code(S));
-  const double dmax = S->meta[slot].rebuilt_after ? 0.0 : o[0];
-  *D = dmax + 2.0 * std::fabs(S->meta[slot].dt) * o[1];
+  const bool rb = S->meta[slot].rebuilt_after;
+  const double adt = std::fabs(S->meta[slot].dt);
+  const double D = (rb ? 0.0 : o[0]) + 2.0 * adt * o[1];
+  const double W = (rb ? colour_radius(S) : std::sqrt(o[4])) - 4.0 * adt * o[1];
+  *due = D >= S->skin / 2.0 - 0.01 || W < S->pot.ex_rc + 0.01;
   return SL_OK;
 }
 
@@ -845,24 +877,28 @@ int step_frozen(sl_system *S, int64_t n, double dt) {
 }
 
 template <typename real>
-int step_coupled(sl_system *S, int64_t n, double dt) {
+int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
   const double h = dt / 4.0;
-  const double thr = S->skin / 2.0 - 0.01;
   const int te = S->prm.thermo_every;
   const int64_t k0 = S->step;
   // decision for the first step uses the predictor of the boundary before it
   if (!S->user_list && S->have_D) {
-    double D;
-    CHK(wait_predictor(S, k0 - 1, &D));
-    if (D >= thr) CHK(rebuild(S));
+    bool due;
+    CHK(wait_predictor(S, k0 - 1, &due));
+    if (due) {
+      CHK(rebuild(S));
+      built = true;
+    }
   }
   CHK(force_launch<real>(S, S->pos, kModeNext, dt, k0));
+  // a boundary that (re)built the list counts as rebuilt for the predictor
+  if (built) S->meta[k0 & 3].rebuilt_after = true;
   S->have_D = true;
   for (int64_t k = k0; k < k0 + n; ++k) {
     if (k > k0 && !S->user_list) {
-      double D;
-      CHK(wait_predictor(S, k - 1, &D));
-      if (D >= thr) {
+      bool due;
+      CHK(wait_predictor(S, k - 1, &due));
+      if (due) {
         CHK(rebuild(S));
         S->meta[k & 3].rebuilt_after = true;
       }
@@ -961,18 +997,24 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(dalloc(&S->seen, 2));
   A_(dalloc(&S->jpcnt, 2));
   A_(dalloc(&S->maxc, 1));
-  A_(dalloc(&S->dslot, 2));
+  A_(dalloc(&S->dslot, 3));
   A_(dalloc(&S->done, 1));
   A_(dalloc(&S->partial, (size_t)nb * 8));
   A_(dalloc(&S->red_out, 8));
   A_(dalloc(&S->thermo, (size_t)kThermoCap * 8));
-  A_(hipHostMalloc((void **)&S->ring, 16 * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
+  A_(hipHostMalloc((void **)&S->ring, 32 * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
   for (int k = 0; k < 4; ++k) A_(hipEventCreateWithFlags(&S->ev[k], hipEventDisableTiming));
   A_(hipHostGetDevicePointer((void **)&S->ring_dev, S->ring, 0));
 #undef A_
-  std::memset(S->ring, 0, 16 * sizeof(double));
+  std::memset(S->ring, 0, 32 * sizeof(double));
   (void)hipMemsetAsync(S->err, 0, sizeof(int), S->st);
-  (void)hipMemsetAsync(S->dslot, 0, 2 * sizeof(unsigned long long), S->st);
+  {
+    // running max slots start at 0, the running min at "no watched pair"
+    const double inf = kInf;
+    unsigned long long init[3] = {0ull, 0ull, 0ull};
+    std::memcpy(&init[2], &inf, sizeof(inf));
+    (void)hipMemcpy(S->dslot, init, sizeof(init), hipMemcpyHostToDevice);
+  }
   (void)hipMemsetAsync(S->done, 0, sizeof(unsigned int), S->st);
   launch_iota(n, S->a[0].id, S->st);
   if (hipStreamSynchronize(S->st) != hipSuccess) {
@@ -1291,12 +1333,15 @@ int sl_set_step(sl_system *S, int64_t step) {
 int sl_step(sl_system *S, int64_t n, double dt) {
   if (!S) return fail(S, SL_E_ARG, "NULL system");
   if (n < 0 || !std::isfinite(dt)) return fail(S, SL_E_ARG, "bad step count or dt");
+  const int64_t rb0 = S->rebuilds;
   CHK(ensure_ready(S));
   CHK(sticky_code(S));
   if (n == 0) return SL_OK;
   if (S->prm.frozen)
     return S->prec == SL_FP64 ? step_frozen<double>(S, n, dt) : step_frozen<float>(S, n, dt);
-  return S->prec == SL_FP64 ? step_coupled<double>(S, n, dt) : step_coupled<float>(S, n, dt);
+  const bool built = S->rebuilds != rb0;  // the list was built at this boundary
+  return S->prec == SL_FP64 ? step_coupled<double>(S, n, dt, built)
+                            : step_coupled<float>(S, n, dt, built);
 }
 
 int sl_get_energy(sl_system *S, sl_energy *out) {
@@ -1683,6 +1728,7 @@ int sl_mlp_train(sl_mlp *m, const sl_dataset *d, const sl_train_opts *o, sl_trai
 namespace {
 struct BatchRep {
   double cur_dm = 0, cur_vm = 0, cur_dt = 0, prev_dm = 0, prev_vm = 0, prev_dt = 0;
+  double cur_wm = kInf, prev_wm = kInf;
   int cur_rebuilt = 0, prev_rebuilt = 0, have_prev = 0;
   bool valid = false;
 };
@@ -1750,23 +1796,29 @@ int batch_step(sl_batch *B, int64_t n, double dt) {
   // call start of every replica: rebuild decision, first kick and drift
   for (int r = 0; r < R; ++r) {
     sl_system *S = B->sys[r];
+    const int64_t rb0 = S->rebuilds;
     BSYS(B, r, ensure_ready(S));
+    bool built = S->rebuilds != rb0;
     BatchRep &q = B->rep[r];
     if (!S->user_list && S->have_D && q.valid && q.have_prev) {
-      const double D = (q.prev_rebuilt ? 0.0 : q.prev_dm) + 2.0 * std::fabs(q.prev_dt) * q.prev_vm;
-      if (D >= S->skin / 2.0 - 0.01) {
+      const double adt = std::fabs(q.prev_dt);
+      const double D = (q.prev_rebuilt ? 0.0 : q.prev_dm) + 2.0 * adt * q.prev_vm;
+      const double W = (q.prev_rebuilt ? colour_radius(S) : std::sqrt(q.prev_wm)) - 4.0 * adt * q.prev_vm;
+      if (D >= S->skin / 2.0 - 0.01 || W < S->pot.ex_rc + 0.01) {
         BSYS(B, r, rebuild(S));
         B->rebuilds++;
+        built = true;
       }
     }
     k0[r] = S->step;
     BSYS(B, r, force_launch<real>(S, S->pos, kModeNext, dt, S->step));
-    double Dn;
-    BSYS(B, r, wait_predictor(S, S->step, &Dn));
-    const double *o = S->ring + 4 * (int)(S->step & 3);
-    q.prev_dm = q.cur_dm; q.prev_vm = q.cur_vm; q.prev_dt = q.cur_dt;
+    bool due_unused;
+    BSYS(B, r, wait_predictor(S, S->step, &due_unused));
+    const double *o = S->ring + 8 * (int)(S->step & 3);
+    q.prev_dm = q.cur_dm; q.prev_vm = q.cur_vm; q.prev_dt = q.cur_dt; q.prev_wm = q.cur_wm;
     q.prev_rebuilt = q.cur_rebuilt; q.have_prev = q.valid ? 1 : 0;
-    q.cur_dm = o[0]; q.cur_vm = o[1]; q.cur_dt = dt; q.cur_rebuilt = 0;
+    q.cur_dm = o[0]; q.cur_vm = o[1]; q.cur_wm = o[4]; q.cur_dt = dt;
+    q.cur_rebuilt = built ? 1 : 0;
     q.valid = true;
     S->have_D = true;
   }
@@ -1786,6 +1838,7 @@ int batch_step(sl_batch *B, int64_t n, double dt) {
       d.F.vx = A.vx; d.F.vy = A.vy; d.F.vz = A.vz;
       d.F.bx = A.bx; d.F.by = A.by; d.F.bz = A.bz;
       d.F.err = S->err;
+      d.F.wmask = A.wmask;
       if (S->K > kMaxClass) return bfail(B, SL_E_COLOR, "replica " + std::to_string(r) + " has too many colours");
       d.K = S->K;
       for (int c = 0; c <= S->K; ++c) d.off[c] = S->class_off[c];
@@ -1797,12 +1850,15 @@ int batch_step(sl_batch *B, int64_t n, double dt) {
       d.amp = noise_amp(S, dt / 4.0);
       d.rs2 = S->pot.ex_rc * S->pot.ex_rc;
       d.thr = S->skin / 2.0 - 0.01;
+      d.wr = colour_radius(S);
+      d.ex_rc = S->pot.ex_rc;
       d.seed = S->prm.seed;
       d.replica = S->prm.replica;
       d.user_list = S->user_list ? 1 : 0;
       const BatchRep &q = B->rep[r];
       d.cur_dm = q.cur_dm; d.cur_vm = q.cur_vm; d.cur_dt = q.cur_dt; d.cur_rebuilt = q.cur_rebuilt;
       d.prev_dm = q.prev_dm; d.prev_vm = q.prev_vm; d.prev_dt = q.prev_dt;
+      d.cur_wm = q.cur_wm; d.prev_wm = q.prev_wm;
       d.prev_rebuilt = q.prev_rebuilt; d.have_prev = q.have_prev;
       std::memcpy(B->h_desc.data() + r * dsz, &d, dsz);
       if (d.step < d.target) any = true;
@@ -1821,6 +1877,7 @@ int batch_step(sl_batch *B, int64_t n, double dt) {
       BatchRep &q = B->rep[r];
       q.cur_dm = d.cur_dm; q.cur_vm = d.cur_vm; q.cur_dt = d.cur_dt; q.cur_rebuilt = d.cur_rebuilt;
       q.prev_dm = d.prev_dm; q.prev_vm = d.prev_vm; q.prev_dt = d.prev_dt;
+      q.cur_wm = d.cur_wm; q.prev_wm = d.prev_wm;
       q.prev_rebuilt = d.prev_rebuilt; q.have_prev = d.have_prev;
       if (d.stopped) {
         BSYS(B, r, rebuild(S));

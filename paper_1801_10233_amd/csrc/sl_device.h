@@ -17,6 +17,7 @@ constexpr double kKb = 8.617333262e-5;         // eV/K
 constexpr double kMuB = 5.7883818060e-5;       // eV/T
 constexpr double kMvv2e = 1.0364269652680506e-4;  // eV per amu A^2/ps^2
 
+constexpr double kInf = 1e300;     // "no watched pair" distance squared
 constexpr int kMaxRep = 4;        // consecutive updates one spin launch can do
 constexpr int kSpinChunk = 4;     // neighbours per lane gathered together (spin phase)
 #ifndef SL_FORCE_CHUNK
@@ -104,9 +105,12 @@ struct ForceArgs {
   double *nx, *ny, *nz;       // next positions (drift target)
   const double *bx, *by, *bz; // positions at the last build
   double *partial;            // [nblocks][8] energy and M partial sums
-  unsigned long long *dslot;  // [2] device max of |r - r_build| and |v| (bits)
+  unsigned long long *dslot;  // [3] device max of |r - r_build| and |v|, min of
+                              // the watched squared distance (bits)
   unsigned int *done;         // block completion counter
-  double *host_out;           // pinned host: {dmax, vmax, err}
+  double *host_out;           // pinned host: {dmax, vmax, err, marker, wmin^2}
+  const unsigned long long *wmask;  // per atom: bit k set when spin-segment
+                                    // slot k holds a same-colour (watched) pair
   int *err;                   // sticky error word (device)
   int frozen;
 };
@@ -132,6 +136,9 @@ struct RepDesc {
   // of the current boundary and of the one before, and whether a rebuild
   // happened at the current boundary after its terms were taken
   double cur_dm, cur_vm, cur_dt, prev_dm, prev_vm, prev_dt;
+  double cur_wm, prev_wm;      // closest watched same-colour distance squared
+  double wr;                   // colour radius (watched distance after a rebuild)
+  double ex_rc;                // exchange cutoff
   int cur_rebuilt, prev_rebuilt, have_prev;
   int stopped;                 // out: the step at `step` needs a rebuild first
 };
@@ -230,6 +237,12 @@ __device__ __forceinline__ double wave_sum(double x) {
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
   return x;
 }
 

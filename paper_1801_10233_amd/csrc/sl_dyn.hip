@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kTailBlock) void k_spin_tail(SysView<real> S, PotCo
 template <typename real, int MODE, int LANES, bool MLP>
 __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotConst &P,
                                            const ForceArgs &A, int i, bool valid, int l,
-                                           double e[8], double &dm, double &vm) {
+                                           double e[8], double &dm, double &vm, double &wm) {
   real fx = 0, fy = 0, fz = 0;
   real ep = 0, ee = 0;
   double rix = 0, riy = 0, riz = 0;
@@ -214,6 +214,9 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
     six = S.sx[i]; siy = S.sy[i]; siz = S.sz[i];
     const int ns = S.nspin[i], na = S.nall[i];
     const int ld = S.ld;
+    // spin-segment slots holding a pair of one colour class are watched
+    const unsigned long long wmk =
+        ((MODE & (kModeFinal | kModeNext)) && A.wmask) ? A.wmask[i] : 0ull;
     // Two segments of the row, each gathered in chunks (all loads of a
     // chunk in flight together): the spin segment [0, ns) needs positions
     // and spins, the rest [ns, na) lies beyond the exchange cutoff (its
@@ -257,6 +260,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           const double dyd = min_image(riy - py[c], S.L[1], S.invL[1]);
           const double dzd = min_image(riz - pz[c], S.L[2], S.invL[2]);
           const double r2d = use ? dxd * dxd + dyd * dyd + dzd * dzd : 1.0;
+          if (seg == 0 && use && ((wmk >> (base + LANES * c)) & 1ull)) wm = fmin(wm, r2d);
           const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd;
           const double rinvd = rsqrt_nr(r2d);
           const real r = (real)(r2d * rinvd), rinv = (real)rinvd;
@@ -350,7 +354,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
 template <typename real, int MODE, int LANES, bool MLP>
 __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
   __shared__ double red[kBlock / 64][8];
-  __shared__ double redm[kBlock / 64][2];
+  __shared__ double redm[kBlock / 64][3];
   __shared__ int last;
   // Tiles are taken from the end of the atom order first: the last colour
   // classes may hold a few atoms scattered over the whole box (repairs),
@@ -361,8 +365,8 @@ __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, 
   const int l = t & (LANES - 1);
   const int i = t / LANES;
   double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double dm = 0.0, vm = 0.0;
-  force_atom<real, MODE, LANES, MLP>(S, P, A, i, i < S.n, l, e, dm, vm);
+  double dm = 0.0, vm = 0.0, wm = kInf;
+  force_atom<real, MODE, LANES, MLP>(S, P, A, i, i < S.n, l, e, dm, vm, wm);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (MODE & kModeEnergy) {
 #pragma unroll
@@ -372,8 +376,8 @@ __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, 
     }
   }
   if (MODE & (kModeFinal | kModeNext)) {
-    const double a = wave_max(dm), b = wave_max(vm);
-    if (lane == 0) { redm[wv][0] = a; redm[wv][1] = b; }
+    const double a = wave_max(dm), b = wave_max(vm), c = wave_min(wm);
+    if (lane == 0) { redm[wv][0] = a; redm[wv][1] = b; redm[wv][2] = c; }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -386,11 +390,16 @@ __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, 
     }
     last = 0;
     if (MODE & (kModeFinal | kModeNext)) {
-      double a = 0.0, b = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) { a = fmax(a, redm[w][0]); b = fmax(b, redm[w][1]); }
+      double a = 0.0, b = 0.0, c = kInf;
+      for (int w = 0; w < kBlock / 64; ++w) {
+        a = fmax(a, redm[w][0]);
+        b = fmax(b, redm[w][1]);
+        c = fmin(c, redm[w][2]);
+      }
       // non-negative doubles order like their bit patterns
       atomicMax(&A.dslot[0], (unsigned long long)__double_as_longlong(a));
       atomicMax(&A.dslot[1], (unsigned long long)__double_as_longlong(b));
+      atomicMin(&A.dslot[2], (unsigned long long)__double_as_longlong(c));
       __threadfence();
       const unsigned prev = atomicAdd(A.done, 1u);
       last = (prev == gridDim.x - 1);
@@ -401,11 +410,13 @@ __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, 
     __threadfence();
     const unsigned long long a = atomicExch(&A.dslot[0], 0ull);
     const unsigned long long b = atomicExch(&A.dslot[1], 0ull);
+    const unsigned long long c = atomicExch(&A.dslot[2], (unsigned long long)__double_as_longlong(kInf));
     atomicExch(A.done, 0u);
     const int err = atomicOr(A.err, 0);
     A.host_out[0] = __longlong_as_double((long long)a);
     A.host_out[1] = __longlong_as_double((long long)b);
     A.host_out[2] = (double)err;
+    A.host_out[4] = __longlong_as_double((long long)c);
     A.host_out[3] = 1.0;  // written marker
   }
 }
@@ -421,15 +432,15 @@ __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, 
 // independent, so no two workgroups ever wait on each other.
 template <typename real, int LANES>
 __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
-  __shared__ double redm[kBatchBlock / 64][2];
-  __shared__ double bcast[2];
+  __shared__ double redm[kBatchBlock / 64][3];
+  __shared__ double bcast[3];
   RepDesc<real> &d = D[blockIdx.x];
   const int t = threadIdx.x, l = t & (LANES - 1), per = kBatchBlock / LANES;
   int pos = d.pos;
   int64_t step = d.step;
   const int64_t target = d.target;
-  double cdm = d.cur_dm, cvm = d.cur_vm, cdt = d.cur_dt;
-  double pdm = d.prev_dm, pvm = d.prev_vm, pdt = d.prev_dt;
+  double cdm = d.cur_dm, cvm = d.cur_vm, cdt = d.cur_dt, cwm = d.cur_wm;
+  double pdm = d.prev_dm, pvm = d.prev_vm, pdt = d.prev_dt, pwm = d.prev_wm;
   int crb = d.cur_rebuilt, prb = d.prev_rebuilt, havep = d.have_prev;
   int stopped = 0;
   bool first = true;
@@ -437,7 +448,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
   while (step < target) {
     if (!first && !d.user_list && havep) {
       const double Dp = (prb ? 0.0 : pdm) + 2.0 * fabs(pdt) * pvm;
-      if (Dp >= d.thr) { stopped = 1; break; }
+      const double Wp = (prb ? d.wr : sqrt(pwm)) - 4.0 * fabs(pdt) * pvm;
+      if (Dp >= d.thr || Wp < d.ex_rc + 0.01) { stopped = 1; break; }
     }
     first = false;
     for (int half = 0; half < 2; ++half) {
@@ -468,28 +480,35 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
     F.nz = const_cast<double *>(d.V[pos].rz);
     const SysView<real> &W = d.V[1 - pos];
     const bool next = step + 1 < target;
-    double bdm = 0.0, bvm = 0.0;
+    double bdm = 0.0, bvm = 0.0, bwm = kInf;
     for (int base = 0; base < W.n; base += per) {
       const int i = base + t / LANES;
-      double e[8], dm = 0.0, vm = 0.0;
-      if (next) force_atom<real, kModeFinal | kModeNext, LANES, false>(W, d.P, F, i, i < W.n, l, e, dm, vm);
-      else force_atom<real, kModeFinal, LANES, false>(W, d.P, F, i, i < W.n, l, e, dm, vm);
+      double e[8], dm = 0.0, vm = 0.0, wm = kInf;
+      if (next) force_atom<real, kModeFinal | kModeNext, LANES, false>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
+      else force_atom<real, kModeFinal, LANES, false>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
       bdm = fmax(bdm, dm);
       bvm = fmax(bvm, vm);
+      bwm = fmin(bwm, wm);
     }
     bdm = wave_max(bdm);
     bvm = wave_max(bvm);
-    if ((t & 63) == 0) { redm[t >> 6][0] = bdm; redm[t >> 6][1] = bvm; }
+    bwm = wave_min(bwm);
+    if ((t & 63) == 0) { redm[t >> 6][0] = bdm; redm[t >> 6][1] = bvm; redm[t >> 6][2] = bwm; }
     __syncthreads();
     if (t == 0) {
-      double a = 0.0, b = 0.0;
-      for (int w = 0; w < kBatchBlock / 64; ++w) { a = fmax(a, redm[w][0]); b = fmax(b, redm[w][1]); }
+      double a = 0.0, b = 0.0, c = kInf;
+      for (int w = 0; w < kBatchBlock / 64; ++w) {
+        a = fmax(a, redm[w][0]);
+        b = fmax(b, redm[w][1]);
+        c = fmin(c, redm[w][2]);
+      }
       bcast[0] = a;
       bcast[1] = b;
+      bcast[2] = c;
     }
     __syncthreads();
-    pdm = cdm; pvm = cvm; pdt = cdt; prb = crb; havep = 1;
-    cdm = bcast[0]; cvm = bcast[1]; cdt = d.dt; crb = 0;
+    pdm = cdm; pvm = cvm; pdt = cdt; pwm = cwm; prb = crb; havep = 1;
+    cdm = bcast[0]; cvm = bcast[1]; cwm = bcast[2]; cdt = d.dt; crb = 0;
     pos = 1 - pos;
     ++step;
     __syncthreads();
@@ -497,8 +516,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
   if (t == 0) {
     d.pos = pos;
     d.step = step;
-    d.cur_dm = cdm; d.cur_vm = cvm; d.cur_dt = cdt; d.cur_rebuilt = crb;
-    d.prev_dm = pdm; d.prev_vm = pvm; d.prev_dt = pdt; d.prev_rebuilt = prb; d.have_prev = havep;
+    d.cur_dm = cdm; d.cur_vm = cvm; d.cur_dt = cdt; d.cur_wm = cwm; d.cur_rebuilt = crb;
+    d.prev_dm = pdm; d.prev_vm = pvm; d.prev_dt = pdt; d.prev_wm = pwm; d.prev_rebuilt = prb;
+    d.have_prev = havep;
     d.stopped = stopped;
   }
 }

@@ -61,6 +61,11 @@ struct ColourArgs {
   const double *kx, *ky, *kz;
   int *colour;
   int kbase;  // colours >= kbase are dropped by a repair
+  // spin-segment entries conflict (may not share a colour) when closer than
+  // sqrt(cr2) at these positions
+  const double *rx, *ry, *rz;
+  double L[3], invL[3];
+  double cr2;
 };
 void launch_colour_fill(int n, int *colour, int value, hipStream_t st);
 // Uncolour every atom that shares its colour with an earlier-key neighbour,
@@ -69,6 +74,10 @@ void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st);
 // One Jones-Plassmann round with key priority, first-fit colour choice.
 void launch_colour_round(const ColourArgs &A, int *remaining, int *reset_next, hipStream_t st);
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st);
+
+// Per atom, the spin-segment slots (< 64) whose entry has the atom's colour.
+void launch_watch_mask(int n, int ld, const int *nbr, const int *nspin, const int *colour,
+                       unsigned long long *wmask, hipStream_t st);
 
 // Permutation to (colour, cell) order.
 void launch_sort_key(int n, const int *colour, const int *cell, int ncell, int *key, int *count,

@@ -149,6 +149,14 @@ __device__ __forceinline__ bool key_less(const ColourArgs &A, int j, int i) {
   return A.id[j] < A.id[i];
 }
 
+// Whether list entry j of atom i is an edge of the colouring graph.
+__device__ __forceinline__ bool conflict(const ColourArgs &A, int i, int j) {
+  const double dx = min_image(A.rx[i] - A.rx[j], A.L[0], A.invL[0]);
+  const double dy = min_image(A.ry[i] - A.ry[j], A.L[1], A.invL[1]);
+  const double dz = min_image(A.rz[i] - A.rz[j], A.L[2], A.invL[2]);
+  return dx * dx + dy * dy + dz * dz < A.cr2;
+}
+
 __global__ void k_colour_fill(int n, int *colour, int value) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) colour[i] = value;
@@ -161,7 +169,7 @@ __global__ void k_colour_mark(ColourArgs A, int *out) {
   bool drop = c >= A.kbase;
   for (int k = 0; k < A.nspin[i]; ++k) {
     const int j = A.nbr[(size_t)k * A.ld + i];
-    if (A.colour[j] == c && key_less(A, j, i)) drop = true;
+    if (A.colour[j] == c && key_less(A, j, i) && conflict(A, i, j)) drop = true;
   }
   out[i] = drop ? -1 : c;
 }
@@ -179,6 +187,7 @@ __global__ void k_colour_round(ColourArgs A, int *remaining, int *reset_next) {
   unsigned long long used = 0ull;
   for (int k = 0; k < A.nspin[i]; ++k) {
     const int j = A.nbr[(size_t)k * A.ld + i];
+    if (!conflict(A, i, j)) continue;
     const int cj = col[j];
     if (cj >= 0) {
       used |= 1ull << (cj & 63);
@@ -195,9 +204,23 @@ __global__ void k_colour_stats(ColourArgs A, int *maxc, int *err) {
   if (i >= A.n) return;
   const int c = A.colour[i];
   atomicMax(maxc, c);
-  for (int k = 0; k < A.nspin[i]; ++k)
-    if (A.colour[A.nbr[(size_t)k * A.ld + i]] == c) atomicOr(err, kErrColour);
+  for (int k = 0; k < A.nspin[i]; ++k) {
+    const int j = A.nbr[(size_t)k * A.ld + i];
+    if (A.colour[j] == c && conflict(A, i, j)) atomicOr(err, kErrColour);
+  }
   if (c < 0) atomicOr(err, kErrColour);
+}
+
+__global__ void k_watch_mask(int n, int ld, const int *nbr, const int *nspin, const int *colour,
+                             unsigned long long *wmask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = colour[i];
+  const int ns = nspin[i] < 64 ? nspin[i] : 64;
+  unsigned long long m = 0ull;
+  for (int k = 0; k < ns; ++k)
+    if (colour[nbr[(size_t)k * ld + i]] == c) m |= 1ull << k;
+  wmask[i] = m;
 }
 
 __global__ void k_sort_key(int n, const int *colour, const int *cell, int ncell, int *key,
@@ -360,6 +383,10 @@ void launch_colour_round(const ColourArgs &A, int *remaining, int *reset_next, h
 }
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st) {
   if (A.n > 0) hipLaunchKernelGGL(k_colour_stats, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, maxc, err);
+}
+void launch_watch_mask(int n, int ld, const int *nbr, const int *nspin, const int *colour,
+                       unsigned long long *wmask, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_watch_mask, dim3(nblocks(n)), dim3(kBlock), 0, st, n, ld, nbr, nspin, colour, wmask);
 }
 void launch_sort_key(int n, const int *colour, const int *cell, int ncell, int *key, int *count,
                      hipStream_t st) {

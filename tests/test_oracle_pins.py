@@ -442,12 +442,28 @@ def test_neighbor_list_equals_brute_force():
         assert mine == brute
 
 
-def _py_greedy(r, box, rows, ns):
+def _edges(r, box, rows, ns, rc):
+    """Colouring-graph neighbours: spin-segment entries closer than rc."""
+    out = []
+    for i in range(len(r)):
+        seg = np.asarray(rows[i][:ns[i]], dtype=int)
+        d = r[i] - r[seg]
+        d -= box * np.round(d / box)
+        out.append(seg[np.einsum("ij,ij->i", d, d) < rc * rc])
+    return out
+
+
+# exchange cutoff plus a third of the 0.3 A skin
+RC_COLOUR = W.EXCHANGE_BJ["ex_rc"] + 0.1
+
+
+def _py_greedy(r, box, rows, ns, rc=RC_COLOUR):
     w = r - box * np.floor(r / box)
     order = sorted(range(len(r)), key=lambda i: (w[i, 2], w[i, 1], w[i, 0], i))
     col = [-1] * len(r)
+    E = _edges(r, box, rows, ns, rc)
     for i in order:
-        used = {col[j] for j in rows[i][:ns[i]] if col[j] >= 0}
+        used = {col[j] for j in E[i] if col[j] >= 0}
         c = 0
         while c in used:
             c += 1
@@ -466,26 +482,28 @@ def test_colouring_valid_and_greedy():
         o.build()
         c, K = o.coloring()
         ns, _, rows = o.neighbor_list()
+        E = _edges(r, box, rows, ns, RC_COLOUR)
         for i in range(N):
-            assert np.all(c[rows[i][:ns[i]]] != c[i])
+            assert np.all(c[E[i]] != c[i])
         assert np.array_equal(c, _py_greedy(r, box, rows, ns))
         if disp == 0.0:
             assert K == (4 if n % 2 == 0 else 9)
 
 
-def _py_repair(r, box, rows, ns, old, kbase):
+def _py_repair(r, box, rows, ns, old, kbase, rc=RC_COLOUR):
     w = r - box * np.floor(r / box)
     key = {i: (w[i, 2], w[i, 1], w[i, 0], i) for i in range(len(r))}
     col = list(old)
+    E = _edges(r, box, rows, ns, rc)
     drop = [old[i] >= kbase or
-            any(old[j] == old[i] and key[j] < key[i] for j in rows[i][:ns[i]])
+            any(old[j] == old[i] and key[j] < key[i] for j in E[i])
             for i in range(len(r))]
     for i in range(len(r)):
         if drop[i]:
             col[i] = -1
     for i in sorted(range(len(r)), key=lambda i: key[i]):
         if col[i] < 0:
-            used = {col[j] for j in rows[i][:ns[i]] if col[j] >= 0}
+            used = {col[j] for j in E[i] if col[j] >= 0}
             c = 0
             while c in used:
                 c += 1
@@ -511,8 +529,9 @@ def test_colouring_repair_keeps_valid_and_local():
     o.build()
     c1, K1 = o.coloring()
     ns, _, rows = o.neighbor_list()
+    E = _edges(r2, box, rows, ns, RC_COLOUR)
     for i in range(N):
-        assert np.all(c1[rows[i][:ns[i]]] != c1[i])
+        assert np.all(c1[E[i]] != c1[i])
     assert np.array_equal(c1, _py_repair(r2, box, rows, ns, c0, K0))
     changed = np.nonzero(c1 != c0)[0]
     assert 0 < len(changed) <= 12
@@ -554,4 +573,8 @@ def test_colouring_repair_rule_through_dynamics():
                 seen_return += 1
             c_prev = c
         r_prev = o.get_state()[0]
+        # the sweep's premise: no two spins of one class ever interact
+        pi, pj = O.brute_pairs(r_prev, box, W.EXCHANGE_BJ["ex_rc"])
+        cc = o.coloring()[0]
+        assert np.all(cc[pi] != cc[pj])
     assert checked >= 5 and seen_overflow >= 1 and seen_return >= 1, (checked, seen_overflow, seen_return)
