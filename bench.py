@@ -13,6 +13,9 @@ trigger), bracketed by device synchronisation on both sides.
 from __future__ import annotations
 
 import argparse
+import csv
+import collections
+import hashlib
 import json
 import os
 import sys
@@ -39,6 +42,68 @@ SPIN_BYTES = {sl.SL_FP64: 24 + 24 + 24 + 14 * 4, sl.SL_FP32: 12 + 12 + 24 + 14 *
 FORCE_BYTES = {sl.SL_FP64: 24 + 24 + 58 * 4 + 48 + 8 + 24 + 24,
                sl.SL_FP32: 24 + 12 + 58 * 4 + 48 + 8 + 24 + 24}
 KIND_NAME = {sl.PROF_SPIN: "k_spin_phase", sl.PROF_FORCE: "k_force"}
+# algorithmic bytes of one whole FP64 / FP32 atom-step (four spin updates,
+# one force pass with kicks and drift), same counting as above
+STEP_BYTES = {sl.SL_FP64: 4 * SPIN_BYTES[sl.SL_FP64] + FORCE_BYTES[sl.SL_FP64],
+              sl.SL_FP32: 4 * SPIN_BYTES[sl.SL_FP32] + FORCE_BYTES[sl.SL_FP32]}
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_10233_amd", "csrc", f)
+                  for f in ("sl_dyn.hip", "sl_device.h")]
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed memory-counter
+    summary, or None when there is none or the kernel sources changed since
+    the counters were taken."""
+    tag = "fp64" if precision == sl.SL_FP64 else "fp32"
+    path = os.path.join(PROFILES, f"{kernel}_432k_{tag}_memory_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def summarize(paths):
+    """Per-kernel averages from rocprofv3 CSV output: kernel-trace files
+    give the mean duration, counter-collection files the mean value of
+    every counter per dispatch."""
+    for path in paths:
+        with open(path) as fh:
+            rows = list(csv.DictReader(fh))
+        if not rows:
+            continue
+        agg = collections.defaultdict(list)
+        if "Counter_Name" in rows[0]:
+            for r in rows:
+                agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+            print(f"# {os.path.basename(path)}: mean counter value per dispatch")
+            for (k, c), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+                print(f"{c:>14s}  dispatches={len(v):6d}  mean={sum(v) / len(v):14.1f}  {k[:110]}")
+        else:
+            for r in rows:
+                agg[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+            print(f"# {os.path.basename(path)}: kernel durations")
+            for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+                print(f"calls={len(v):6d}  mean_us={sum(v) / len(v) / 1e3:10.3f}  "
+                      f"total_ms={sum(v) / 1e6:10.3f}  {k[:110]}")
 
 
 def log(*a):
@@ -67,12 +132,35 @@ def timed_run(S, steps, dt, profile=False):
     return t1 - t0, prof
 
 
-def drift_per_10ps(w, precision, steps, every=10):
+def batched_throughput(steps, lanes=0):
+    """Whole-batch atom-steps/s of the 64 uneven replicas (FP32 bulk)."""
+    ws = W.batched_replicas()
+    N = sum(w.N for w in ws)
+    B = sl.Batch(ws, precision=sl.SL_FP32)
+    if lanes:
+        B.set_lanes(lanes)
+    B.step(10, ws[0].dt)
+    sync()
+    t0 = time.perf_counter()
+    B.step(steps, ws[0].dt)
+    sync()
+    el = time.perf_counter() - t0
+    st = B.stats()
+    B.close()
+    return dict(value=round(N * steps / el, 1), unit="atom-steps/s", replicas=len(ws),
+                atoms=N, steps=steps, ms_per_step=round(el / steps * 1e3, 4),
+                dtype="f32", stats=st)
+
+
+def drift_per_10ps(w, precision, steps, every=10, settle=2000):
     """Least-squares slope of E_total/N against time on the undamped twin,
-    scaled to 10 ps."""
+    scaled to 10 ps, over `steps` steps after `settle` steps in which the
+    spin and lattice subsystems start exchanging energy."""
     S = sl.system_from_workload(w, precision=precision, thermo_every=every)
-    S.step(steps, w.dt)
+    S.step(settle + steps, w.dt)
     st, E, _ = S.thermo()
+    keep = st > settle
+    st, E = st[keep], E[keep]
     t = st * w.dt
     slope = np.polyfit(t, E / w.N, 1)[0]
     S.close()
@@ -123,10 +211,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32 form and drift")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--drift-steps", type=int, default=10000)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--summarize", nargs="+", metavar="CSV",
+                    help="print per-kernel averages of rocprofv3 CSV files and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this "
               "build (see DESIGN.md for how the path would shard).", file=sys.stderr)
@@ -165,11 +260,18 @@ def main():
                                 atoms_per_launch=round(v[2] / max(v[0], 1), 1))
              for k, v in kinds.items()}
     log("kernels:", json.dumps(other))
+    traffic = counter_traffic(KIND_NAME[dom], prec)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else round(traffic, 1),
+                    traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     kernel=KIND_NAME[dom], avg_launch_us=round(avg_ms * 1e3, 3),
                     algorithmic_bytes_per_atom=per_atom,
-                    atoms_per_launch=round(work / launches, 1), kernels=other)
+                    algorithmic_bytes_per_launch=round(bytes_per_launch, 1),
+                    atoms_per_launch=round(work / launches, 1), kernels=other,
+                    whole_step=dict(algorithmic_bytes_per_atom_step=STEP_BYTES[prec],
+                                    achieved_GBs=round(STEP_BYTES[prec] * value / 1e9, 1),
+                                    frac=round(STEP_BYTES[prec] * value / 1e9 / HBM_PEAK_GBS, 4)))
 
     out = dict(metric="atom-steps/s, 432k-atom bcc spin-lattice, plain FP64 vs FP32/MLP form @ drift",
                value=round(value, 1), unit="atom-steps/s", n_gpus=1, steps=args.steps,
@@ -193,15 +295,18 @@ def main():
         S32.close()
         v32 = w.N * args.steps / el32
         twin = W.large_langevin(n=args.n, nve=True)
-        d64, f64 = drift_per_10ps(twin, sl.SL_FP64, 1000)
-        d32, f32 = drift_per_10ps(twin, sl.SL_FP32, 1000)
+        d64, f64 = drift_per_10ps(twin, sl.SL_FP64, args.drift_steps)
+        d32, f32 = drift_per_10ps(twin, sl.SL_FP32, args.drift_steps)
         out["forms"] = dict(
             fp64=dict(value=round(value, 1), drift_eV_per_atom_per_10ps=d64, E_rms_eV_per_atom=f64),
             fp32=dict(value=round(v32, 1), speedup_vs_fp64=round(v32 / value, 3),
                       drift_eV_per_atom_per_10ps=d32, E_rms_eV_per_atom=f32),
-            drift_run="undamped twin, 1000 steps (0.1 ps), E sampled every 10 steps, "
+            drift_run=f"undamped twin, 2000 settling steps then {args.drift_steps} steps "
+                      f"({args.drift_steps * twin.dt:.2f} ps), E sampled every 10 steps, "
                       "least-squares slope scaled to 10 ps")
         log("forms:", json.dumps(out["forms"]))
+        out["batched"] = batched_throughput(args.batch_steps)
+        log("batched:", json.dumps(out["batched"]))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
