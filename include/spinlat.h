@@ -306,12 +306,14 @@ int sl_mlp_train(sl_mlp *m, const sl_dataset *d, const sl_train_opts *o, sl_trai
  * Batched replicas: R independent coupled systems (each with its own box,
  * size, list, colouring, Philox key/replica index, bath temperature and
  * field) advanced together. A step of every replica is the step of
- * sl_step; the replicas run in one persistent kernel launch (replayed from
- * a captured hipGraph), one workgroup per replica, which stops a replica
- * before a step that needs a neighbour-list rebuild; the library rebuilds
- * it and replays the launch until every replica has done n steps.
- * Results per replica equal those of a single sl_system up to summation
- * order. All replicas share one precision; frozen lattices are not batched.
+ * sl_step, with the same rebuild rule per replica. Two execution modes
+ * (sl_batch_set_mode): one persistent kernel launch (replayed from a
+ * captured hipGraph) with one workgroup per replica, which stops a replica
+ * before a step that needs a neighbour-list rebuild, the library rebuilding
+ * it and replaying the launch until every replica has done n steps; or one
+ * launch per colour phase over all replicas. Results per replica equal
+ * those of a single sl_system up to summation order. All replicas share
+ * one precision; frozen lattices are not batched.
  */
 typedef struct sl_batch sl_batch;
 
@@ -328,6 +330,20 @@ int sl_batch_get_state(sl_batch *b, int r, double *x, double *v, double *s,
 int sl_batch_get_energy(sl_batch *b, int r, sl_energy *out);
 /* n steps of length dt for every replica. */
 int sl_batch_step(sl_batch *b, int64_t n, double dt);
+
+/* Execution mode of sl_batch_step; both give the same trajectories for the
+ * same lanes setting (they share the per-atom device code).
+ *   SL_BATCH_PERSISTENT: one workgroup per replica runs all its steps in
+ *     one launch, replayed from a captured hipGraph (suits many small
+ *     replicas: no launch per phase);
+ *   SL_BATCH_PHASED: one launch per colour phase and per force pass over
+ *     all replicas at once (grid = tiles x replicas), the host deciding
+ *     rebuilds one step ahead (suits replicas too large for one CU).
+ * Default SL_BATCH_PHASED (5x faster than the persistent launch for 64
+ * replicas of 1k-28k atoms on MI355X). */
+enum { SL_BATCH_PERSISTENT = 0, SL_BATCH_PHASED = 1 };
+int sl_batch_set_mode(sl_batch *b, int mode);
+int sl_batch_get_mode(sl_batch *b, int *mode);
 /* Lanes per atom inside the persistent kernel (1, 2 or 4; speed only). */
 int sl_batch_set_lanes(sl_batch *b, int lanes);
 int sl_batch_get_stats(sl_batch *b, int64_t *launches, int64_t *rebuilds, int *lanes);

@@ -1745,6 +1745,8 @@ struct sl_batch {
   hipGraphExec_t exec = nullptr;
   int graph_lanes = -1;
   int lanes = 2;
+  int mode = SL_BATCH_PHASED;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int64_t launches = 0, rebuilds = 0;
   std::string last_err;
 };
@@ -1770,6 +1772,49 @@ int bfail(sl_batch *B, int code, const std::string &msg) {
     int rc_ = (x);                                                           \
     if (rc_) return bfail((B), rc_, "replica " + std::to_string(r) + ": " + (B)->sys[r]->last_err); \
   } while (0)
+
+// Descriptor of replica r for the batched kernels (current buffers, class
+// offsets, step, predictor state of the last two boundaries).
+template <typename real>
+int fill_desc(sl_batch *B, int r, double dt, int64_t target, RepDesc<real> &d) {
+  sl_system *S = B->sys[r];
+  std::memset(&d, 0, sizeof(d));
+  d.V[0] = view<real>(S, 0);
+  d.V[1] = view<real>(S, 1);
+  d.P = S->pc;
+  Atoms &A = S->a[S->cur];
+  d.F.ftm2v = 1.0 / kMvv2e;
+  d.F.mass = A.mass;
+  d.F.vx = A.vx; d.F.vy = A.vy; d.F.vz = A.vz;
+  d.F.bx = A.bx; d.F.by = A.by; d.F.bz = A.bz;
+  d.F.err = S->err;
+  d.F.wmask = A.wmask;
+  d.F.dslot = S->dslot;
+  d.F.done = S->done;
+  if (S->K > kMaxClass) return bfail(B, SL_E_COLOR, "replica " + std::to_string(r) + " has too many colours");
+  d.K = S->K;
+  for (int c = 0; c <= S->K; ++c) d.off[c] = S->class_off[c];
+  d.pos = S->pos;
+  d.step = S->step;
+  d.target = target;
+  d.dt = dt;
+  d.h = dt / 4.0;
+  d.amp = noise_amp(S, dt / 4.0);
+  d.rs2 = S->pot.ex_rc * S->pot.ex_rc;
+  d.thr = S->skin / 2.0 - 0.01;
+  d.wr = colour_radius(S);
+  d.ex_rc = S->pot.ex_rc;
+  d.seed = S->prm.seed;
+  d.replica = S->prm.replica;
+  d.user_list = S->user_list ? 1 : 0;
+  const BatchRep &q = B->rep[r];
+  d.cur_dm = q.cur_dm; d.cur_vm = q.cur_vm; d.cur_dt = q.cur_dt; d.cur_rebuilt = q.cur_rebuilt;
+  d.prev_dm = q.prev_dm; d.prev_vm = q.prev_vm; d.prev_dt = q.prev_dt;
+  d.cur_wm = q.cur_wm; d.prev_wm = q.prev_wm;
+  d.prev_rebuilt = q.prev_rebuilt; d.have_prev = q.have_prev;
+  d.ring = S->ring_dev;
+  return SL_OK;
+}
 
 template <typename real>
 int batch_launch(sl_batch *B) {
@@ -1828,38 +1873,7 @@ int batch_step(sl_batch *B, int64_t n, double dt) {
     for (int r = 0; r < R; ++r) {
       sl_system *S = B->sys[r];
       RepDesc<real> d;
-      std::memset(&d, 0, sizeof(d));
-      d.V[0] = view<real>(S, 0);
-      d.V[1] = view<real>(S, 1);
-      d.P = S->pc;
-      Atoms &A = S->a[S->cur];
-      d.F.ftm2v = 1.0 / kMvv2e;
-      d.F.mass = A.mass;
-      d.F.vx = A.vx; d.F.vy = A.vy; d.F.vz = A.vz;
-      d.F.bx = A.bx; d.F.by = A.by; d.F.bz = A.bz;
-      d.F.err = S->err;
-      d.F.wmask = A.wmask;
-      if (S->K > kMaxClass) return bfail(B, SL_E_COLOR, "replica " + std::to_string(r) + " has too many colours");
-      d.K = S->K;
-      for (int c = 0; c <= S->K; ++c) d.off[c] = S->class_off[c];
-      d.pos = S->pos;
-      d.step = S->step;
-      d.target = k0[r] + n;
-      d.dt = dt;
-      d.h = dt / 4.0;
-      d.amp = noise_amp(S, dt / 4.0);
-      d.rs2 = S->pot.ex_rc * S->pot.ex_rc;
-      d.thr = S->skin / 2.0 - 0.01;
-      d.wr = colour_radius(S);
-      d.ex_rc = S->pot.ex_rc;
-      d.seed = S->prm.seed;
-      d.replica = S->prm.replica;
-      d.user_list = S->user_list ? 1 : 0;
-      const BatchRep &q = B->rep[r];
-      d.cur_dm = q.cur_dm; d.cur_vm = q.cur_vm; d.cur_dt = q.cur_dt; d.cur_rebuilt = q.cur_rebuilt;
-      d.prev_dm = q.prev_dm; d.prev_vm = q.prev_vm; d.prev_dt = q.prev_dt;
-      d.cur_wm = q.cur_wm; d.prev_wm = q.prev_wm;
-      d.prev_rebuilt = q.prev_rebuilt; d.have_prev = q.have_prev;
+      CHK(fill_desc<real>(B, r, dt, k0[r] + n, d));
       std::memcpy(B->h_desc.data() + r * dsz, &d, dsz);
       if (d.step < d.target) any = true;
     }
@@ -1890,6 +1904,149 @@ int batch_step(sl_batch *B, int64_t n, double dt) {
   return SL_OK;
 }
 
+
+// Phase-batched mode: every spin phase and force pass is one launch over
+// all replicas; the host pipelines one step ahead exactly as step_coupled
+// does for one system (decision before step k from the predictor of
+// boundary k-1), with one event per boundary for the whole batch.
+template <typename real>
+int batch_step_phased(sl_batch *B, int64_t n, double dt) {
+  const int R = B->R;
+  const size_t dsz = sizeof(RepDesc<real>);
+  std::vector<int64_t> k0(R);
+  std::vector<int> pos0(R);
+  // call start: same decision as the persistent mode (predictor state of
+  // the previous call's last two boundaries)
+  for (int r = 0; r < R; ++r) {
+    sl_system *S = B->sys[r];
+    const int64_t rb0 = S->rebuilds;
+    BSYS(B, r, ensure_ready(S));
+    bool built = S->rebuilds != rb0;
+    BatchRep &q = B->rep[r];
+    if (!S->user_list && S->have_D && q.valid && q.have_prev) {
+      const double adt = std::fabs(q.prev_dt);
+      const double D = (q.prev_rebuilt ? 0.0 : q.prev_dm) + 2.0 * adt * q.prev_vm;
+      const double W = (q.prev_rebuilt ? colour_radius(S) : std::sqrt(q.prev_wm)) - 4.0 * adt * q.prev_vm;
+      if (D >= S->skin / 2.0 - 0.01 || W < S->pot.ex_rc + 0.01) {
+        BSYS(B, r, rebuild(S));
+        B->rebuilds++;
+        built = true;
+      }
+    }
+    k0[r] = S->step;
+    pos0[r] = S->pos;
+    const int slot = (int)(S->step & 3);
+    S->ring[8 * slot + 3] = 0.0;
+    S->meta[slot].boundary = S->step;
+    S->meta[slot].dt = dt;
+    S->meta[slot].rebuilt_after = built;
+    RepDesc<real> d;
+    CHK(fill_desc<real>(B, r, dt, k0[r] + n, d));
+    std::memcpy(B->h_desc.data() + r * dsz, &d, dsz);
+  }
+  BCHK(B, hipMemcpyAsync(B->d_desc, B->h_desc.data(), dsz * R, hipMemcpyHostToDevice, B->st));
+  BCHK(B, hipStreamSynchronize(B->st));
+  auto extents = [&](int &Kmax, int &max_class, int &max_n) {
+    Kmax = 0; max_class = 0; max_n = 0;
+    for (auto *S : B->sys) {
+      Kmax = std::max(Kmax, S->K);
+      max_n = std::max(max_n, S->n);
+      for (int c = 0; c < S->K; ++c)
+        max_class = std::max(max_class, S->class_off[c + 1] - S->class_off[c]);
+    }
+  };
+  int Kmax, max_class, max_n;
+  extents(Kmax, max_class, max_n);
+  const RepDesc<real> *D = (const RepDesc<real> *)B->d_desc;
+  BatchPhase bp{};
+  bp.kk = 0;
+  bp.after = 0;
+  launch_batch_force<real>(D, R, max_n, kModeNext, bp, B->lanes, B->st);
+  BCHK(B, hipEventRecord(B->ev[0], B->st));
+  for (int64_t kk = 0; kk < n; ++kk) {
+    if (kk > 0) {
+      // rebuild decision for step kk from the predictor of boundary kk - 1
+      BCHK(B, hipEventSynchronize(B->ev[(kk - 1) & 3]));
+      bool changed = false;
+      for (int r = 0; r < R; ++r) {
+        sl_system *S = B->sys[r];
+        if (S->user_list) continue;
+        const int64_t b = k0[r] + kk - 1;
+        const int slot = (int)(b & 3);
+        const double *o = S->ring + 8 * slot;
+        if (o[3] != 1.0) return bfail(B, SL_E_HIP, "replica " + std::to_string(r) + ": predictor not written");
+        S->sticky |= (int)o[2];
+        BSYS(B, r, sticky_code(S));
+        const bool rb = S->meta[slot].rebuilt_after;
+        const double adt = std::fabs(dt);
+        const double Dv = (rb ? 0.0 : o[0]) + 2.0 * adt * o[1];
+        const double Wv = (rb ? colour_radius(S) : std::sqrt(o[4])) - 4.0 * adt * o[1];
+        if (Dv >= S->skin / 2.0 - 0.01 || Wv < S->pot.ex_rc + 0.01) {
+          BSYS(B, r, rebuild(S));
+          B->rebuilds++;
+          S->meta[(b + 1) & 3].rebuilt_after = true;
+          RepDesc<real> d;
+          CHK(fill_desc<real>(B, r, dt, k0[r] + n, d));
+          d.pos = pos0[r];  // kernels index buffers from the call start
+          d.step = k0[r];
+          std::memcpy(B->h_desc.data() + r * dsz, &d, dsz);
+          BCHK(B, hipMemcpyAsync((char *)B->d_desc + r * dsz, B->h_desc.data() + r * dsz, dsz,
+                                 hipMemcpyHostToDevice, B->st));
+          changed = true;
+        }
+      }
+      if (changed) {
+        BCHK(B, hipStreamSynchronize(B->st));
+        extents(Kmax, max_class, max_n);
+      }
+    }
+    bp.kk = (int)kk;
+    for (int half = 0; half < 2; ++half) {
+      bp.half = half;
+      bp.Kmax = Kmax;
+      for (int p = 0; p < 2 * Kmax - 1; ++p) {
+        bp.p = p;
+        launch_batch_spin<real>(D, R, max_class, bp, B->lanes, B->st);
+      }
+    }
+    const int mode = kk + 1 < n ? (kModeFinal | kModeNext) : kModeFinal;
+    for (int r = 0; r < R; ++r) {
+      sl_system *S = B->sys[r];
+      const int64_t b = k0[r] + kk + 1;
+      const int slot = (int)(b & 3);
+      S->ring[8 * slot + 3] = 0.0;
+      S->meta[slot].boundary = b;
+      S->meta[slot].dt = dt;
+      S->meta[slot].rebuilt_after = false;
+      S->pos = 1 - S->pos;
+      S->step = b;
+    }
+    bp.after = 1;
+    launch_batch_force<real>(D, R, max_n, mode, bp, B->lanes, B->st);
+    bp.after = 0;
+    BCHK(B, hipEventRecord(B->ev[(kk + 1) & 3], B->st));
+    B->launches += 2 * (2 * Kmax - 1) + 1;
+  }
+  BCHK(B, hipStreamSynchronize(B->st));
+  // predictor state of the last two boundaries, for the next call's start
+  for (int r = 0; r < R; ++r) {
+    sl_system *S = B->sys[r];
+    BatchRep &q = B->rep[r];
+    const int64_t bl = k0[r] + n, bp2 = bl - 1;
+    const double *oc = S->ring + 8 * (int)(bl & 3);
+    const double *op = S->ring + 8 * (int)(bp2 & 3);
+    S->sticky |= (int)oc[2];
+    BSYS(B, r, sticky_code(S));
+    q.prev_dm = op[0]; q.prev_vm = op[1]; q.prev_wm = op[4]; q.prev_dt = dt;
+    q.prev_rebuilt = S->meta[bp2 & 3].rebuilt_after ? 1 : 0;
+    q.cur_dm = oc[0]; q.cur_vm = oc[1]; q.cur_wm = oc[4]; q.cur_dt = dt;
+    q.cur_rebuilt = S->meta[bl & 3].rebuilt_after ? 1 : 0;
+    q.have_prev = 1;
+    q.valid = true;
+    S->have_D = true;
+  }
+  return SL_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1915,6 +2072,12 @@ int sl_batch_create(int R, const sl_params *params, const sl_potential *pots, sl
     B->last_err = "hipStreamCreate failed";
     return bail(SL_E_HIP);
   }
+  for (int k = 0; k < 4; ++k)
+    if (hipEventCreateWithFlags(&B->ev[k], hipEventDisableTiming) != hipSuccess) {
+      B->ev[k] = nullptr;
+      B->last_err = "hipEventCreate failed";
+      return bail(SL_E_HIP);
+    }
   B->sys.assign(R, nullptr);
   B->rep.assign(R, BatchRep());
   for (int r = 0; r < R; ++r) {
@@ -1949,6 +2112,8 @@ int sl_batch_destroy(sl_batch *B) {
   for (auto *S : B->sys)
     if (S) sl_destroy(S);
   if (B->d_desc) (void)hipFree(B->d_desc);
+  for (auto &e : B->ev)
+    if (e) (void)hipEventDestroy(e);
   if (B->st) (void)hipStreamDestroy(B->st);
   delete B;
   return SL_OK;
@@ -1978,7 +2143,23 @@ int sl_batch_step(sl_batch *B, int64_t n, double dt) {
   if (!B) return bfail(B, SL_E_ARG, "NULL batch");
   if (n < 0 || !std::isfinite(dt)) return bfail(B, SL_E_ARG, "bad step count or dt");
   if (n == 0) return SL_OK;
+  if (B->mode == SL_BATCH_PHASED)
+    return B->prec == SL_FP64 ? batch_step_phased<double>(B, n, dt)
+                              : batch_step_phased<float>(B, n, dt);
   return B->prec == SL_FP64 ? batch_step<double>(B, n, dt) : batch_step<float>(B, n, dt);
+}
+
+int sl_batch_set_mode(sl_batch *B, int mode) {
+  if (!B || !(mode == SL_BATCH_PERSISTENT || mode == SL_BATCH_PHASED))
+    return bfail(B, SL_E_ARG, "mode must be SL_BATCH_PERSISTENT or SL_BATCH_PHASED");
+  B->mode = mode;
+  return SL_OK;
+}
+
+int sl_batch_get_mode(sl_batch *B, int *mode) {
+  if (!B || !mode) return bfail(B, SL_E_ARG, "NULL argument");
+  *mode = B->mode;
+  return SL_OK;
 }
 
 int sl_batch_set_lanes(sl_batch *B, int lanes) {

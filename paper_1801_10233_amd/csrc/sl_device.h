@@ -141,6 +141,19 @@ struct RepDesc {
   double ex_rc;                // exchange cutoff
   int cur_rebuilt, prev_rebuilt, have_prev;
   int stopped;                 // out: the step at `step` needs a rebuild first
+  double *ring;                // pinned host predictor slots [4][8] (phase mode)
+};
+
+// One launch of the phase-batched mode: every replica's share of colour
+// phase p of a spin half-step, or of a force pass. Replica r (K_r classes)
+// visits class p for p < K_r - 1, its last class twice in a row at
+// p = K_r - 1 and class K_r - 2 - (p - Kmax) for p >= Kmax; any other phase
+// leaves it idle, so each replica keeps its own forward/backward order.
+struct BatchPhase {
+  int p, Kmax;
+  int half;   // spin: 0 first half-step (boundary positions), 1 second
+  int kk;     // steps since the call started: replica step = step + kk
+  int after;  // force: 1 at the boundary after step kk, 0 at the call start
 };
 
 // -------------------------------------------------------------------------

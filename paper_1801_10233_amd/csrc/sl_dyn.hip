@@ -535,6 +535,135 @@ void launch_batch_run(RepDesc<real> *D, int R, int lanes, hipStream_t st) {
 template void launch_batch_run<double>(RepDesc<double> *, int, int, hipStream_t);
 template void launch_batch_run<float>(RepDesc<float> *, int, int, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Phase-batched replicas: one launch covers every replica's share of one
+// colour phase (blockIdx.y = replica, blockIdx.x = tile of its class), so
+// the whole device works on each phase instead of one workgroup per replica.
+// All replicas advance in lockstep inside a call; replica r is at step
+// d.step + kk with its current positions in buffer d.pos ^ (kk & 1).
+template <typename real, int LANES>
+__global__ __launch_bounds__(kBlock) void k_batch_spin(const RepDesc<real> *D, BatchPhase bp) {
+  const RepDesc<real> &d = D[blockIdx.y];
+  const int K = d.K;
+  const int subf = 2 * bp.half;
+  int c, nrep = 1, s0 = subf, s1 = subf + 1;
+  if (bp.p < bp.Kmax) {
+    if (bp.p >= K) return;
+    c = bp.p;
+    if (c == K - 1) nrep = 2;
+  } else {
+    c = K - 2 - (bp.p - bp.Kmax);
+    if (c < 0) return;
+    s0 = subf + 1;
+  }
+  const int b0 = d.off[c], b1 = d.off[c + 1];
+  const int base = b0 + (int)blockIdx.x * (kBlock / LANES);
+  if (base >= b1) return;
+  const int i = base + (int)threadIdx.x / LANES, l = threadIdx.x & (LANES - 1);
+  const int pos = d.pos ^ (bp.kk & 1);
+  const int64_t step = d.step + bp.kk;
+  const int64_t st[kMaxRep] = {step, step, step, step};
+  const int sb[kMaxRep] = {s0, s1, 0, 0};
+  spin_update<real, true, true, LANES, false>(d.V[bp.half == 0 ? pos : 1 - pos], d.P, i, i < b1,
+                                             l, nrep, st, sb, d.h, d.amp, d.seed, d.replica,
+                                             d.rs2);
+}
+
+// Force, kicks and drift of every replica at one boundary, with each
+// replica's rebuild predictor reduced by its own last block into its own
+// pinned slot (as k_force does for one system).
+template <typename real, int MODE, int LANES>
+__global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, BatchPhase bp) {
+  __shared__ double redm[kBlock / 64][3];
+  __shared__ int last;
+  const RepDesc<real> &d = D[blockIdx.y];
+  const int n = d.V[0].n;
+  const int per = kBlock / LANES;
+  const int nb = (n + per - 1) / per;
+  if ((int)blockIdx.x >= nb) return;
+  // buffer holding this boundary's positions; the drift goes to the other
+  const int cur = bp.after ? 1 - (d.pos ^ (bp.kk & 1)) : d.pos;
+  const int64_t boundary = d.step + bp.kk + bp.after;
+  ForceArgs F = d.F;
+  F.dt = d.dt;
+  F.nx = const_cast<double *>(d.V[1 - cur].rx);
+  F.ny = const_cast<double *>(d.V[1 - cur].ry);
+  F.nz = const_cast<double *>(d.V[1 - cur].rz);
+  F.host_out = d.ring + 8 * (int)(boundary & 3);
+  const int i = (int)blockIdx.x * per + (int)threadIdx.x / LANES, l = threadIdx.x & (LANES - 1);
+  double e[8], dm = 0.0, vm = 0.0, wm = kInf;
+  force_atom<real, MODE, LANES, false>(d.V[cur], d.P, F, i, i < n, l, e, dm, vm, wm);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double a = wave_max(dm), b = wave_max(vm), c = wave_min(wm);
+  if (lane == 0) { redm[wv][0] = a; redm[wv][1] = b; redm[wv][2] = c; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0.0, y = 0.0, z = kInf;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      x = fmax(x, redm[w][0]);
+      y = fmax(y, redm[w][1]);
+      z = fmin(z, redm[w][2]);
+    }
+    atomicMax(&F.dslot[0], (unsigned long long)__double_as_longlong(x));
+    atomicMax(&F.dslot[1], (unsigned long long)__double_as_longlong(y));
+    atomicMin(&F.dslot[2], (unsigned long long)__double_as_longlong(z));
+    __threadfence();
+    last = (atomicAdd(F.done, 1u) == (unsigned)nb - 1);
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    const unsigned long long x = atomicExch(&F.dslot[0], 0ull);
+    const unsigned long long y = atomicExch(&F.dslot[1], 0ull);
+    const unsigned long long z = atomicExch(&F.dslot[2], (unsigned long long)__double_as_longlong(kInf));
+    atomicExch(F.done, 0u);
+    const int err = atomicOr(F.err, 0);
+    F.host_out[0] = __longlong_as_double((long long)x);
+    F.host_out[1] = __longlong_as_double((long long)y);
+    F.host_out[2] = (double)err;
+    F.host_out[4] = __longlong_as_double((long long)z);
+    F.host_out[3] = 1.0;  // written marker
+  }
+}
+
+template <typename real>
+void launch_batch_spin(const RepDesc<real> *D, int R, int max_class, const BatchPhase &bp,
+                       int lanes, hipStream_t st) {
+  if (R <= 0 || max_class <= 0) return;
+  const int per = kBlock / lanes;
+  const dim3 grid((max_class + per - 1) / per, R);
+  switch (lanes) {
+    case 1: hipLaunchKernelGGL((k_batch_spin<real, 1>), grid, dim3(kBlock), 0, st, D, bp); break;
+    case 4: hipLaunchKernelGGL((k_batch_spin<real, 4>), grid, dim3(kBlock), 0, st, D, bp); break;
+    default: hipLaunchKernelGGL((k_batch_spin<real, 2>), grid, dim3(kBlock), 0, st, D, bp); break;
+  }
+}
+
+template <typename real, int MODE>
+static void batch_force_mode(const RepDesc<real> *D, const dim3 &grid, const BatchPhase &bp,
+                             int lanes, hipStream_t st) {
+  switch (lanes) {
+    case 2: hipLaunchKernelGGL((k_batch_force<real, MODE, 2>), grid, dim3(kBlock), 0, st, D, bp); break;
+    case 4: hipLaunchKernelGGL((k_batch_force<real, MODE, 4>), grid, dim3(kBlock), 0, st, D, bp); break;
+    default: hipLaunchKernelGGL((k_batch_force<real, MODE, 1>), grid, dim3(kBlock), 0, st, D, bp); break;
+  }
+}
+
+template <typename real>
+void launch_batch_force(const RepDesc<real> *D, int R, int max_n, int mode, const BatchPhase &bp,
+                        int lanes, hipStream_t st) {
+  if (R <= 0 || max_n <= 0) return;
+  const int per = kBlock / lanes;
+  const dim3 grid((max_n + per - 1) / per, R);
+  if (mode == kModeNext) batch_force_mode<real, kModeNext>(D, grid, bp, lanes, st);
+  else if (mode == kModeFinal) batch_force_mode<real, kModeFinal>(D, grid, bp, lanes, st);
+  else batch_force_mode<real, kModeFinal | kModeNext>(D, grid, bp, lanes, st);
+}
+template void launch_batch_spin<double>(const RepDesc<double> *, int, int, const BatchPhase &, int, hipStream_t);
+template void launch_batch_spin<float>(const RepDesc<float> *, int, int, const BatchPhase &, int, hipStream_t);
+template void launch_batch_force<double>(const RepDesc<double> *, int, int, int, const BatchPhase &, int, hipStream_t);
+template void launch_batch_force<float>(const RepDesc<float> *, int, int, int, const BatchPhase &, int, hipStream_t);
+
 // Fixed-order sum of nb partial rows of 8 doubles (deterministic result).
 __global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, double *out) {
   __shared__ double buf[256][8];

@@ -19,6 +19,16 @@ void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
 int force_blocks(int n, int lanes);
 template <typename real>
 void launch_batch_run(RepDesc<real> *D, int R, int lanes, hipStream_t st);
+// Phase-batched mode: one colour phase of every replica (max_class = the
+// largest class of any replica) and one force pass of every replica (max_n =
+// the largest replica; mode kModeNext at the call start, kModeFinal with or
+// without kModeNext after a step).
+template <typename real>
+void launch_batch_spin(const RepDesc<real> *D, int R, int max_class, const BatchPhase &bp,
+                       int lanes, hipStream_t st);
+template <typename real>
+void launch_batch_force(const RepDesc<real> *D, int R, int max_n, int mode, const BatchPhase &bp,
+                        int lanes, hipStream_t st);
 void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st);
 
 // --- rebuild kernels (sl_nbr.hip) ---

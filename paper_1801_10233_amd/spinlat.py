@@ -28,6 +28,8 @@ SL_HOST = 0
 SL_DEVICE = 1
 SL_FP64 = 0
 SL_FP32 = 1
+SL_BATCH_PERSISTENT = 0
+SL_BATCH_PHASED = 1
 
 PROF_SPIN, PROF_FORCE, PROF_REBUILD, PROF_REDUCE = 0, 1, 2, 3
 
@@ -44,7 +46,7 @@ EXPORTS = [
     "sl_mlp_loss_grad", "sl_mlp_train",
     "sl_batch_create", "sl_batch_destroy", "sl_batch_set_state", "sl_batch_get_state",
     "sl_batch_get_energy", "sl_batch_step", "sl_batch_set_lanes", "sl_batch_get_stats",
-    "sl_batch_last_error",
+    "sl_batch_last_error", "sl_batch_set_mode", "sl_batch_get_mode",
 ]
 
 SL_MLP_NPARAM = 5378
@@ -167,6 +169,8 @@ def lib():
         "sl_batch_set_lanes": ([vp, C.c_int], C.c_int),
         "sl_batch_get_stats": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), ip], C.c_int),
         "sl_batch_last_error": ([vp], C.c_char_p),
+        "sl_batch_set_mode": ([vp, C.c_int], C.c_int),
+        "sl_batch_get_mode": ([vp, ip], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -511,6 +515,14 @@ class Batch:
 
     def set_lanes(self, lanes):
         self._check(lib().sl_batch_set_lanes(self.h, int(lanes)))
+
+    def set_mode(self, mode):
+        self._check(lib().sl_batch_set_mode(self.h, int(mode)))
+
+    def mode(self):
+        m = C.c_int()
+        self._check(lib().sl_batch_get_mode(self.h, C.byref(m)))
+        return m.value
 
     def stats(self):
         a = C.c_int64(); b = C.c_int64(); c = C.c_int()

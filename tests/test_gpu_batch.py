@@ -1,4 +1,5 @@
-"""Batched replicas (one persistent launch) vs the CPU oracle, per replica.
+"""Batched replicas vs the CPU oracle, per replica, in both execution modes
+(one persistent launch; one launch per colour phase over all replicas).
 
 Replicas of uneven size, temperature and field, each with its own Philox
 replica index; FP64 bar as for a single system (1e-10 over the run),
@@ -21,12 +22,17 @@ def _small_replicas(R=4, seed=77, hot=False):
     return ws
 
 
+MODES = [0, 1]   # SL_BATCH_PERSISTENT, SL_BATCH_PHASED
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("lanes", [1, 2, 4])
-def test_batch_matches_oracle_per_replica(lanes):
+def test_batch_matches_oracle_per_replica(lanes, mode):
     from paper_1801_10233_amd import spinlat as sl
     ws = _small_replicas()
     b = sl.Batch(ws, precision=sl.SL_FP64)
     b.set_lanes(lanes)
+    b.set_mode(mode)
     b.step(60, 1e-4)
     for r, w in enumerate(ws):
         o = make_oracle(w)
@@ -40,11 +46,14 @@ def test_batch_matches_oracle_per_replica(lanes):
         assert dr < 1e-10 and ds < 1e-10 and dv < 1e-10
 
 
-def test_batch_through_rebuilds_and_calls():
+@pytest.mark.parametrize("modes", [(0, 0), (1, 1), (0, 1), (1, 0)])
+def test_batch_through_rebuilds_and_calls(modes):
+    # two calls, possibly switching the execution mode between them
     from paper_1801_10233_amd import spinlat as sl
     ws = _small_replicas(R=3, seed=5, hot=True)
     b = sl.Batch(ws, precision=sl.SL_FP64)
-    for chunk in (45, 80):
+    for chunk, mode in zip((45, 80), modes):
+        b.set_mode(mode)
         b.step(chunk, 2e-4)
     st = b.stats()
     print("batch stats", st, flush=True)
@@ -62,13 +71,34 @@ def test_batch_through_rebuilds_and_calls():
     assert tot >= 3 and st["rebuilds"] == tot
 
 
-def test_batch_fp32_energies_close_to_oracle():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_fp32_energies_close_to_oracle(mode):
     from paper_1801_10233_amd import spinlat as sl
     ws = _small_replicas(R=3, seed=9)
     b = sl.Batch(ws, precision=sl.SL_FP32)
+    b.set_mode(mode)
     b.step(50, 1e-4)
     for r, w in enumerate(ws):
         o = make_oracle(w)
         o.step(50, 1e-4)
         eg, eo = b.energy(r)["total"], o.energy()["total"]
         assert abs(eg - eo) / w.N < 1e-5
+
+
+def test_batch_modes_agree():
+    # same per-atom device code and lanes; the compiler may still contract
+    # multiply-adds differently in the two kernels, so agreement is to
+    # rounding, far inside the oracle bar
+    from paper_1801_10233_amd import spinlat as sl
+    ws = _small_replicas(R=5, seed=21, hot=True)
+    out = []
+    for mode in MODES:
+        b = sl.Batch(ws, precision=sl.SL_FP64)
+        b.set_mode(mode)
+        b.step(70, 2e-4)
+        out.append([b.get_state(r) for r in range(len(ws))])
+        print("mode", mode, b.stats(), flush=True)
+        b.close()
+    for a, c in zip(*out):
+        for x, y in zip(a, c):
+            assert np.abs(x - y).max() <= 1e-12 * max(1.0, np.abs(x).max())
