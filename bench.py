@@ -132,13 +132,12 @@ def timed_run(S, steps, dt, profile=False):
     return t1 - t0, prof
 
 
-def batched_throughput(steps, lanes=0):
+def batched_throughput(steps, tune=True):
     """Whole-batch atom-steps/s of the 64 uneven replicas (FP32 bulk)."""
     ws = W.batched_replicas()
     N = sum(w.N for w in ws)
     B = sl.Batch(ws, precision=sl.SL_FP32)
-    if lanes:
-        B.set_lanes(lanes)
+    tuned = B.autotune(10, ws[0].dt) if tune else None
     B.step(10, ws[0].dt)
     sync()
     t0 = time.perf_counter()
@@ -149,7 +148,7 @@ def batched_throughput(steps, lanes=0):
     B.close()
     return dict(value=round(N * steps / el, 1), unit="atom-steps/s", replicas=len(ws),
                 atoms=N, steps=steps, ms_per_step=round(el / steps * 1e3, 4),
-                dtype="f32", stats=st)
+                dtype="f32", tuned=tuned, stats=st)
 
 
 def drift_per_10ps(w, precision, steps, every=10, settle=2000):
@@ -212,6 +211,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip FP32 form and drift")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--drift-steps", type=int, default=10000)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shapes (no autotune before timing)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--summarize", nargs="+", metavar="CSV",
                     help="print per-kernel averages of rocprofv3 CSV files and exit")
@@ -237,7 +238,9 @@ def main():
     log(f"workload {w.name}: N={w.N} box={w.box[0]:.3f} A dt={w.dt} ps")
     t_setup = time.perf_counter()
     S = sl.system_from_workload(w, precision=prec)
-    S.step(args.warmup, w.dt)           # includes the first list build and colouring
+    S.step(0, w.dt)                     # first list build and colouring
+    tuned = None if args.no_tune else S.autotune(20, w.dt)
+    S.step(args.warmup, w.dt)
     S.synchronize()
     log(f"setup + warmup {time.perf_counter() - t_setup:.2f} s; stats {S.stats()}")
 
@@ -282,7 +285,7 @@ def main():
                config=dict(workload="large_langevin: bcc 60^3 cells, 432000 atoms, Morse + "
                                     "Bethe-Slater exchange + uniaxial K=1e-4 eV + spin Langevin "
                                     "lambda=0.01 at 300 K (Philox), dt=1e-4 ps",
-                           atoms=w.N, dt_ps=w.dt, colours=st["n_colours"],
+                           atoms=w.N, dt_ps=w.dt, colours=st["n_colours"], tuning=tuned,
                            rebuilds_in_run=st["rebuilds"], parallelism="single GPU"),
                roofline=roofline)
     S.close()
@@ -290,6 +293,9 @@ def main():
     if not args.no_extras:
         # FP32 form on the same workload, and drift of both forms on the NVE twin
         S32 = sl.system_from_workload(w, precision=sl.SL_FP32)
+        S32.step(0, w.dt)
+        if not args.no_tune:
+            S32.autotune(20, w.dt)
         S32.step(args.warmup, w.dt)
         el32, _ = timed_run(S32, args.steps, w.dt)
         S32.close()
@@ -305,7 +311,7 @@ def main():
                       f"({args.drift_steps * twin.dt:.2f} ps), E sampled every 10 steps, "
                       "least-squares slope scaled to 10 ps")
         log("forms:", json.dumps(out["forms"]))
-        out["batched"] = batched_throughput(args.batch_steps)
+        out["batched"] = batched_throughput(args.batch_steps, tune=not args.no_tune)
         log("batched:", json.dumps(out["batched"]))
 
     if not args.no_cpu:

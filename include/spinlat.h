@@ -209,6 +209,20 @@ typedef struct {
 int sl_set_tuning(sl_system *sys, const sl_tuning *t);
 int sl_get_tuning(sl_system *sys, sl_tuning *t);
 
+/* Autotuner. Runs `steps` steps of length dt under each candidate launch
+ * shape (spin lanes 1, 2, 4; force lanes 1, 2) on a scratch copy of the
+ * system (same parameters, interactions, learned potential, user list,
+ * state and step counter; its own stream and memory, freed before
+ * returning), times the spin-phase and force kernels with HIP events, and
+ * sets the fastest shape on sys (returned in *chosen if not NULL). sys is
+ * not advanced, and its later results change at most by summation-order
+ * roundoff (the shape only splits neighbour sums across lanes); colouring,
+ * skin and rebuild rule are never touched. When the environment variable
+ * SL_TUNE_CACHE names a file, results are looked up there first (one JSON
+ * object per line, keyed by the GPU architecture and the system's shape)
+ * and appended after tuning. */
+int sl_autotune(sl_system *sys, int steps, double dt, sl_tuning *chosen);
+
 /* Per-kernel timing with HIP events on the system's stream. When on, every
  * launch of the spin-phase, force and rebuild kernels is bracketed by a
  * pair of events; sl_get_profile returns, per kernel kind, the launch count
@@ -344,6 +358,12 @@ int sl_batch_step(sl_batch *b, int64_t n, double dt);
 enum { SL_BATCH_PERSISTENT = 0, SL_BATCH_PHASED = 1 };
 int sl_batch_set_mode(sl_batch *b, int mode);
 int sl_batch_get_mode(sl_batch *b, int *mode);
+
+/* Batch autotuner: times `steps` steps of a scratch copy of the batch
+ * under each (mode, lanes) pair (phased with 1, 2, 4 lanes; persistent
+ * with 1, 2) and keeps the fastest on b; b is not advanced. Same cache as
+ * sl_autotune. */
+int sl_batch_autotune(sl_batch *b, int steps, double dt, int *mode, int *lanes);
 /* Lanes per atom inside the persistent kernel (1, 2 or 4; speed only). */
 int sl_batch_set_lanes(sl_batch *b, int lanes);
 int sl_batch_get_stats(sl_batch *b, int64_t *launches, int64_t *rebuilds, int *lanes);

@@ -7,6 +7,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1723,6 +1726,167 @@ int sl_mlp_train(sl_mlp *m, const sl_dataset *d, const sl_train_opts *o, sl_trai
 
 }  // extern "C"
 
+
+// ============================================================================
+// Autotuner: times launch shapes on scratch copies and keeps the fastest.
+namespace {
+
+// State of S in user order, masses included.
+int user_state(sl_system *S, std::vector<double> &r, std::vector<double> &v,
+               std::vector<double> &sp, std::vector<double> &m) {
+  const int n = S->n;
+  r.resize(3 * (size_t)n);
+  v.resize(3 * (size_t)n);
+  sp.resize(3 * (size_t)n);
+  m.resize(n);
+  CHK(sl_get_state(S, r.data(), v.data(), sp.data(), SL_HOST));
+  std::vector<double> mi(n);
+  std::vector<int> id(n);
+  Atoms &A = S->a[S->cur];
+  HIPCHK(S, hipMemcpy(mi.data(), A.mass, sizeof(double) * n, hipMemcpyDeviceToHost));
+  HIPCHK(S, hipMemcpy(id.data(), A.id, sizeof(int) * n, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) m[id[i]] = mi[i];
+  if (S->prec == SL_FP32)  // FP32 spins are unit to FP32 rounding only
+    for (int i = 0; i < n; ++i) {
+      double *q = &sp[3 * (size_t)i];
+      const double inv = 1.0 / std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+      q[0] *= inv; q[1] *= inv; q[2] *= inv;
+    }
+  return SL_OK;
+}
+
+// Scratch copy of S (parameters, interactions, learned potential, user
+// list, state and step counter) on its own stream.
+int clone_system(sl_system *S, sl_system **out) {
+  *out = nullptr;
+  CHK(sl_synchronize(S));
+  sl_params p = S->prm;
+  p.stream = nullptr;
+  p.skin = S->skin;
+  p.max_nbr = S->max_nbr;
+  p.max_spin_nbr = S->max_spin;
+  sl_system *C = nullptr;
+  int rc = sl_create(&p, &C);
+  if (rc) return fail(S, rc, std::string("autotune copy: ") + sl_last_error(nullptr));
+  auto bail = [&](int code) {
+    const std::string e = C->last_err;
+    sl_destroy(C);
+    return fail(S, code, "autotune copy: " + e);
+  };
+  if ((rc = sl_set_potential(C, &S->pot))) return bail(rc);
+  std::vector<double> r, v, sp, m;
+  CHK(user_state(S, r, v, sp, m));
+  if ((rc = sl_set_state(C, r.data(), v.data(), sp.data(), m.data(), SL_HOST))) return bail(rc);
+  if (S->user_list) {
+    const int n = S->n;
+    std::vector<int> ns(n), na(n);
+    const int64_t tot = sl_get_neighbor_list(S, ns.data(), na.data(), nullptr, 0);
+    if (tot < 0) return bail((int)tot);
+    std::vector<int> idx(std::max<int64_t>(tot, 1)), off(n + 1, 0);
+    const int64_t t2 = sl_get_neighbor_list(S, ns.data(), na.data(), idx.data(), tot);
+    if (t2 < 0) return bail((int)t2);
+    for (int i = 0; i < n; ++i) off[i + 1] = off[i] + na[i];
+    if ((rc = sl_set_neighbor_list(C, off.data(), idx.data(), SL_HOST))) return bail(rc);
+  }
+  if (S->mlp && (rc = sl_set_mlp(C, S->mlp))) return bail(rc);
+  if ((rc = sl_set_step(C, S->step))) return bail(rc);
+  *out = C;
+  return SL_OK;
+}
+
+// Optional cache of tuned shapes: one JSON object per line in the file named
+// by SL_TUNE_CACHE, keyed by the device and the workload's shape.
+std::string tune_key(const std::string &what) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  return arch + " " + what;
+}
+
+bool cache_lookup(const std::string &key, int vals[3]) {
+  const char *path = std::getenv("SL_TUNE_CACHE");
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  const std::string want = "{\"key\": \"" + key + "\"";
+  while (std::fgets(line, sizeof(line), f)) {
+    if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
+    const char *q = std::strstr(line, "\"vals\": [");
+    if (q && std::sscanf(q, "\"vals\": [%d, %d, %d]", &vals[0], &vals[1], &vals[2]) == 3) found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const std::string &key, const int vals[3]) {
+  const char *path = std::getenv("SL_TUNE_CACHE");
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"vals\": [%d, %d, %d]}\n", key.c_str(), vals[0], vals[1], vals[2]);
+  std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sl_autotune(sl_system *S, int steps, double dt, sl_tuning *chosen) {
+  if (!S || steps < 1 || !std::isfinite(dt) || dt == 0.0) return fail(S, SL_E_ARG, "bad autotune arguments");
+  CHK(ensure_ready(S));
+  const std::string key = tune_key(
+      "system n=" + std::to_string(S->n) + " prec=" + std::to_string(S->prec) +
+      " frozen=" + std::to_string(S->prm.frozen) + " langevin=" + std::to_string(S->pc.langevin) +
+      " aniso=" + std::to_string(S->pc.aniso_on) + " mlp=" + std::to_string(S->mlp ? 1 : 0) +
+      " K=" + std::to_string(S->K));
+  int v[3];
+  if (!cache_lookup(key, v)) {
+    sl_system *C = nullptr;
+    CHK(clone_system(S, &C));
+    // (spin lanes, force lanes) trials; spin lanes are judged by the
+    // spin-phase kernel time, force lanes by the force kernel time
+    const int trial[3][2] = {{1, 1}, {2, 2}, {4, 1}};
+    double spin_us[3] = {0, 0, 0}, force_us[3] = {0, 0, 0};
+    int rc = SL_OK;
+    for (int t = 0; t < 3 && rc == SL_OK; ++t) {
+      sl_tuning tt{trial[t][0], trial[t][1], S->small_class};
+      if ((rc = sl_set_tuning(C, &tt))) break;
+      if ((rc = sl_step(C, 2, dt))) break;
+      if ((rc = sl_set_profiling(C, 1))) break;
+      if ((rc = sl_step(C, steps, dt))) break;
+      if ((rc = sl_synchronize(C))) break;
+      int64_t l0 = 0, l1 = 0;
+      double m0 = 0, m1 = 0, w0 = 0, w1 = 0;
+      sl_get_profile(C, 0, &l0, &m0, &w0);
+      sl_get_profile(C, 1, &l1, &m1, &w1);
+      spin_us[t] = l0 ? 1e3 * m0 / l0 : 0.0;
+      force_us[t] = l1 ? 1e3 * m1 / l1 : 0.0;
+      rc = sl_set_profiling(C, 0);
+    }
+    const std::string err = rc ? C->last_err : std::string();
+    sl_destroy(C);
+    if (rc) return fail(S, rc, "autotune trial: " + err);
+    int bs = 0;
+    for (int t = 1; t < 3; ++t)
+      if (spin_us[t] < spin_us[bs]) bs = t;
+    const double f1 = 0.5 * (force_us[0] + force_us[2]), f2 = force_us[1];
+    v[0] = trial[bs][0];
+    v[1] = (S->prm.frozen || f1 <= f2) ? 1 : 2;
+    v[2] = S->small_class;
+    cache_store(key, v);
+  }
+  sl_tuning t{v[0], v[1], v[2]};
+  CHK(sl_set_tuning(S, &t));
+  if (chosen) *chosen = t;
+  return SL_OK;
+}
+
+}  // extern "C"
+
 // ============================================================================
 // Batched replicas.
 namespace {
@@ -1746,6 +1910,8 @@ struct sl_batch {
   int graph_lanes = -1;
   int lanes = 2;
   int mode = SL_BATCH_PHASED;
+  std::vector<sl_params> params;     // creation parameters, for autotune clones
+  std::vector<sl_potential> pots;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int64_t launches = 0, rebuilds = 0;
   std::string last_err;
@@ -2080,6 +2246,8 @@ int sl_batch_create(int R, const sl_params *params, const sl_potential *pots, sl
     }
   B->sys.assign(R, nullptr);
   B->rep.assign(R, BatchRep());
+  B->params.assign(params, params + R);
+  B->pots.assign(pots, pots + R);
   for (int r = 0; r < R; ++r) {
     sl_params p = params[r];
     p.stream = B->st;
@@ -2147,6 +2315,60 @@ int sl_batch_step(sl_batch *B, int64_t n, double dt) {
     return B->prec == SL_FP64 ? batch_step_phased<double>(B, n, dt)
                               : batch_step_phased<float>(B, n, dt);
   return B->prec == SL_FP64 ? batch_step<double>(B, n, dt) : batch_step<float>(B, n, dt);
+}
+
+
+int sl_batch_autotune(sl_batch *B, int steps, double dt, int *mode, int *lanes) {
+  if (!B || steps < 1 || !std::isfinite(dt) || dt == 0.0) return bfail(B, SL_E_ARG, "bad autotune arguments");
+  std::string what = "batch R=" + std::to_string(B->R) + " prec=" + std::to_string(B->prec);
+  int64_t natoms = 0;
+  for (auto *S : B->sys) natoms += S->n;
+  what += " atoms=" + std::to_string(natoms);
+  const std::string key = tune_key(what);
+  int v[3];
+  if (!cache_lookup(key, v)) {
+    sl_batch *C = nullptr;
+    int rc = sl_batch_create(B->R, B->params.data(), B->pots.data(), &C);
+    if (rc) return bfail(B, rc, std::string("autotune copy: ") + sl_batch_last_error(nullptr));
+    for (int r = 0; r < B->R && rc == SL_OK; ++r) {
+      sl_system *S = B->sys[r];
+      std::vector<double> x, vv, sp, m;
+      if ((rc = user_state(S, x, vv, sp, m))) break;
+      if ((rc = sl_batch_set_state(C, r, x.data(), vv.data(), sp.data(), m.data(), SL_HOST))) break;
+      if ((rc = sl_set_step(C->sys[r], S->step))) break;
+    }
+    // (mode, lanes) trials timed on the whole batch
+    const int trial[5][2] = {{SL_BATCH_PHASED, 1}, {SL_BATCH_PHASED, 2}, {SL_BATCH_PHASED, 4},
+                             {SL_BATCH_PERSISTENT, 1}, {SL_BATCH_PERSISTENT, 2}};
+    double best = 1e300;
+    v[0] = B->mode;
+    v[1] = B->lanes;
+    v[2] = 0;
+    for (int t = 0; t < 5 && rc == SL_OK; ++t) {
+      C->mode = trial[t][0];
+      C->lanes = trial[t][1];
+      if ((rc = sl_batch_step(C, 2, dt))) break;
+      if (hipStreamSynchronize(C->st) != hipSuccess) { rc = SL_E_HIP; break; }
+      const auto t0 = std::chrono::steady_clock::now();
+      if ((rc = sl_batch_step(C, steps, dt))) break;
+      if (hipStreamSynchronize(C->st) != hipSuccess) { rc = SL_E_HIP; break; }
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (el < best) {
+        best = el;
+        v[0] = trial[t][0];
+        v[1] = trial[t][1];
+      }
+    }
+    const std::string err = rc ? C->last_err : std::string();
+    sl_batch_destroy(C);
+    if (rc) return bfail(B, rc, "autotune trial: " + err);
+    cache_store(key, v);
+  }
+  B->mode = v[0];
+  B->lanes = v[1];
+  if (mode) *mode = v[0];
+  if (lanes) *lanes = v[1];
+  return SL_OK;
 }
 
 int sl_batch_set_mode(sl_batch *B, int mode) {

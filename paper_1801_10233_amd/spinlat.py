@@ -39,14 +39,14 @@ EXPORTS = [
     "sl_set_neighbor", "sl_set_neighbor_list", "sl_get_neighbor_list",
     "sl_set_coloring", "sl_get_coloring", "sl_set_step", "sl_step",
     "sl_get_energy", "sl_get_magnetization", "sl_get_thermo", "sl_get_stats",
-    "sl_synchronize", "sl_set_tuning", "sl_get_tuning", "sl_set_profiling",
+    "sl_synchronize", "sl_set_tuning", "sl_get_tuning", "sl_autotune", "sl_set_profiling",
     "sl_get_profile", "sl_last_error",
     "sl_mlp_create", "sl_mlp_destroy", "sl_mlp_set_weights", "sl_mlp_get_weights",
     "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
     "sl_mlp_loss_grad", "sl_mlp_train",
     "sl_batch_create", "sl_batch_destroy", "sl_batch_set_state", "sl_batch_get_state",
     "sl_batch_get_energy", "sl_batch_step", "sl_batch_set_lanes", "sl_batch_get_stats",
-    "sl_batch_last_error", "sl_batch_set_mode", "sl_batch_get_mode",
+    "sl_batch_last_error", "sl_batch_set_mode", "sl_batch_get_mode", "sl_batch_autotune",
 ]
 
 SL_MLP_NPARAM = 5378
@@ -145,6 +145,7 @@ def lib():
         "sl_synchronize": ([vp], C.c_int),
         "sl_set_tuning": ([vp, C.POINTER(sl_tuning)], C.c_int),
         "sl_get_tuning": ([vp, C.POINTER(sl_tuning)], C.c_int),
+        "sl_autotune": ([vp, C.c_int, C.c_double, C.POINTER(sl_tuning)], C.c_int),
         "sl_set_profiling": ([vp, C.c_int], C.c_int),
         "sl_get_profile": ([vp, C.c_int, C.POINTER(C.c_int64), dp, dp], C.c_int),
         "sl_last_error": ([vp], C.c_char_p),
@@ -171,6 +172,7 @@ def lib():
         "sl_batch_last_error": ([vp], C.c_char_p),
         "sl_batch_set_mode": ([vp, C.c_int], C.c_int),
         "sl_batch_get_mode": ([vp, ip], C.c_int),
+        "sl_batch_autotune": ([vp, C.c_int, C.c_double, ip, ip], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -356,6 +358,13 @@ class System:
         return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
                     small_class=t.small_class)
 
+    def autotune(self, steps, dt):
+        """Time launch shapes on a scratch copy and keep the fastest."""
+        t = sl_tuning()
+        self._check(lib().sl_autotune(self.h, int(steps), float(dt), C.byref(t)))
+        return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
+                    small_class=t.small_class)
+
     def set_mlp(self, mlp):
         self._mlp = mlp
         self._check(lib().sl_set_mlp(self.h, mlp.h if mlp is not None else None))
@@ -523,6 +532,12 @@ class Batch:
         m = C.c_int()
         self._check(lib().sl_batch_get_mode(self.h, C.byref(m)))
         return m.value
+
+    def autotune(self, steps, dt):
+        """Time (mode, lanes) pairs on a scratch copy and keep the fastest."""
+        m = C.c_int(); ln = C.c_int()
+        self._check(lib().sl_batch_autotune(self.h, int(steps), float(dt), C.byref(m), C.byref(ln)))
+        return dict(mode=m.value, lanes=ln.value)
 
     def stats(self):
         a = C.c_int64(); b = C.c_int64(); c = C.c_int()
