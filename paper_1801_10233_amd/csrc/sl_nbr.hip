@@ -83,42 +83,76 @@ __global__ void k_bucket_sort(int nbucket, const int *start, int *items) {
 
 // Full neighbour rows from the 27 surrounding cells (fewer when a side has
 // under three cells: then that side is one cell and the minimum image
-// covers it). Pass 0 writes the spin segment (r^2 < rs2), pass 1 the rest
-// (rs2 <= r^2 < rl2). Entries are in cell order, atoms ascending inside a
-// cell, so the row order is deterministic.
-__global__ void k_nbr_build(NbrBuildArgs A) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n) return;
-  const double rix = A.rx[i], riy = A.ry[i], riz = A.rz[i];
-  const int c = A.cell[i];
-  const int cx = c % A.G.nc[0], cy = (c / A.G.nc[0]) % A.G.nc[1], cz = c / (A.G.nc[0] * A.G.nc[1]);
+// covers it). The spin segment (r^2 < rs2) comes first, then the rest of
+// the row (rs2 <= r^2 < rl2); inside each segment entries follow the cell
+// loop order, atoms ascending inside a cell, so rows are deterministic.
+// kNbrLanes lanes share one atom, each scanning a contiguous run of the
+// cells: a counting sweep, a segmented prefix sum over the lanes, then a
+// writing sweep that puts every entry at its place in that order. This cuts
+// the serial chain per thread ~16x (small systems have few atoms to spread
+// over the device, so the one-thread-per-atom build was latency bound).
+constexpr int kNbrLanes = 16;
+
+__global__ __launch_bounds__(kBlock) void k_nbr_build(NbrBuildArgs A) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / kNbrLanes), l = (int)(t % kNbrLanes);
+  const bool valid = i < A.n;
   const int ox = A.G.nc[0] >= 3 ? 1 : 0, oy = A.G.nc[1] >= 3 ? 1 : 0, oz = A.G.nc[2] >= 3 ? 1 : 0;
+  const int wx = 2 * ox + 1, wy = 2 * oy + 1, M = wx * wy * (2 * oz + 1);
+  const int m0 = M * l / kNbrLanes, m1 = M * (l + 1) / kNbrLanes;
   const double Lx = A.G.L[0], Ly = A.G.L[1], Lz = A.G.L[2];
   const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
-  int ns = 0, nt = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int dz = -oz; dz <= oz; ++dz)
-      for (int dy = -oy; dy <= oy; ++dy)
-        for (int dx = -ox; dx <= ox; ++dx) {
-          const int qx = (cx + dx + A.G.nc[0]) % A.G.nc[0];
-          const int qy = (cy + dy + A.G.nc[1]) % A.G.nc[1];
-          const int qz = (cz + dz + A.G.nc[2]) % A.G.nc[2];
-          const int q = (qz * A.G.nc[1] + qy) * A.G.nc[0] + qx;
-          for (int p = A.cstart[q]; p < A.cstart[q + 1]; ++p) {
-            const int j = A.catoms[p];
-            if (j == i) continue;
-            const double ddx = min_image(rix - A.rx[j], Lx, iLx);
-            const double ddy = min_image(riy - A.ry[j], Ly, iLy);
-            const double ddz = min_image(riz - A.rz[j], Lz, iLz);
-            const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-            const bool take = pass == 0 ? (r2 < A.rs2) : (r2 >= A.rs2 && r2 < A.rl2);
-            if (!take) continue;
-            if (nt < A.max_nbr) A.nbr[(size_t)nt * A.ld + i] = j;
-            ++nt;
-            if (pass == 0) ++ns;
+  double rix = 0, riy = 0, riz = 0;
+  int cx = 0, cy = 0, cz = 0;
+  if (valid) {
+    rix = A.rx[i]; riy = A.ry[i]; riz = A.rz[i];
+    const int c = A.cell[i];
+    cx = c % A.G.nc[0]; cy = (c / A.G.nc[0]) % A.G.nc[1]; cz = c / (A.G.nc[0] * A.G.nc[1]);
+  }
+  int cnt[2] = {0, 0};   // spin, rest
+  int off[2] = {0, 0};
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    if (valid)
+      for (int m = m0; m < m1; ++m) {
+        const int dx = m % wx - ox, dy = (m / wx) % wy - oy, dz = m / (wx * wy) - oz;
+        const int qx = (cx + dx + A.G.nc[0]) % A.G.nc[0];
+        const int qy = (cy + dy + A.G.nc[1]) % A.G.nc[1];
+        const int qz = (cz + dz + A.G.nc[2]) % A.G.nc[2];
+        const int q = (qz * A.G.nc[1] + qy) * A.G.nc[0] + qx;
+        for (int p = A.cstart[q]; p < A.cstart[q + 1]; ++p) {
+          const int j = A.catoms[p];
+          if (j == i) continue;
+          const double ddx = min_image(rix - A.rx[j], Lx, iLx);
+          const double ddy = min_image(riy - A.ry[j], Ly, iLy);
+          const double ddz = min_image(riz - A.rz[j], Lz, iLz);
+          const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          if (r2 >= A.rl2 && r2 >= A.rs2) continue;
+          const int seg = r2 < A.rs2 ? 0 : 1;
+          if (sweep == 0) {
+            ++cnt[seg];
+          } else {
+            const int k = off[seg]++;
+            if (k < A.max_nbr) A.nbr[(size_t)k * A.ld + i] = j;
           }
         }
+      }
+    if (sweep == 0) {
+      // inclusive scans of both counts over the lanes of this atom
+      int ps = cnt[0], pr = cnt[1];
+#pragma unroll
+      for (int o = 1; o < kNbrLanes; o <<= 1) {
+        const int a = __shfl_up(ps, o, kNbrLanes), b = __shfl_up(pr, o, kNbrLanes);
+        if (l >= o) { ps += a; pr += b; }
+      }
+      const int ts = __shfl(ps, kNbrLanes - 1, kNbrLanes), tr = __shfl(pr, kNbrLanes - 1, kNbrLanes);
+      off[0] = ps - cnt[0];
+      off[1] = ts + pr - cnt[1];
+      cnt[0] = ts;
+      cnt[1] = tr;
+    }
   }
+  if (!valid || l != 0) return;
+  const int ns = cnt[0], nt = cnt[0] + cnt[1];
   if (nt > A.max_nbr || ns > A.max_spin) atomicOr(A.err, kErrNbrOverflow);
   atomicMax(&A.seen[0], ns);
   atomicMax(&A.seen[1], nt);
@@ -366,7 +400,8 @@ void launch_bucket_sort(int nbucket, const int *start, int *items, hipStream_t s
   if (nbucket > 0) hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks(nbucket)), dim3(kBlock), 0, st, nbucket, start, items);
 }
 void launch_nbr_build(const NbrBuildArgs &A, hipStream_t st) {
-  if (A.n > 0) hipLaunchKernelGGL(k_nbr_build, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A);
+  const long threads = (long)A.n * kNbrLanes;
+  if (A.n > 0) hipLaunchKernelGGL(k_nbr_build, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, A);
 }
 void launch_keys(int n, const double *rx, const double *ry, const double *rz, const double L[3],
                  double *kx, double *ky, double *kz, hipStream_t st) {
