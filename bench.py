@@ -127,7 +127,8 @@ def timed_run(S, steps, dt, profile=False):
     t1 = time.perf_counter()
     prof = None
     if profile:
-        prof = {k: S.profile(k) for k in (sl.PROF_SPIN, sl.PROF_FORCE, sl.PROF_REBUILD)}
+        prof = {k: S.profile(k) for k in (sl.PROF_SPIN, sl.PROF_FORCE, sl.PROF_REBUILD,
+                                          sl.PROF_TABLE)}
         S.set_profiling(False)
     return t1 - t0, prof
 
@@ -151,11 +152,56 @@ def batched_throughput(steps, tune=True):
                 dtype="f32", tuned=tuned, stats=st)
 
 
-def drift_per_10ps(w, precision, steps, every=10, settle=2000):
+MLP_WEIGHTS = os.path.join(ROOT, "paper_1801_10233_amd", "data", "mlp_bj_weights.npy")
+
+
+def load_mlp():
+    m = sl.Mlp()
+    m.set_weights(np.load(MLP_WEIGHTS, allow_pickle=False))
+    return m
+
+
+def mlp_form(w, steps, warmup, tune):
+    """The learned potential (BF16-MFMA table, FP32 bulk) on the same
+    workload: throughput, then its forces, hbar*omega and pair + exchange
+    energy against the analytic FP64 path at the state it reached."""
+    m = load_mlp()
+    S = sl.system_from_workload(w, precision=sl.SL_FP32)
+    S.set_mlp(m)
+    S.step(0, w.dt)
+    if tune:
+        S.autotune(20, w.dt)
+    S.step(warmup, w.dt)
+    el, prof = timed_run(S, steps, w.dt, profile=True)
+    kinds = {name: dict(launches=k[0], avg_us=round(k[1] / max(k[0], 1) * 1e3, 3))
+             for name, k in (("k_spin_phase", prof[sl.PROF_SPIN]),
+                             ("k_force", prof[sl.PROF_FORCE]),
+                             ("k_mlp_table", prof[sl.PROF_TABLE]))}
+    r, v, s = S.get_state()
+    Fm, hm = S.fields()
+    em = S.energy()
+    A = sl.system_from_workload(w, precision=sl.SL_FP64)
+    s = s / np.linalg.norm(s, axis=1)[:, None]      # FP32 spins are unit to FP32 rounding
+    A.set_state(r, v, s, w.mass)
+    Fa, ha = A.fields()
+    ea = A.energy()
+    S.close()
+    A.close()
+    value = w.N * steps / el
+    return dict(value=round(value, 1), ms_per_step=round(el / steps * 1e3, 4), kernels=kinds,
+                force_rel_rms_vs_fp64=float(np.sqrt(np.sum((Fm - Fa) ** 2) / np.sum(Fa ** 2))),
+                hbar_omega_rel_rms_vs_fp64=float(np.sqrt(np.sum((hm - ha) ** 2) / np.sum(ha ** 2))),
+                pair_exchange_energy_err_eV_per_atom=float(
+                    (em["pair"] + em["exchange"] - ea["pair"] - ea["exchange"]) / w.N)), m
+
+
+def drift_per_10ps(w, precision, steps, every=10, settle=2000, mlp=None):
     """Least-squares slope of E_total/N against time on the undamped twin,
     scaled to 10 ps, over `steps` steps after `settle` steps in which the
     spin and lattice subsystems start exchanging energy."""
     S = sl.system_from_workload(w, precision=precision, thermo_every=every)
+    if mlp is not None:
+        S.set_mlp(mlp)
     S.step(settle + steps, w.dt)
     st, E, _ = S.thermo()
     keep = st > settle
@@ -303,10 +349,15 @@ def main():
         twin = W.large_langevin(n=args.n, nve=True)
         d64, f64 = drift_per_10ps(twin, sl.SL_FP64, args.drift_steps)
         d32, f32 = drift_per_10ps(twin, sl.SL_FP32, args.drift_steps)
+        mform, mlp = mlp_form(w, args.steps, args.warmup, not args.no_tune)
+        dml, fml = drift_per_10ps(twin, sl.SL_FP32, args.drift_steps, mlp=mlp)
         out["forms"] = dict(
             fp64=dict(value=round(value, 1), drift_eV_per_atom_per_10ps=d64, E_rms_eV_per_atom=f64),
             fp32=dict(value=round(v32, 1), speedup_vs_fp64=round(v32 / value, 3),
                       drift_eV_per_atom_per_10ps=d32, E_rms_eV_per_atom=f32),
+            mlp=dict(mform, speedup_vs_fp64=round(mform["value"] / value, 3),
+                     drift_eV_per_atom_per_10ps=dml, E_rms_eV_per_atom=fml,
+                     weights="paper_1801_10233_amd/data/mlp_bj_weights.npy (train_mlp.py)"),
             drift_run=f"undamped twin, 2000 settling steps then {args.drift_steps} steps "
                       f"({args.drift_steps * twin.dt:.2f} ps), E sampled every 10 steps, "
                       "least-squares slope scaled to 10 ps")

@@ -267,11 +267,23 @@ const char *sl_mlp_last_error(const sl_mlp *m);
 
 /* Use the learned potential for J and the mechanical pair energy of this
  * system (replacing Morse and Bethe-Slater; Zeeman, anisotropy and the bath
- * are kept); NULL restores the analytic potential. FP32 form only. After
- * every drift the network is evaluated once per unordered pair of the list
- * and the spin phases and the force kernel read that table. The handle must
- * outlive its use; its weights may be changed between sl_step calls. */
+ * are kept); NULL restores the analytic potential. FP32 form only. The
+ * evaluation follows sl_set_mlp_mode. The handle must outlive its use; its
+ * weights may be changed between sl_step calls. */
 int sl_set_mlp(sl_system *sys, sl_mlp *m);
+
+/* How a system evaluates the learned potential.
+ *   SL_MLP_SPLINE (default): the network's raw outputs and r-derivatives
+ *     are tabulated once per weight update (4096 points on [0.5 A, rc], the
+ *     FP32 master weights evaluated in FP64) and every pair takes a cubic
+ *     Hermite interpolant of them; the force is the exact derivative of
+ *     the interpolated energy, so the dynamics conserve the energy that is
+ *     reported.
+ *   SL_MLP_PAIRWISE: after every drift the network itself is evaluated
+ *     once per unordered pair of the list (BF16 MFMA, FP32 accumulation;
+ *     value and r-tangent streams) and the kernels read that table. */
+enum { SL_MLP_PAIRWISE = 0, SL_MLP_SPLINE = 1 };
+int sl_set_mlp_mode(sl_system *sys, int mode);
 
 /* Per-atom force F_i = sum_j [-phi'(r) + J'(r) s_i.s_j] e_ij (Eq. p_advance)
  * and exchange part of hbar omega_i = sum_j J(r_ij) s_j (Sec. 2) of the

@@ -105,6 +105,7 @@ struct sl_system {
   // learned potential (FP32 form): unordered pairs of the list with their
   // mirror slots, and one (J, J', phi, phi') table per position buffer
   sl_mlp *mlp = nullptr;
+  int mlp_mode = SL_MLP_SPLINE;  // how the learned potential is evaluated
   int2 *mpairs = nullptr;
   int *mirror = nullptr, *mcnt = nullptr, *mstart = nullptr;
   int npair = 0, mpair_cap = 0;
@@ -146,9 +147,11 @@ template <typename T>
 hipError_t dalloc(T **p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-  if (e == hipSuccess) e = hipMemset(*p, 0, count * sizeof(T));
-  return e;
+  // Not cleared: a clear on the null stream would not be ordered with the
+  // library's non-blocking stream. Every buffer is written before it is read
+  // (list slots past a row's end are masked, and gathered indices are
+  // range-checked before use).
+  return hipMalloc((void **)p, count * sizeof(T));
 }
 
 void dfree(void *p) {
@@ -236,7 +239,10 @@ SysView<real> view(sl_system *S, int posbuf) {
   v.nspin = A.nspin;
   v.nall = A.nall;
   v.id = A.id;
-  v.tab = S->mlp ? S->tab[posbuf] : nullptr;
+  v.tab = nullptr;
+  v.spl = SplineView{};
+  if (S->mlp && S->mlp_mode == SL_MLP_SPLINE) v.spl = S->mlp->spline_view();
+  else if (S->mlp) v.tab = S->tab[posbuf];
   return v;
 }
 
@@ -471,7 +477,7 @@ int mlp_pairs(sl_system *S) {
 
 // Table of the learned potential at the positions of buffer b.
 int ensure_table(sl_system *S, int b) {
-  if (!S->mlp || S->tab_ok[b]) return SL_OK;
+  if (!S->mlp || S->mlp_mode != SL_MLP_PAIRWISE || S->tab_ok[b]) return SL_OK;
   Atoms &A = S->a[S->cur];
   MlpTableArgs T;
   T.npair = S->npair;
@@ -1298,7 +1304,8 @@ int sl_set_coloring(sl_system *S, const int *colour, int where) {
   CHK(read_err(S));
   if (S->sticky & kErrColour) {
     S->sticky &= ~kErrColour;
-    HIPCHK(S, hipMemset(S->err, 0, sizeof(int)));
+    HIPCHK(S, hipMemsetAsync(S->err, 0, sizeof(int), S->st));
+    HIPCHK(S, hipStreamSynchronize(S->st));
     S->have_colour = false;
     return fail(S, SL_E_COLOR, "colouring puts two interacting spins in one class");
   }
@@ -1440,6 +1447,15 @@ int sl_set_mlp(sl_system *S, sl_mlp *m) {
   return SL_OK;
 }
 
+int sl_set_mlp_mode(sl_system *S, int mode) {
+  if (!S || !(mode == SL_MLP_PAIRWISE || mode == SL_MLP_SPLINE))
+    return fail(S, SL_E_ARG, "mode must be SL_MLP_PAIRWISE or SL_MLP_SPLINE");
+  CHK(sl_synchronize(S));
+  S->mlp_mode = mode;
+  S->tab_ok[0] = S->tab_ok[1] = false;
+  return SL_OK;
+}
+
 int sl_set_tuning(sl_system *S, const sl_tuning *t) {
   if (!S || !t) return fail(S, SL_E_ARG, "NULL argument");
   auto ok = [](int x) { return x == 0 || x == 1 || x == 2 || x == 4 || x == 8; };
@@ -1552,6 +1568,8 @@ int mlp_trainer(sl_mlp *m, const sl_dataset *d) {
       sl_destroy(S);
       return mfail_str(m, rc, "trainer: " + e);
     }
+    // training differentiates the network at every pair: per-pair table
+    S->mlp_mode = SL_MLP_PAIRWISE;
     m->trainer = S;
   }
   return SL_OK;

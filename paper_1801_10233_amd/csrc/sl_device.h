@@ -52,6 +52,46 @@ struct PotConst {
 };
 
 // Per-system geometry and arrays (device pointers).
+// Learned pair potential as a cubic Hermite spline of the network's raw
+// outputs (y0, y0', y1, y1') tabulated at r0 + k dr, k = 0..last. The
+// interpolant's derivative is exact, so forces are the gradient of the
+// energy that is reported (the dynamics conserve it).
+struct SplineView {
+  const float4 *t;   // null: no spline
+  float r0, dr, idr;
+  int last;
+  float sJ, sP;      // output scales
+  float y1c, d1c;    // raw y1(rc), y1'(rc) (shifted-force constants)
+  float exrc, rc;    // cuts of J (Heaviside) and phi
+};
+
+// (J, J', phi, phi') at r from the spline (cut and shifted-force rules as
+// for the network itself).
+__device__ __forceinline__ float4 spline_phys(const SplineView &s, float r) {
+  float u = (r - s.r0) * s.idr;
+  u = fminf(fmaxf(u, 0.0f), (float)s.last);
+  const int k = min((int)u, s.last - 1);
+  const float x = u - (float)k, x2 = x * x, x3 = x2 * x;
+  const float4 a = s.t[k], b = s.t[k + 1];
+  const float h00 = 2.0f * x3 - 3.0f * x2 + 1.0f, h10 = x3 - 2.0f * x2 + x;
+  const float h01 = 3.0f * x2 - 2.0f * x3, h11 = x3 - x2;
+  const float g00 = 6.0f * (x2 - x), g10 = 3.0f * x2 - 4.0f * x + 1.0f, g11 = 3.0f * x2 - 2.0f * x;
+  const float y0 = h00 * a.x + h01 * b.x + s.dr * (h10 * a.y + h11 * b.y);
+  const float d0 = g00 * (a.x - b.x) * s.idr + g10 * a.y + g11 * b.y;
+  const float y1 = h00 * a.z + h01 * b.z + s.dr * (h10 * a.w + h11 * b.w);
+  const float d1 = g00 * (a.z - b.z) * s.idr + g10 * a.w + g11 * b.w;
+  float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (r < s.exrc) {
+    o.x = s.sJ * y0;
+    o.y = s.sJ * d0;
+  }
+  if (r < s.rc) {
+    o.z = s.sP * (y1 - s.y1c - (r - s.rc) * s.d1c);
+    o.w = s.sP * (d1 - s.d1c);
+  }
+  return o;
+}
+
 template <typename real>
 struct SysView {
   int n;          // atoms
@@ -65,6 +105,7 @@ struct SysView {
   const int *id;               // user id of each internal atom
   const float4 *tab;           // learned-potential table (J, J', phi, phi') per
                                // list entry at these positions, or null
+  SplineView spl;              // learned potential as a spline (spl.t null: unused)
 };
 
 struct SpinPhaseArgs {

@@ -34,7 +34,7 @@ struct SpinChunk {
   static constexpr int value = LANES >= 8 ? 2 : (LANES >= 4 ? 4 : 8);
 };
 
-template <typename real, bool LANGEVIN, bool ANISO, int LANES, bool MLP>
+template <typename real, bool LANGEVIN, bool ANISO, int LANES, int MLP>
 __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotConst &P, int i,
                                             bool valid, int l, int nrep, const int64_t *step,
                                             const int *sub, double hd, double ampd,
@@ -70,7 +70,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
       float jt[CH];
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
-        if (MLP) {
+        if (MLP == 1) {
           const int k = base + LANES * c;
           jt[c] = k < S.kcap ? S.tab[(size_t)k * ld + i].x : 0.f;
         } else {
@@ -83,8 +83,14 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         const bool in = base + LANES * c < ns;
-        if (MLP) {
+        if (MLP == 1) {
           J[c] = in ? (real)jt[c] : (real)0;
+        } else if (MLP == 2) {
+          const double dx = min_image(rix - px[c], S.L[0], S.invL[0]);
+          const double dy = min_image(riy - py[c], S.L[1], S.invL[1]);
+          const double dz = min_image(riz - pz[c], S.L[2], S.invL[2]);
+          const float r = (float)sqrt(dx * dx + dy * dy + dz * dz);
+          J[c] = in ? (real)spline_phys(S.spl, r).x : (real)0;
         } else {
           const double dx = min_image(rix - px[c], S.L[0], S.invL[0]);
           const double dy = min_image(riy - py[c], S.L[1], S.invL[1]);
@@ -152,7 +158,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
   S.sz[i] = sz;
 }
 
-template <typename real, bool LANGEVIN, bool ANISO, int LANES, bool MLP>
+template <typename real, bool LANGEVIN, bool ANISO, int LANES, int MLP>
 __global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst P,
                                                        SpinPhaseArgs A) {
   // LANES consecutive lanes share one atom: each gathers every LANES-th
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst
 // adds) in one workgroup: the items are applied in order with a workgroup
 // barrier between them, which keeps the class order of the sweep while
 // paying one launch for the whole run.
-template <typename real, bool LANGEVIN, bool ANISO, int LANES, bool MLP>
+template <typename real, bool LANGEVIN, bool ANISO, int LANES, int MLP>
 __global__ __launch_bounds__(kTailBlock) void k_spin_tail(SysView<real> S, PotConst P,
                                                           TailArgs T) {
   const int l = threadIdx.x & (LANES - 1);
@@ -201,7 +207,7 @@ __global__ __launch_bounds__(kTailBlock) void k_spin_tail(SysView<real> S, PotCo
 // the first lane the kicks, the drift into the other position buffer, the
 // energy terms e[8] = (kin, pair, exchange, Zeeman, aniso, Mx, My, Mz) and
 // the rebuild predictor terms |r - r_build| and |v|.
-template <typename real, int MODE, int LANES, bool MLP>
+template <typename real, int MODE, int LANES, int MLP>
 __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotConst &P,
                                            const ForceArgs &A, int i, bool valid, int l,
                                            double e[8], double &dm, double &vm, double &wm) {
@@ -246,7 +252,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
 #pragma unroll
           for (int c = 0; c < kForceChunk; ++c) sij[c] = 0;
         }
-        if (MLP) {
+        if (MLP == 1) {
 #pragma unroll
           for (int c = 0; c < kForceChunk; ++c) {
             const int k = base + LANES * c;
@@ -265,6 +271,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           const double rinvd = rsqrt_nr(r2d);
           const real r = (real)(r2d * rinvd), rinv = (real)rinvd;
           real cc = 0;
+          if (MLP == 2) tt[c] = use ? spline_phys(S.spl, (float)r) : make_float4(0.f, 0.f, 0.f, 0.f);
           if (MLP) {
             // learned phi'(r), J'(r) (and phi, J for energies) from the table
             cc = -(real)tt[c].w + (real)tt[c].y * sij[c];
@@ -351,7 +358,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
   }
 }
 
-template <typename real, int MODE, int LANES, bool MLP>
+template <typename real, int MODE, int LANES, int MLP>
 __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
   __shared__ double red[kBlock / 64][8];
   __shared__ double redm[kBlock / 64][3];
@@ -465,7 +472,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
         const int b0 = d.off[c], b1 = d.off[c + 1];
         for (int base = b0; base < b1; base += per) {
           const int i = base + t / LANES;
-          spin_update<real, true, true, LANES, false>(V, d.P, i, i < b1, l, nrep, st, sb, d.h, d.amp,
+          spin_update<real, true, true, LANES, 0>(V, d.P, i, i < b1, l, nrep, st, sb, d.h, d.amp,
                                                      d.seed, d.replica, d.rs2);
         }
         __syncthreads();
@@ -484,8 +491,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
     for (int base = 0; base < W.n; base += per) {
       const int i = base + t / LANES;
       double e[8], dm = 0.0, vm = 0.0, wm = kInf;
-      if (next) force_atom<real, kModeFinal | kModeNext, LANES, false>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
-      else force_atom<real, kModeFinal, LANES, false>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
+      if (next) force_atom<real, kModeFinal | kModeNext, LANES, 0>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
+      else force_atom<real, kModeFinal, LANES, 0>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
       bdm = fmax(bdm, dm);
       bvm = fmax(bvm, vm);
       bwm = fmin(bwm, wm);
@@ -564,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_spin(const RepDesc<real> *D, B
   const int64_t step = d.step + bp.kk;
   const int64_t st[kMaxRep] = {step, step, step, step};
   const int sb[kMaxRep] = {s0, s1, 0, 0};
-  spin_update<real, true, true, LANES, false>(d.V[bp.half == 0 ? pos : 1 - pos], d.P, i, i < b1,
+  spin_update<real, true, true, LANES, 0>(d.V[bp.half == 0 ? pos : 1 - pos], d.P, i, i < b1,
                                              l, nrep, st, sb, d.h, d.amp, d.seed, d.replica,
                                              d.rs2);
 }
@@ -592,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, 
   F.host_out = d.ring + 8 * (int)(boundary & 3);
   const int i = (int)blockIdx.x * per + (int)threadIdx.x / LANES, l = threadIdx.x & (LANES - 1);
   double e[8], dm = 0.0, vm = 0.0, wm = kInf;
-  force_atom<real, MODE, LANES, false>(d.V[cur], d.P, F, i, i < n, l, e, dm, vm, wm);
+  force_atom<real, MODE, LANES, 0>(d.V[cur], d.P, F, i, i < n, l, e, dm, vm, wm);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double a = wave_max(dm), b = wave_max(vm), c = wave_min(wm);
   if (lane == 0) { redm[wv][0] = a; redm[wv][1] = b; redm[wv][2] = c; }
@@ -686,7 +693,7 @@ __global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, 
 // ---------------------------------------------------------------------------
 // Host launchers. The learned-potential variants (table lookups instead of
 // the analytic J and V) exist in the FP32 form only.
-template <typename real, int LANES, bool MLP>
+template <typename real, int LANES, int MLP>
 static void spin_phase_lanes2(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
                               hipStream_t st) {
   const long threads = (long)(A.end - A.begin) * LANES;
@@ -701,8 +708,9 @@ static void spin_phase_lanes2(const SysView<real> &S, const PotConst &P, const S
 template <typename real, int LANES>
 static void spin_phase_lanes(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
                              hipStream_t st) {
-  if (sizeof(real) == 4 && S.tab) spin_phase_lanes2<real, LANES, (sizeof(real) == 4)>(S, P, A, st);
-  else spin_phase_lanes2<real, LANES, false>(S, P, A, st);
+  if (sizeof(real) == 4 && S.spl.t) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
+  else if (sizeof(real) == 4 && S.tab) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, st);
+  else spin_phase_lanes2<real, LANES, 0>(S, P, A, st);
 }
 
 template <typename real>
@@ -717,7 +725,7 @@ void launch_spin_phase(const SysView<real> &S, const PotConst &P, const SpinPhas
   }
 }
 
-template <typename real, int LANES, bool MLP>
+template <typename real, int LANES, int MLP>
 static void spin_tail_lanes2(const SysView<real> &S, const PotConst &P, const TailArgs &T,
                              hipStream_t st) {
   const bool lg = P.langevin != 0, an = P.aniso_on != 0;
@@ -730,8 +738,9 @@ static void spin_tail_lanes2(const SysView<real> &S, const PotConst &P, const Ta
 template <typename real, int LANES>
 static void spin_tail_lanes(const SysView<real> &S, const PotConst &P, const TailArgs &T,
                             hipStream_t st) {
-  if (sizeof(real) == 4 && S.tab) spin_tail_lanes2<real, LANES, (sizeof(real) == 4)>(S, P, T, st);
-  else spin_tail_lanes2<real, LANES, false>(S, P, T, st);
+  if (sizeof(real) == 4 && S.spl.t) spin_tail_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, T, st);
+  else if (sizeof(real) == 4 && S.tab) spin_tail_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, T, st);
+  else spin_tail_lanes2<real, LANES, 0>(S, P, T, st);
 }
 
 template <typename real>
@@ -746,7 +755,7 @@ void launch_spin_tail(const SysView<real> &S, const PotConst &P, const TailArgs 
   }
 }
 
-template <typename real, int LANES, bool MLP>
+template <typename real, int LANES, int MLP>
 static void force_lanes2(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
                          hipStream_t st) {
   const long threads = (long)S.n * LANES;
@@ -764,8 +773,9 @@ static void force_lanes2(const SysView<real> &S, const PotConst &P, const ForceA
 template <typename real, int LANES>
 static void force_lanes(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
                         hipStream_t st) {
-  if (sizeof(real) == 4 && S.tab) force_lanes2<real, LANES, (sizeof(real) == 4)>(S, P, A, st);
-  else force_lanes2<real, LANES, false>(S, P, A, st);
+  if (sizeof(real) == 4 && S.spl.t) force_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
+  else if (sizeof(real) == 4 && S.tab) force_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, st);
+  else force_lanes2<real, LANES, 0>(S, P, A, st);
 }
 
 // Blocks needed by a force launch (rows of the partial-sum buffer).

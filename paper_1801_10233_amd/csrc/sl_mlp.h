@@ -85,5 +85,9 @@ void launch_mlp_eval(const float *r, int P, const MlpDevWeights *w, const MlpCfg
                      const float *yc, int raw, float4 *out, hipStream_t st);
 void launch_mlp_table(const MlpTableArgs &A, const MlpDevWeights *w, const MlpCfgDev &c,
                       const float *yc, hipStream_t st);
+// Raw outputs (y0, y0', y1, y1') of the FP32 master network evaluated in
+// FP64 at r0 + q dr, q = 0..P-1 (the spline table of the dynamics).
+void launch_mlp_grid(const float *params, double r0, double dr, int P, double sigma,
+                     double mu_step, float4 *out, hipStream_t st);
 
 }  // namespace sl

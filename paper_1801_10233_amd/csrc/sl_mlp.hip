@@ -225,6 +225,51 @@ void launch_mlp_eval(const float *r, int P, const MlpDevWeights *w, const MlpCfg
   hipLaunchKernelGGL(k_mlp_eval, dim3(mlp_grid(P)), dim3(256), 0, st, r, P, w, c, yc, raw, out);
 }
 
+// One wavefront per grid distance, lane h = hidden unit h of both layers;
+// FP64 arithmetic on the FP32 master parameters (layout W1[64x16], c1,
+// W2[64x64], c2, W3[2x64], c3), value and r-tangent together. Unlike the
+// BF16 operand path this is smooth in r at the scale of the spline grid.
+__global__ __launch_bounds__(64) void k_mlp_grid(const float *p, double r0, double dr, int P,
+                                                 double sigma, double mu, float4 *out) {
+  __shared__ double a1[64], t1[64];
+  const int q = blockIdx.x, h = threadIdx.x;
+  if (q >= P) return;
+  const float *W1 = p, *c1 = W1 + 64 * 16, *W2 = c1 + 64, *c2 = W2 + 64 * 64;
+  const float *W3 = c2 + 64, *c3 = W3 + 2 * 64;
+  const double r = r0 + q * dr;
+  double z = c1[h], dz = 0.0;
+  for (int k = 0; k < 16; ++k) {
+    const double x = (r - k * mu) / sigma, b = exp(-x * x);
+    z += (double)W1[h * 16 + k] * b;
+    dz += (double)W1[h * 16 + k] * (-2.0 * x / sigma) * b;
+  }
+  double s = 1.0 / (1.0 + exp(-z));
+  a1[h] = z * s;
+  t1[h] = s * (1.0 + z * (1.0 - s)) * dz;
+  __syncthreads();
+  double z2 = c2[h], dz2 = 0.0;
+  for (int k = 0; k < 64; ++k) {
+    z2 += (double)W2[h * 64 + k] * a1[k];
+    dz2 += (double)W2[h * 64 + k] * t1[k];
+  }
+  s = 1.0 / (1.0 + exp(-z2));
+  const double a2 = z2 * s, t2 = s * (1.0 + z2 * (1.0 - s)) * dz2;
+  double y0 = W3[h] * a2, d0 = W3[h] * t2, y1 = W3[64 + h] * a2, d1 = W3[64 + h] * t2;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    y0 += __shfl_xor(y0, o, 64);
+    d0 += __shfl_xor(d0, o, 64);
+    y1 += __shfl_xor(y1, o, 64);
+    d1 += __shfl_xor(d1, o, 64);
+  }
+  if (h == 0) out[q] = make_float4((float)(y0 + c3[0]), (float)d0, (float)(y1 + c3[1]), (float)d1);
+}
+
+void launch_mlp_grid(const float *params, double r0, double dr, int P, double sigma,
+                     double mu_step, float4 *out, hipStream_t st) {
+  if (P > 0) hipLaunchKernelGGL(k_mlp_grid, dim3(P), dim3(64), 0, st, params, r0, dr, P, sigma, mu_step, out);
+}
+
 void launch_mlp_table(const MlpTableArgs &A, const MlpDevWeights *w, const MlpCfgDev &c,
                       const float *yc, hipStream_t st) {
   if (A.npair <= 0) return;
@@ -574,7 +619,7 @@ namespace sl {
 // learned-potential table; with references, also the loss residual terms:
 //   gF_i = 2 wF (F_i - Fref_i)/(3N),  gW_i = 2 wW (hw_i - hwref_i)/(3N),
 //   lossp_i = [wF |F_i - Fref_i|^2 + wW |hw_i - hwref_i|^2]/(3N).
-template <typename real, bool MLP>
+template <typename real, int MLP>
 __global__ void k_fields(SysView<real> S, PotConst P, FieldArgs A) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
@@ -592,7 +637,7 @@ __global__ void k_fields(SysView<real> S, PotConst P, FieldArgs A) {
     const double sij = six * sjx + siy * sjy + siz * sjz;
     double J = 0, dJ = 0, V = 0, dV = 0;
     if (MLP) {
-      const float4 t = S.tab[(size_t)k * ld + i];
+      const float4 t = MLP == 2 ? spline_phys(S.spl, (float)r) : S.tab[(size_t)k * ld + i];
       J = t.x; dJ = t.y; V = t.z; dV = t.w;
     } else {
       if (P.ex_on && r2 < P.eRc2) {
@@ -697,8 +742,9 @@ __global__ __launch_bounds__(256) void k_sum_f2(const float2 *x, int n, float4 *
 template <typename real>
 void launch_fields(const SysView<real> &S, const PotConst &P, const FieldArgs &A, hipStream_t st) {
   const int nb = (S.n + 255) / 256;
-  if (sizeof(real) == 4 && S.tab) hipLaunchKernelGGL((k_fields<real, (sizeof(real) == 4)>), dim3(nb), dim3(256), 0, st, S, P, A);
-  else hipLaunchKernelGGL((k_fields<real, false>), dim3(nb), dim3(256), 0, st, S, P, A);
+  if (sizeof(real) == 4 && S.spl.t) hipLaunchKernelGGL((k_fields<real, (sizeof(real) == 4 ? 2 : 0)>), dim3(nb), dim3(256), 0, st, S, P, A);
+  else if (sizeof(real) == 4 && S.tab) hipLaunchKernelGGL((k_fields<real, (sizeof(real) == 4 ? 1 : 0)>), dim3(nb), dim3(256), 0, st, S, P, A);
+  else hipLaunchKernelGGL((k_fields<real, 0>), dim3(nb), dim3(256), 0, st, S, P, A);
 }
 template void launch_fields<double>(const SysView<double> &, const PotConst &, const FieldArgs &, hipStream_t);
 template void launch_fields<float>(const SysView<float> &, const PotConst &, const FieldArgs &, hipStream_t);

@@ -64,7 +64,8 @@ int sl_mlp_create(const sl_mlp_spec *spec, sl_mlp **out) {
       hipMalloc((void **)&m->adam_v, sizeof(float) * SL_MLP_NPARAM) != hipSuccess ||
       hipMalloc((void **)&m->w, sizeof(MlpDevWeights)) != hipSuccess ||
       hipMalloc((void **)&m->yc, sizeof(float) * 4) != hipSuccess ||
-      hipMalloc((void **)&m->scratch4, sizeof(float4) * 64) != hipSuccess) {
+      hipMalloc((void **)&m->scratch4, sizeof(float4) * 64) != hipSuccess ||
+      hipMalloc((void **)&m->spl, sizeof(float4) * sl_mlp::kSplinePoints) != hipSuccess) {
     m->last_err = "device allocation failed";
     return bail(SL_E_NOMEM);
   }
@@ -77,7 +78,8 @@ int sl_mlp_destroy(sl_mlp *m) {
   if (m->st) (void)hipStreamSynchronize(m->st);
   if (m->trainer) sl_destroy(m->trainer);
   for (void *p : {(void *)m->master, (void *)m->w, (void *)m->yc, (void *)m->scratch4,
-                  (void *)m->wt, (void *)m->grad, (void *)m->adam_m, (void *)m->adam_v})
+                  (void *)m->wt, (void *)m->grad, (void *)m->adam_m, (void *)m->adam_v,
+                  (void *)m->spl})
     if (p) (void)hipFree(p);
   if (m->own_stream && m->st) (void)hipStreamDestroy(m->st);
   delete m;
@@ -97,7 +99,17 @@ int mlp_refresh(sl_mlp *m) {
   MCHK(m, hipMemcpyAsync(d_r, &rc, sizeof(float), hipMemcpyHostToDevice, m->st));
   launch_mlp_eval(d_r, 1, m->w, m->cfg(), m->yc, 1, m->scratch4, m->st);
   MCHK(m, hipMemcpyAsync(m->yc, (float *)m->scratch4 + 2, 2 * sizeof(float), hipMemcpyDeviceToDevice, m->st));
+  // spline table: the master network in FP64 on the grid; its last point is
+  // rc, which gives the shifted-force constants of the spline form
+  const double dr = (m->rc - sl_mlp::kSplineR0) / (sl_mlp::kSplinePoints - 1);
+  launch_mlp_grid(m->master, sl_mlp::kSplineR0, dr, sl_mlp::kSplinePoints, m->sigma, m->mu_step,
+                  m->spl, m->st);
+  float4 last;
+  MCHK(m, hipMemcpyAsync(&last, m->spl + sl_mlp::kSplinePoints - 1, sizeof(float4),
+                         hipMemcpyDeviceToHost, m->st));
   MCHK(m, hipStreamSynchronize(m->st));
+  m->spl_yc[0] = last.z;
+  m->spl_yc[1] = last.w;
   m->have_weights = true;
   return SL_OK;
 }

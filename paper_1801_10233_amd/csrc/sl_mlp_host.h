@@ -18,7 +18,27 @@ struct sl_mlp {
   int64_t adam_t = 0;
   struct sl_system *trainer = nullptr;  // geometry of the training snapshots
   bool have_weights = false;
+  // raw outputs tabulated for the spline form of the dynamics
+  static constexpr int kSplinePoints = 4096;
+  static constexpr double kSplineR0 = 0.5;  // A; closer pairs take the end value
+  float4 *spl = nullptr;
+  float spl_yc[2] = {0.f, 0.f};             // spline's y1(rc), y1'(rc)
   std::string last_err;
+  sl::SplineView spline_view() const {
+    sl::SplineView v;
+    v.t = spl;
+    v.r0 = (float)kSplineR0;
+    v.dr = (float)((rc - kSplineR0) / (kSplinePoints - 1));
+    v.idr = (float)((kSplinePoints - 1) / (rc - kSplineR0));
+    v.last = kSplinePoints - 1;
+    v.sJ = (float)sJ;
+    v.sP = (float)sP;
+    v.y1c = spl_yc[0];
+    v.d1c = spl_yc[1];
+    v.exrc = (float)ex_rc;
+    v.rc = (float)rc;
+    return v;
+  }
   sl::MlpCfgDev cfg() const {
     sl::MlpCfgDev c;
     c.inv_sigma = (float)(1.0 / sigma);

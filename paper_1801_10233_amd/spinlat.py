@@ -28,10 +28,13 @@ SL_HOST = 0
 SL_DEVICE = 1
 SL_FP64 = 0
 SL_FP32 = 1
+SL_MLP_PAIRWISE = 0
+SL_MLP_SPLINE = 1
 SL_BATCH_PERSISTENT = 0
 SL_BATCH_PHASED = 1
 
-PROF_SPIN, PROF_FORCE, PROF_REBUILD, PROF_REDUCE = 0, 1, 2, 3
+PROF_SPIN, PROF_FORCE, PROF_REBUILD, PROF_TABLE = 0, 1, 2, 3  # kernel kinds of sl_get_profile
+PROF_REDUCE = PROF_TABLE
 
 # Every function the header declares (checked by the tests).
 EXPORTS = [
@@ -40,6 +43,7 @@ EXPORTS = [
     "sl_set_coloring", "sl_get_coloring", "sl_set_step", "sl_step",
     "sl_get_energy", "sl_get_magnetization", "sl_get_thermo", "sl_get_stats",
     "sl_synchronize", "sl_set_tuning", "sl_get_tuning", "sl_autotune", "sl_set_profiling",
+    "sl_set_mlp_mode",
     "sl_get_profile", "sl_last_error",
     "sl_mlp_create", "sl_mlp_destroy", "sl_mlp_set_weights", "sl_mlp_get_weights",
     "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
@@ -146,6 +150,7 @@ def lib():
         "sl_set_tuning": ([vp, C.POINTER(sl_tuning)], C.c_int),
         "sl_get_tuning": ([vp, C.POINTER(sl_tuning)], C.c_int),
         "sl_autotune": ([vp, C.c_int, C.c_double, C.POINTER(sl_tuning)], C.c_int),
+        "sl_set_mlp_mode": ([vp, C.c_int], C.c_int),
         "sl_set_profiling": ([vp, C.c_int], C.c_int),
         "sl_get_profile": ([vp, C.c_int, C.POINTER(C.c_int64), dp, dp], C.c_int),
         "sl_last_error": ([vp], C.c_char_p),
@@ -364,6 +369,9 @@ class System:
         self._check(lib().sl_autotune(self.h, int(steps), float(dt), C.byref(t)))
         return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
                     small_class=t.small_class)
+
+    def set_mlp_mode(self, mode):
+        self._check(lib().sl_set_mlp_mode(self.h, int(mode)))
 
     def set_mlp(self, mlp):
         self._mlp = mlp

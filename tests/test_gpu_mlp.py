@@ -53,9 +53,11 @@ def _small_weights(seed):
     return p.astype(np.float32).astype(np.float64)
 
 
-def test_mlp_dynamics_matches_fp64_mlp_oracle():
-    """FP32 form with the learned potential (BF16 MFMA table) against the
-    oracle driven by the same network in FP64."""
+@pytest.mark.parametrize("mode", [0, 1])   # SL_MLP_PAIRWISE, SL_MLP_SPLINE
+def test_mlp_dynamics_matches_fp64_mlp_oracle(mode):
+    """FP32 form with the learned potential (per-pair BF16 MFMA table, or
+    the spline of the network's outputs) against the oracle driven by the
+    same network in FP64."""
     from paper_1801_10233_amd import spinlat as sl
     from paper_1801_10233_amd import workloads as W
     from tests.common import make_oracle
@@ -64,6 +66,7 @@ def test_mlp_dynamics_matches_fp64_mlp_oracle():
     m = sl.Mlp()
     m.set_weights(p.astype(np.float32))
     g = sl.system_from_workload(w, precision=sl.SL_FP32)
+    g.set_mlp_mode(mode)
     g.set_mlp(m)
     o = make_oracle(w)
     o.set_mlp(CFG, p)
@@ -140,3 +143,52 @@ def test_mlp_training_reduces_loss():
     print("train", log, flush=True)
     assert log["updates"] == 100
     assert log["loss_last"] < 0.5 * log["loss_first"]
+
+
+def test_trained_network_beats_untrained_and_tracks_analytic():
+    """The committed network (trained on the GPU by train_mlp.py) reproduces
+    the analytic forces and hbar*omega of an unseen configuration to a few
+    per mil; the same network before training is off by order one."""
+    import os
+    from paper_1801_10233_amd import spinlat as sl
+    from paper_1801_10233_amd import workloads as W
+    from paper_1801_10233_amd.train_mlp import init_weights
+    w = W.coupled_nve(n=8, T=600.0, spin_seed=4242, vel_seed=4243)
+    w.r = w.r + W.thermal_displacements(w.N, 0.07, 4244)
+    a = sl.system_from_workload(w)
+    Fa, ha = a.fields()
+    path = os.path.join(os.path.dirname(sl.__file__), "data", "mlp_bj_weights.npy")
+    errs = []
+    for p in (np.load(path, allow_pickle=False), init_weights(7)):
+        m = sl.Mlp()
+        m.set_weights(p)
+        g = sl.system_from_workload(w, precision=sl.SL_FP32)
+        g.set_mlp(m)
+        F, hw = g.fields()
+        errs.append((np.sqrt(np.sum((F - Fa) ** 2) / np.sum(Fa ** 2)),
+                     np.sqrt(np.sum((hw - ha) ** 2) / np.sum(ha ** 2))))
+    print("trained", errs[0], "untrained", errs[1], flush=True)
+    assert errs[0][0] < 0.02 and errs[0][1] < 0.02
+    assert errs[1][0] > 0.3 and errs[1][1] > 0.3
+
+
+def test_spline_form_conserves_energy():
+    """The spline form's forces are the exact derivative of its energy: an
+    undamped FP32 run keeps E_total to the FP32 level, with no drift
+    beyond it (the per-pair BF16 form is checked against the oracle above)."""
+    import os
+    from paper_1801_10233_amd import spinlat as sl
+    from paper_1801_10233_amd import workloads as W
+    w = W.large_langevin(n=10, nve=True)
+    path = os.path.join(os.path.dirname(sl.__file__), "data", "mlp_bj_weights.npy")
+    m = sl.Mlp()
+    m.set_weights(np.load(path, allow_pickle=False))
+    g = sl.system_from_workload(w, precision=sl.SL_FP32, thermo_every=10)
+    g.set_mlp_mode(sl.SL_MLP_SPLINE)
+    g.set_mlp(m)
+    g.step(3000, w.dt)
+    st, E, _ = g.thermo()
+    e = E / w.N
+    slope = np.polyfit(st[50:] * w.dt, e[50:], 1)[0] * 10.0    # eV/atom per 10 ps
+    print("spline NVE: drift per 10 ps", slope, "rms", np.std(e), flush=True)
+    assert abs(slope) < 1e-5 and np.std(e) < 1e-5
