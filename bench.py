@@ -115,11 +115,14 @@ def sync():
     torch.cuda.synchronize()
 
 
+PROFILE_EVERY = 10   # HIP events bracket the launches of every 10th timed step
+
+
 def timed_run(S, steps, dt, profile=False):
     S.synchronize()
     sync()
     if profile:
-        S.set_profiling(True)
+        S.set_profiling(True, every=PROFILE_EVERY)
     t0 = time.perf_counter()
     S.step(steps, dt)
     S.synchronize()
@@ -315,6 +318,8 @@ def main():
                     traffic=None if traffic is None else round(traffic, 1),
                     traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     kernel=KIND_NAME[dom], avg_launch_us=round(avg_ms * 1e3, 3),
+                    timing=f"HIP events on the library stream around every launch of every "
+                           f"{PROFILE_EVERY}th timed step",
                     algorithmic_bytes_per_atom=per_atom,
                     algorithmic_bytes_per_launch=round(bytes_per_launch, 1),
                     atoms_per_launch=round(work / launches, 1), kernels=other,

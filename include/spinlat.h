@@ -204,6 +204,11 @@ typedef struct {
     int spin_lanes;
     int force_lanes;
     int small_class;
+    int jcache;       /* exchange-coefficient cache (analytic potential):
+                         J(r_ij) of every spin-segment entry is evaluated once
+                         per drift and read by the spin phases; 0 = default
+                         (on for the FP32 form, off for FP64, as measured on
+                         MI355X), 1 on, -1 off */
 } sl_tuning;
 
 int sl_set_tuning(sl_system *sys, const sl_tuning *t);
@@ -223,11 +228,15 @@ int sl_get_tuning(sl_system *sys, sl_tuning *t);
  * and appended after tuning. */
 int sl_autotune(sl_system *sys, int steps, double dt, sl_tuning *chosen);
 
-/* Per-kernel timing with HIP events on the system's stream. When on, every
- * launch of the spin-phase, force and rebuild kernels is bracketed by a
- * pair of events; sl_get_profile returns, per kernel kind, the launch count
- * and the summed event time in ms. Kinds: 0 spin phase, 1 force,
- * 2 neighbour rebuild, 3 learned-potential table. */
+/* Per-kernel timing with HIP events on the system's stream. With on = 1
+ * every launch of the spin-phase, force, rebuild and table kernels is
+ * bracketed by a pair of events; with on = N > 1 only the launches of every
+ * N-th step are (the event packets themselves cost a few microseconds of
+ * GPU time each); 0 stops. sl_get_profile returns, per kernel kind, the launch count
+ * and the summed event time in ms since profiling was last switched on
+ * (switching it off keeps the totals readable). Kinds: 0 spin phase,
+ * 1 force, 2 neighbour rebuild, 3 pair-coefficient table (exchange cache
+ * or per-pair learned potential). */
 int sl_set_profiling(sl_system *sys, int on);
 int sl_get_profile(sl_system *sys, int kind, int64_t *launches, double *ms,
                    double *work_items);

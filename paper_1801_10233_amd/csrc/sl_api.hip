@@ -111,8 +111,14 @@ struct sl_system {
   int npair = 0, mpair_cap = 0;
   float4 *tab[2] = {nullptr, nullptr};
   bool tab_ok[2] = {false, false};
+  // exchange-coefficient cache per position buffer (analytic potential)
+  int jcache = -1;  // set from the precision at creation (on for FP32)
+  void *jc[2] = {nullptr, nullptr};
+  bool jc_ok[2] = {false, false};
 
   bool prof = false;
+  int prof_every = 1;     // time the launches of every prof_every-th step
+  bool prof_now = false;  // the current step is timed
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
   int64_t prof_launch[4] = {0, 0, 0, 0};
@@ -241,6 +247,7 @@ SysView<real> view(sl_system *S, int posbuf) {
   v.id = A.id;
   v.tab = nullptr;
   v.spl = SplineView{};
+  v.jc = (!S->mlp && S->jcache > 0 && S->jc_ok[posbuf]) ? (const real *)S->jc[posbuf] : nullptr;
   if (S->mlp && S->mlp_mode == SL_MLP_SPLINE) v.spl = S->mlp->spline_view();
   else if (S->mlp) v.tab = S->tab[posbuf];
   return v;
@@ -264,13 +271,13 @@ struct ProfScope {
   double work;
   hipEvent_t a = nullptr;
   ProfScope(sl_system *S_, int kind_, double work_) : S(S_), kind(kind_), work(work_) {
-    if (S->prof) {
+    if (S->prof_now) {
       a = get_event(S);
       (void)hipEventRecord(a, S->st);
     }
   }
   ~ProfScope() {
-    if (S->prof) {
+    if (a) {
       hipEvent_t b = get_event(S);
       (void)hipEventRecord(b, S->st);
       S->prof_recs.push_back({kind, a, b, work});
@@ -501,6 +508,25 @@ int ensure_table(sl_system *S, int b) {
   return SL_OK;
 }
 
+// Exchange coefficients of buffer b's positions for the spin phases (once
+// per drift; the analytic potential only).
+template <typename real>
+int ensure_jcache(sl_system *S, int b) {
+  if (S->mlp || S->jcache <= 0 || S->jc_ok[b]) return SL_OK;
+  if (!S->jc[b]) {
+    real *p = nullptr;
+    HIPCHK(S, dalloc(&p, (size_t)S->ld * S->max_nbr));
+    S->jc[b] = p;
+  }
+  SysView<real> v = view<real>(S, b);
+  {
+    ProfScope ps(S, 3, (double)S->n);
+    launch_jcache<real>(v, S->pc, (real *)S->jc[b], S->pot.ex_rc * S->pot.ex_rc, S->st);
+  }
+  S->jc_ok[b] = true;
+  return SL_OK;
+}
+
 // Colour classes (repairing the previous colouring when there is one) and
 // permutation of all per-atom arrays into (colour, cell) order.
 int colour_and_permute(sl_system *S, bool repair) {
@@ -589,6 +615,7 @@ int colour_and_permute(sl_system *S, bool repair) {
   launch_permute_atoms(P, S->st);
   launch_permute_nbr(n, S->ld, S->perm, S->inv, A.nbr, A.nspin, A.nall, B.nbr, B.nspin, B.nall, S->st);
   S->cur = 1 - S->cur;
+  S->jc_ok[0] = S->jc_ok[1] = false;
   // class offsets = bucket starts of the first cell of every colour
   std::vector<int> bs(nbin + 1);
   HIPCHK(S, hipMemcpyAsync(bs.data(), S->bstart, sizeof(int) * (nbin + 1), hipMemcpyDeviceToHost, S->st));
@@ -711,6 +738,7 @@ double noise_amp(const sl_system *S, double h) {
 template <typename real>
 void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) {
   (void)ensure_table(S, posbuf);
+  (void)ensure_jcache<real>(S, posbuf);
   std::vector<Item> items;
   for (size_t i = 0; i < u.size();) {
     Item it;
@@ -795,7 +823,7 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   F.wmask = A.wmask;
   F.frozen = S->prm.frozen;
   CHK(ensure_table(S, posbuf));
-  if (mode & kModeNext) S->tab_ok[1 - posbuf] = false;
+  if (mode & kModeNext) S->tab_ok[1 - posbuf] = S->jc_ok[1 - posbuf] = false;
   const int slot = (int)(boundary & 3);
   F.host_out = S->ring_dev + 8 * slot;
   if (mode & (kModeFinal | kModeNext)) {
@@ -912,6 +940,7 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
         S->meta[k & 3].rebuilt_after = true;
       }
     }
+    S->prof_now = S->prof && (k % S->prof_every == 0);
     std::vector<Upd> u;
     half_step_updates(S, k, 0, u);
     run_updates<real>(S, S->pos, u, h);
@@ -928,6 +957,7 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
     S->pos = 1 - S->pos;
     S->step = b;
   }
+  S->prof_now = S->prof;
   return SL_OK;
 }
 
@@ -970,6 +1000,7 @@ int sl_create(const sl_params *p, sl_system **out) {
   }
   S->skin = p->frozen ? 0.0 : p->skin;
   S->max_nbr = p->max_nbr > 0 ? p->max_nbr : 80;
+  S->jcache = S->prec == SL_FP32 ? 1 : -1;
   S->max_spin = p->max_spin_nbr > 0 ? p->max_spin_nbr : 32;
   if (S->max_spin > S->max_nbr) S->max_spin = S->max_nbr;
   int rc = SL_OK;
@@ -1053,7 +1084,7 @@ int sl_destroy(sl_system *S) {
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
                   (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo,
                   (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
-                  (void *)S->tab[0], (void *)S->tab[1]})
+                  (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1]})
     dfree(p);
   if (S->ring) (void)hipHostFree(S->ring);
   if (S->own_stream && S->st) (void)hipStreamDestroy(S->st);
@@ -1138,6 +1169,7 @@ int sl_set_state(sl_system *S, const double *r, const double *v, const double *s
   S->have_colour = false;
   S->have_D = false;
   S->tab_ok[0] = S->tab_ok[1] = false;
+  S->jc_ok[0] = S->jc_ok[1] = false;
   S->sticky = 0;
   HIPCHK(S, hipMemsetAsync(S->err, 0, sizeof(int), S->st));
   return SL_OK;
@@ -1177,12 +1209,16 @@ int sl_set_neighbor(sl_system *S, double skin, int max_nbr) {
     if (S->max_spin > max_nbr) S->max_spin = max_nbr;
     HIPCHK(S, dalloc(&S->a[0].nbr, (size_t)S->ld * S->max_nbr));
     HIPCHK(S, dalloc(&S->a[1].nbr, (size_t)S->ld * S->max_nbr));
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
       if (S->tab[b]) {
         dfree(S->tab[b]);
         S->tab[b] = nullptr;
         HIPCHK(S, dalloc(&S->tab[b], (size_t)S->ld * S->max_nbr));
       }
+      dfree(S->jc[b]);  // reallocated at the next use with the new capacity
+      S->jc[b] = nullptr;
+      S->jc_ok[b] = false;
+    }
   }
   S->user_list = false;
   S->have_list = false;
@@ -1461,10 +1497,12 @@ int sl_set_tuning(sl_system *S, const sl_tuning *t) {
   auto ok = [](int x) { return x == 0 || x == 1 || x == 2 || x == 4 || x == 8; };
   if (!ok(t->spin_lanes) || !ok(t->force_lanes)) return fail(S, SL_E_ARG, "lanes must be 1, 2, 4 or 8");
   if (t->small_class < -1) return fail(S, SL_E_ARG, "small_class must be >= -1");
+  if (t->jcache < -1 || t->jcache > 1) return fail(S, SL_E_ARG, "jcache must be -1, 0 or 1");
   CHK(sl_synchronize(S));
   S->spin_lanes = t->spin_lanes ? t->spin_lanes : 2;
   S->force_lanes = t->force_lanes ? t->force_lanes : 1;
   S->small_class = t->small_class == 0 ? 512 : t->small_class;
+  S->jcache = t->jcache == 0 ? (S->prec == SL_FP32 ? 1 : -1) : t->jcache;
   return SL_OK;
 }
 
@@ -1473,18 +1511,23 @@ int sl_get_tuning(sl_system *S, sl_tuning *t) {
   t->spin_lanes = S->spin_lanes;
   t->force_lanes = S->force_lanes;
   t->small_class = S->small_class;
+  t->jcache = S->jcache;
   return SL_OK;
 }
 
 int sl_set_profiling(sl_system *S, int on) {
   if (!S) return fail(S, SL_E_ARG, "NULL system");
-  if (S->prof && !on) prof_collect(S);
+  if (S->prof && !on) prof_collect(S);  // totals stay readable after stopping
+  if (on < 0) return fail(S, SL_E_ARG, "profiling period must be >= 0");
+  if (on && !S->prof)
+    for (int k = 0; k < 4; ++k) {        // a new measurement starts from zero
+      S->prof_launch[k] = 0;
+      S->prof_ms[k] = 0.0;
+      S->prof_work[k] = 0.0;
+    }
   S->prof = on != 0;
-  for (int k = 0; k < 4; ++k) {
-    S->prof_launch[k] = 0;
-    S->prof_ms[k] = 0.0;
-    S->prof_work[k] = 0.0;
-  }
+  S->prof_every = on > 1 ? on : 1;
+  S->prof_now = S->prof;
   return SL_OK;
 }
 
@@ -1823,7 +1866,7 @@ std::string tune_key(const std::string &what) {
   return arch + " " + what;
 }
 
-bool cache_lookup(const std::string &key, int vals[3]) {
+bool cache_lookup(const std::string &key, int vals[4]) {
   const char *path = std::getenv("SL_TUNE_CACHE");
   if (!path) return false;
   FILE *f = std::fopen(path, "r");
@@ -1834,18 +1877,20 @@ bool cache_lookup(const std::string &key, int vals[3]) {
   while (std::fgets(line, sizeof(line), f)) {
     if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
     const char *q = std::strstr(line, "\"vals\": [");
-    if (q && std::sscanf(q, "\"vals\": [%d, %d, %d]", &vals[0], &vals[1], &vals[2]) == 3) found = true;
+    if (q && std::sscanf(q, "\"vals\": [%d, %d, %d, %d]", &vals[0], &vals[1], &vals[2], &vals[3]) == 4)
+      found = true;
   }
   std::fclose(f);
   return found;
 }
 
-void cache_store(const std::string &key, const int vals[3]) {
+void cache_store(const std::string &key, const int vals[4]) {
   const char *path = std::getenv("SL_TUNE_CACHE");
   if (!path) return;
   FILE *f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"vals\": [%d, %d, %d]}\n", key.c_str(), vals[0], vals[1], vals[2]);
+  std::fprintf(f, "{\"key\": \"%s\", \"vals\": [%d, %d, %d, %d]}\n", key.c_str(), vals[0], vals[1],
+               vals[2], vals[3]);
   std::fclose(f);
 }
 
@@ -1861,43 +1906,48 @@ int sl_autotune(sl_system *S, int steps, double dt, sl_tuning *chosen) {
       " frozen=" + std::to_string(S->prm.frozen) + " langevin=" + std::to_string(S->pc.langevin) +
       " aniso=" + std::to_string(S->pc.aniso_on) + " mlp=" + std::to_string(S->mlp ? 1 : 0) +
       " K=" + std::to_string(S->K));
-  int v[3];
+  int v[4];
   if (!cache_lookup(key, v)) {
     sl_system *C = nullptr;
     CHK(clone_system(S, &C));
-    // (spin lanes, force lanes) trials; spin lanes are judged by the
-    // spin-phase kernel time, force lanes by the force kernel time
-    const int trial[3][2] = {{1, 1}, {2, 2}, {4, 1}};
-    double spin_us[3] = {0, 0, 0}, force_us[3] = {0, 0, 0};
+    // (spin lanes, force lanes, J cache) trials, each run twice in turn
+    // (the better run counts). Spin lanes and the J cache are judged by the
+    // spin-phase time per step including the cache's own kernel, force
+    // lanes by the force kernel time.
+    const int trial[4][3] = {{1, 1, 1}, {2, 2, 1}, {4, 1, 1}, {2, 1, -1}};
+    double spin_ms[4] = {1e300, 1e300, 1e300, 1e300}, force_us[4] = {1e300, 1e300, 1e300, 1e300};
     int rc = SL_OK;
-    for (int t = 0; t < 3 && rc == SL_OK; ++t) {
-      sl_tuning tt{trial[t][0], trial[t][1], S->small_class};
-      if ((rc = sl_set_tuning(C, &tt))) break;
-      if ((rc = sl_step(C, 2, dt))) break;
-      if ((rc = sl_set_profiling(C, 1))) break;
-      if ((rc = sl_step(C, steps, dt))) break;
-      if ((rc = sl_synchronize(C))) break;
-      int64_t l0 = 0, l1 = 0;
-      double m0 = 0, m1 = 0, w0 = 0, w1 = 0;
-      sl_get_profile(C, 0, &l0, &m0, &w0);
-      sl_get_profile(C, 1, &l1, &m1, &w1);
-      spin_us[t] = l0 ? 1e3 * m0 / l0 : 0.0;
-      force_us[t] = l1 ? 1e3 * m1 / l1 : 0.0;
-      rc = sl_set_profiling(C, 0);
-    }
+    for (int pass = 0; pass < 2 && rc == SL_OK; ++pass)
+      for (int t = 0; t < 4 && rc == SL_OK; ++t) {
+        sl_tuning tt{trial[t][0], trial[t][1], S->small_class, trial[t][2]};
+        if ((rc = sl_set_tuning(C, &tt))) break;
+        if ((rc = sl_step(C, 3, dt))) break;
+        if ((rc = sl_set_profiling(C, 1))) break;
+        if ((rc = sl_step(C, steps, dt))) break;
+        if ((rc = sl_synchronize(C))) break;
+        int64_t l0 = 0, l1 = 0, l3 = 0;
+        double m0 = 0, m1 = 0, m3 = 0, w = 0;
+        sl_get_profile(C, 0, &l0, &m0, &w);
+        sl_get_profile(C, 1, &l1, &m1, &w);
+        sl_get_profile(C, 3, &l3, &m3, &w);
+        spin_ms[t] = std::min(spin_ms[t], (m0 + m3) / steps);
+        if (l1) force_us[t] = std::min(force_us[t], 1e3 * m1 / l1);
+        rc = sl_set_profiling(C, 0);
+      }
     const std::string err = rc ? C->last_err : std::string();
     sl_destroy(C);
     if (rc) return fail(S, rc, "autotune trial: " + err);
     int bs = 0;
-    for (int t = 1; t < 3; ++t)
-      if (spin_us[t] < spin_us[bs]) bs = t;
-    const double f1 = 0.5 * (force_us[0] + force_us[2]), f2 = force_us[1];
+    for (int t = 1; t < 4; ++t)
+      if (spin_ms[t] < spin_ms[bs]) bs = t;
+    const double f1 = std::min(force_us[0], std::min(force_us[2], force_us[3])), f2 = force_us[1];
     v[0] = trial[bs][0];
     v[1] = (S->prm.frozen || f1 <= f2) ? 1 : 2;
     v[2] = S->small_class;
+    v[3] = trial[bs][2];
     cache_store(key, v);
   }
-  sl_tuning t{v[0], v[1], v[2]};
+  sl_tuning t{v[0], v[1], v[2], v[3]};
   CHK(sl_set_tuning(S, &t));
   if (chosen) *chosen = t;
   return SL_OK;
@@ -2343,7 +2393,7 @@ int sl_batch_autotune(sl_batch *B, int steps, double dt, int *mode, int *lanes) 
   for (auto *S : B->sys) natoms += S->n;
   what += " atoms=" + std::to_string(natoms);
   const std::string key = tune_key(what);
-  int v[3];
+  int v[4] = {0, 0, 0, 0};
   if (!cache_lookup(key, v)) {
     sl_batch *C = nullptr;
     int rc = sl_batch_create(B->R, B->params.data(), B->pots.data(), &C);
@@ -2362,6 +2412,7 @@ int sl_batch_autotune(sl_batch *B, int steps, double dt, int *mode, int *lanes) 
     v[0] = B->mode;
     v[1] = B->lanes;
     v[2] = 0;
+    v[3] = 0;
     for (int t = 0; t < 5 && rc == SL_OK; ++t) {
       C->mode = trial[t][0];
       C->lanes = trial[t][1];

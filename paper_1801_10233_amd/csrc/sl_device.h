@@ -106,6 +106,8 @@ struct SysView {
   const float4 *tab;           // learned-potential table (J, J', phi, phi') per
                                // list entry at these positions, or null
   SplineView spl;              // learned potential as a spline (spl.t null: unused)
+  const real *jc;              // exchange coefficients J(r_ij) per spin-segment
+                               // entry at these positions, or null
 };
 
 struct SpinPhaseArgs {

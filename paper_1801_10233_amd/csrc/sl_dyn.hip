@@ -68,11 +68,15 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
       real qx[CH], qy[CH], qz[CH], J[CH];
       double px[CH], py[CH], pz[CH];
       float jt[CH];
+      real jr[CH];
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         if (MLP == 1) {
           const int k = base + LANES * c;
           jt[c] = k < S.kcap ? S.tab[(size_t)k * ld + i].x : 0.f;
+        } else if (MLP == 3) {
+          const int k = base + LANES * c;
+          jr[c] = k < S.kcap ? S.jc[(size_t)k * ld + i] : (real)0;
         } else {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
         }
@@ -85,6 +89,8 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
         const bool in = base + LANES * c < ns;
         if (MLP == 1) {
           J[c] = in ? (real)jt[c] : (real)0;
+        } else if (MLP == 3) {
+          J[c] = in ? jr[c] : (real)0;
         } else if (MLP == 2) {
           const double dx = min_image(rix - px[c], S.L[0], S.invL[0]);
           const double dy = min_image(riy - py[c], S.L[1], S.invL[1]);
@@ -671,6 +677,39 @@ template void launch_batch_spin<float>(const RepDesc<float> *, int, int, const B
 template void launch_batch_force<double>(const RepDesc<double> *, int, int, int, const BatchPhase &, int, hipStream_t);
 template void launch_batch_force<float>(const RepDesc<float> *, int, int, int, const BatchPhase &, int, hipStream_t);
 
+// Exchange coefficients at one set of positions (the optional pair
+// coefficient cache): J(r_ij) for every spin-segment entry, with the same
+// expression as the spin phase's own evaluation. Positions change only at
+// the drift, so one evaluation serves the two spin half-steps that use
+// these positions (Sec. 3: coefficients must be re-evaluated after the
+// positions move, and only then).
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_jcache(SysView<real> S, PotConst P, real *out,
+                                                   double rs2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const int ns = S.nspin[i];
+  const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
+  for (int k = 0; k < ns; ++k) {
+    const int j = S.nbr[(size_t)k * S.ld + i];
+    const double dx = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
+    const double dy = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
+    const double dz = min_image(riz - S.rz[j], S.L[2], S.invL[2]);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const real u = (real)(r2 * P.eInvD2);
+    const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+    out[(size_t)k * S.ld + i] = r2 < rs2 ? Jc : (real)0;
+  }
+}
+
+template <typename real>
+void launch_jcache(const SysView<real> &S, const PotConst &P, real *out, double rs2,
+                   hipStream_t st) {
+  if (S.n > 0) hipLaunchKernelGGL((k_jcache<real>), dim3((S.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, P, out, rs2);
+}
+template void launch_jcache<double>(const SysView<double> &, const PotConst &, double *, double, hipStream_t);
+template void launch_jcache<float>(const SysView<float> &, const PotConst &, float *, double, hipStream_t);
+
 // Fixed-order sum of nb partial rows of 8 doubles (deterministic result).
 __global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, double *out) {
   __shared__ double buf[256][8];
@@ -708,7 +747,8 @@ static void spin_phase_lanes2(const SysView<real> &S, const PotConst &P, const S
 template <typename real, int LANES>
 static void spin_phase_lanes(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
                              hipStream_t st) {
-  if (sizeof(real) == 4 && S.spl.t) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
+  if (S.jc) spin_phase_lanes2<real, LANES, 3>(S, P, A, st);
+  else if (sizeof(real) == 4 && S.spl.t) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
   else if (sizeof(real) == 4 && S.tab) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, st);
   else spin_phase_lanes2<real, LANES, 0>(S, P, A, st);
 }
@@ -738,7 +778,8 @@ static void spin_tail_lanes2(const SysView<real> &S, const PotConst &P, const Ta
 template <typename real, int LANES>
 static void spin_tail_lanes(const SysView<real> &S, const PotConst &P, const TailArgs &T,
                             hipStream_t st) {
-  if (sizeof(real) == 4 && S.spl.t) spin_tail_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, T, st);
+  if (S.jc) spin_tail_lanes2<real, LANES, 3>(S, P, T, st);
+  else if (sizeof(real) == 4 && S.spl.t) spin_tail_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, T, st);
   else if (sizeof(real) == 4 && S.tab) spin_tail_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, T, st);
   else spin_tail_lanes2<real, LANES, 0>(S, P, T, st);
 }

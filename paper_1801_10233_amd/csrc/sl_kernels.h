@@ -19,6 +19,10 @@ void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
 int force_blocks(int n, int lanes);
 template <typename real>
 void launch_batch_run(RepDesc<real> *D, int R, int lanes, hipStream_t st);
+// Exchange-coefficient cache: J(r_ij) per spin-segment entry (ELL layout).
+template <typename real>
+void launch_jcache(const SysView<real> &S, const PotConst &P, real *out, double rs2,
+                   hipStream_t st);
 // Phase-batched mode: one colour phase of every replica (max_class = the
 // largest class of any replica) and one force pass of every replica (max_n =
 // the largest replica; mode kModeNext at the call start, kModeFinal with or

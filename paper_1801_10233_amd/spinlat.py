@@ -84,7 +84,8 @@ class sl_stats(C.Structure):
 
 
 class sl_tuning(C.Structure):
-    _fields_ = [("spin_lanes", C.c_int), ("force_lanes", C.c_int), ("small_class", C.c_int)]
+    _fields_ = [("spin_lanes", C.c_int), ("force_lanes", C.c_int), ("small_class", C.c_int),
+                ("jcache", C.c_int)]
 
 
 class sl_mlp_spec(C.Structure):
@@ -353,22 +354,22 @@ class System:
     def synchronize(self):
         self._check(lib().sl_synchronize(self.h))
 
-    def set_tuning(self, spin_lanes=0, force_lanes=0, small_class=0):
-        t = sl_tuning(int(spin_lanes), int(force_lanes), int(small_class))
+    def set_tuning(self, spin_lanes=0, force_lanes=0, small_class=0, jcache=0):
+        t = sl_tuning(int(spin_lanes), int(force_lanes), int(small_class), int(jcache))
         self._check(lib().sl_set_tuning(self.h, C.byref(t)))
 
     def tuning(self):
         t = sl_tuning()
         self._check(lib().sl_get_tuning(self.h, C.byref(t)))
         return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
-                    small_class=t.small_class)
+                    small_class=t.small_class, jcache=t.jcache)
 
     def autotune(self, steps, dt):
         """Time launch shapes on a scratch copy and keep the fastest."""
         t = sl_tuning()
         self._check(lib().sl_autotune(self.h, int(steps), float(dt), C.byref(t)))
         return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
-                    small_class=t.small_class)
+                    small_class=t.small_class, jcache=t.jcache)
 
     def set_mlp_mode(self, mode):
         self._check(lib().sl_set_mlp_mode(self.h, int(mode)))
@@ -383,8 +384,9 @@ class System:
         self._check(lib().sl_get_fields(self.h, F.ctypes.data, hw.ctypes.data, SL_HOST))
         return F, hw
 
-    def set_profiling(self, on=True):
-        self._check(lib().sl_set_profiling(self.h, int(bool(on))))
+    def set_profiling(self, on=True, every=1):
+        """Time kernel launches with HIP events (those of every `every`-th step)."""
+        self._check(lib().sl_set_profiling(self.h, int(every) if on else 0))
 
     def profile(self, kind):
         n = C.c_int64(); ms = C.c_double(); w = C.c_double()

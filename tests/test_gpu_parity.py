@@ -70,20 +70,22 @@ def test_coupled_nve_parity_100_steps(n):
         assert eg[k] == pytest.approx(eo[k], rel=1e-11, abs=1e-11), k
 
 
-@pytest.mark.parametrize("spin_lanes,force_lanes,small", [(1, 1, -1), (2, 8, -1), (8, 2, 4096),
-                                                         (4, 4, -1)])
-def test_launch_shapes_keep_parity(spin_lanes, force_lanes, small):
-    # every launch shape (lanes per atom, fused small classes on/off) gives
-    # the oracle's trajectory to roundoff
+@pytest.mark.parametrize("spin_lanes,force_lanes,small,jcache", [
+    (1, 1, -1, 1), (2, 8, -1, -1), (8, 2, 4096, 1), (4, 4, -1, -1), (2, 1, 512, -1)])
+def test_launch_shapes_keep_parity(spin_lanes, force_lanes, small, jcache):
+    # every launch shape (lanes per atom, fused small classes on/off, the
+    # exchange-coefficient cache on/off) gives the oracle's trajectory to
+    # roundoff
     w = W.large_langevin(n=8)
     o = make_oracle(w)
     g = make_gpu(w)
-    g.set_tuning(spin_lanes, force_lanes, small)
-    assert g.tuning() == dict(spin_lanes=spin_lanes, force_lanes=force_lanes, small_class=small)
+    g.set_tuning(spin_lanes, force_lanes, small, jcache)
+    assert g.tuning() == dict(spin_lanes=spin_lanes, force_lanes=force_lanes, small_class=small,
+                              jcache=jcache)
     o.step(50, w.dt)
     g.step(50, w.dt)
     p = parity(w, o, g)
-    _print("shape", spin_lanes, force_lanes, small, p)
+    _print("shape", spin_lanes, force_lanes, small, jcache, p)
     assert p["ok"], p
 
 
