@@ -204,11 +204,12 @@ typedef struct {
     int spin_lanes;
     int force_lanes;
     int small_class;
-    int jcache;       /* exchange-coefficient cache (analytic potential):
-                         J(r_ij) of every spin-segment entry is evaluated once
-                         per drift and read by the spin phases; 0 = default
-                         (on for the FP32 form, off for FP64, as measured on
-                         MI355X), 1 on, -1 off */
+    int jcache;       /* exchange-coefficient cache (analytic potential and
+                         the spline form of a learned one): J(r_ij) of every
+                         spin-segment entry is evaluated once per drift and
+                         read by the spin phases; 0 = default (on for the
+                         FP32 form, off for FP64, as measured on MI355X),
+                         1 on, -1 off */
 } sl_tuning;
 
 int sl_set_tuning(sl_system *sys, const sl_tuning *t);

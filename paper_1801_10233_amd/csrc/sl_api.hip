@@ -247,7 +247,8 @@ SysView<real> view(sl_system *S, int posbuf) {
   v.id = A.id;
   v.tab = nullptr;
   v.spl = SplineView{};
-  v.jc = (!S->mlp && S->jcache > 0 && S->jc_ok[posbuf]) ? (const real *)S->jc[posbuf] : nullptr;
+  const bool jc_use = (!S->mlp || S->mlp_mode == SL_MLP_SPLINE) && S->jcache > 0;
+  v.jc = (jc_use && S->jc_ok[posbuf]) ? (const real *)S->jc[posbuf] : nullptr;
   if (S->mlp && S->mlp_mode == SL_MLP_SPLINE) v.spl = S->mlp->spline_view();
   else if (S->mlp) v.tab = S->tab[posbuf];
   return v;
@@ -512,7 +513,7 @@ int ensure_table(sl_system *S, int b) {
 // per drift; the analytic potential only).
 template <typename real>
 int ensure_jcache(sl_system *S, int b) {
-  if (S->mlp || S->jcache <= 0 || S->jc_ok[b]) return SL_OK;
+  if ((S->mlp && S->mlp_mode != SL_MLP_SPLINE) || S->jcache <= 0 || S->jc_ok[b]) return SL_OK;
   if (!S->jc[b]) {
     real *p = nullptr;
     HIPCHK(S, dalloc(&p, (size_t)S->ld * S->max_nbr));
@@ -1479,6 +1480,7 @@ int sl_set_mlp(sl_system *S, sl_mlp *m) {
   }
   S->mlp = m;
   S->tab_ok[0] = S->tab_ok[1] = false;
+  S->jc_ok[0] = S->jc_ok[1] = false;
   if (m && S->have_list && S->have_colour) CHK(mlp_pairs(S));
   return SL_OK;
 }
@@ -1489,6 +1491,7 @@ int sl_set_mlp_mode(sl_system *S, int mode) {
   CHK(sl_synchronize(S));
   S->mlp_mode = mode;
   S->tab_ok[0] = S->tab_ok[1] = false;
+  S->jc_ok[0] = S->jc_ok[1] = false;
   return SL_OK;
 }
 

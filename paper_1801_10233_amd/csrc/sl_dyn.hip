@@ -683,29 +683,57 @@ template void launch_batch_force<float>(const RepDesc<float> *, int, int, int, c
 // the drift, so one evaluation serves the two spin half-steps that use
 // these positions (Sec. 3: coefficients must be re-evaluated after the
 // positions move, and only then).
-template <typename real>
+template <typename real, bool SPL>
 __global__ __launch_bounds__(kBlock) void k_jcache(SysView<real> S, PotConst P, real *out,
                                                    double rs2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
   const int ns = S.nspin[i];
   const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
-  for (int k = 0; k < ns; ++k) {
-    const int j = S.nbr[(size_t)k * S.ld + i];
-    const double dx = min_image(rix - S.rx[j], S.L[0], S.invL[0]);
-    const double dy = min_image(riy - S.ry[j], S.L[1], S.invL[1]);
-    const double dz = min_image(riz - S.rz[j], S.L[2], S.invL[2]);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const real u = (real)(r2 * P.eInvD2);
-    const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
-    out[(size_t)k * S.ld + i] = r2 < rs2 ? Jc : (real)0;
+  // slots in chunks of 8 with all loads of a chunk issued before use; the
+  // slot rows below kcap exist for every atom, so their loads need no guard
+  constexpr int CH = 8;
+  for (int k0 = 0; k0 < ns; k0 += CH) {
+    int jj[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int k = k0 + c;
+      const int j = k < S.kcap ? S.nbr[(size_t)k * S.ld + i] : i;
+      jj[c] = (k < ns && (unsigned)j < (unsigned)S.n) ? j : i;
+    }
+    double xj[CH], yj[CH], zj[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      xj[c] = S.rx[jj[c]];
+      yj[c] = S.ry[jj[c]];
+      zj[c] = S.rz[jj[c]];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int k = k0 + c;
+      if (k >= ns) break;
+      const double dx = min_image(rix - xj[c], S.L[0], S.invL[0]);
+      const double dy = min_image(riy - yj[c], S.L[1], S.invL[1]);
+      const double dz = min_image(riz - zj[c], S.L[2], S.invL[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (SPL) {  // learned potential (spline form): J with its own cut
+        out[(size_t)k * S.ld + i] = (real)spline_phys(S.spl, (float)sqrt(r2)).x;
+      } else {
+        const real u = (real)(r2 * P.eInvD2);
+        const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+        out[(size_t)k * S.ld + i] = r2 < rs2 ? Jc : (real)0;
+      }
+    }
   }
 }
 
 template <typename real>
 void launch_jcache(const SysView<real> &S, const PotConst &P, real *out, double rs2,
                    hipStream_t st) {
-  if (S.n > 0) hipLaunchKernelGGL((k_jcache<real>), dim3((S.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, P, out, rs2);
+  if (S.n <= 0) return;
+  const dim3 grid((S.n + kBlock - 1) / kBlock);
+  if (S.spl.t) hipLaunchKernelGGL((k_jcache<real, true>), grid, dim3(kBlock), 0, st, S, P, out, rs2);
+  else hipLaunchKernelGGL((k_jcache<real, false>), grid, dim3(kBlock), 0, st, S, P, out, rs2);
 }
 template void launch_jcache<double>(const SysView<double> &, const PotConst &, double *, double, hipStream_t);
 template void launch_jcache<float>(const SysView<float> &, const PotConst &, float *, double, hipStream_t);

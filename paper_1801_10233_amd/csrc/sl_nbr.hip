@@ -88,11 +88,13 @@ __global__ void k_bucket_sort(int nbucket, const int *start, int *items) {
 // loop order, atoms ascending inside a cell, so rows are deterministic.
 // kNbrLanes lanes share one atom, each scanning a contiguous run of the
 // cells: a counting sweep, a segmented prefix sum over the lanes, then a
-// writing sweep that puts every entry at its place in that order. This cuts
-// the serial chain per thread ~16x (small systems have few atoms to spread
-// over the device, so the one-thread-per-atom build was latency bound).
-constexpr int kNbrLanes = 16;
+// writing sweep that puts every entry at its place in that order. With 16
+// lanes the serial chain per thread is ~16x shorter, which small systems
+// (too few atoms to fill the device) need; large systems keep one lane per
+// atom, whose list writes stay coalesced across the wavefront.
+constexpr int kNbrManyAtoms = 1 << 16;  // from here on one lane per atom
 
+template <int kNbrLanes>
 __global__ __launch_bounds__(kBlock) void k_nbr_build(NbrBuildArgs A) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(t / kNbrLanes), l = (int)(t % kNbrLanes);
@@ -400,8 +402,13 @@ void launch_bucket_sort(int nbucket, const int *start, int *items, hipStream_t s
   if (nbucket > 0) hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks(nbucket)), dim3(kBlock), 0, st, nbucket, start, items);
 }
 void launch_nbr_build(const NbrBuildArgs &A, hipStream_t st) {
-  const long threads = (long)A.n * kNbrLanes;
-  if (A.n > 0) hipLaunchKernelGGL(k_nbr_build, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, A);
+  if (A.n <= 0) return;
+  if (A.n >= kNbrManyAtoms) {
+    hipLaunchKernelGGL(k_nbr_build<1>, dim3((unsigned)((A.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, A);
+  } else {
+    const long threads = (long)A.n * 16;
+    hipLaunchKernelGGL(k_nbr_build<16>, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, A);
+  }
 }
 void launch_keys(int n, const double *rx, const double *ry, const double *rz, const double L[3],
                  double *kx, double *ky, double *kz, hipStream_t st) {
