@@ -82,7 +82,16 @@ typedef struct {
  *  - Zeeman (Sec. 2, Eq. s_hamiltonian): -sum_i g mu_B B.s_i.
  *  - Uniaxial anisotropy (appendix A.2): -sum_i K (s_i.n)^2.
  *  - Spin bath (Sec. 4.1, Eq. sLLG): transverse damping lambda and white
- *    noise at temperature T with D_S = lambda (1 + lambda^2) k_B T / hbar. */
+ *    noise at temperature T with D_S = lambda (1 + lambda^2) k_B T / hbar.
+ *  - Lattice bath (Sec. 4.2, Eq. p_advance_T): friction -lat_gamma p/m
+ *    (lat_gamma in amu/ps; 0 = no bath) and white noise at lat_temperature
+ *    with D_L = 2 lat_gamma k_B T (Einstein relation). The friction and
+ *    noise are integrated exactly over |dt| (an Ornstein-Uhlenbeck step,
+ *    v <- c v + sqrt((1 - c^2) k_B T/m) xi, c = exp(-lat_gamma |dt|/m)) in
+ *    the middle of each drift: half drift, bath, half drift. The normals
+ *    come from Philox4x32-10 keyed by seed XOR 0x6C61747469636521 with
+ *    counter (atom id, step low, step high, replica << 2), Box-Muller as
+ *    for the spin noise. Ignored on a frozen lattice. */
 typedef struct {
     int morse_on;
     double morse_D, morse_alpha, morse_r0, morse_rc;
@@ -94,6 +103,8 @@ typedef struct {
     double aniso_n[3];
     double lambda;
     double temperature;
+    double lat_gamma;
+    double lat_temperature;
 } sl_potential;
 
 /* Energies in eV: kinetic sum_i m v^2/2, pair, exchange, Zeeman, anisotropy. */
@@ -183,6 +194,15 @@ int sl_get_energy(sl_system *sys, sl_energy *out);
 
 /* M = sum_i s_i of the current state. Synchronises. */
 int sl_get_magnetization(sl_system *sys, double M[3]);
+
+/* Temperatures of the current state (Sec. 4.2), in K: the kinetic lattice
+ * temperature T_L = (2 / 3 N k_B) sum_i m_i v_i^2 / 2 (Eq.
+ * lattice_temperature) and the spin temperature of Nurdin et al.
+ * T_S = (hbar / 2 k_B) sum_i |s_i x omega_i|^2 / sum_i s_i.omega_i (Eq.
+ * spin_temperature) with the conservative omega_i (exchange, Zeeman and
+ * anisotropy). Either pointer may be NULL. Both are deterministic device
+ * reductions. Synchronises. */
+int sl_get_temperatures(sl_system *sys, double *T_lattice, double *T_spin);
 
 /* Samples recorded every thermo_every steps since the last call: up to max
  * entries of (step, energy, M[3]); *count receives the number written. */
@@ -364,6 +384,8 @@ int sl_batch_set_state(sl_batch *b, int r, const double *x, const double *v,
 int sl_batch_get_state(sl_batch *b, int r, double *x, double *v, double *s,
                        int where);
 int sl_batch_get_energy(sl_batch *b, int r, sl_energy *out);
+/* Temperatures of replica r (same contract as sl_get_temperatures). */
+int sl_batch_get_temperatures(sl_batch *b, int r, double *T_lattice, double *T_spin);
 /* n steps of length dt for every replica. */
 int sl_batch_step(sl_batch *b, int64_t n, double dt);
 

@@ -930,6 +930,37 @@ static double max_speed(const orc_sys *S)
     return m;
 }
 
+/* Drift of one step. Without a lattice bath: r += dt v. With the bath of
+ * Eq. p_advance_T (friction -gamma_L p/m and a white-noise force whose
+ * strength follows from the Einstein relation, D_L = 2 gamma_L k_B T_L),
+ * the friction-plus-noise part is an Ornstein-Uhlenbeck process in v that
+ * is integrated exactly over |dt| and placed between two half drifts:
+ *   r += (dt/2) v;  v = c v + sqrt((1 - c^2) k_B T_L / m) xi;  r += (dt/2) v
+ * with c = exp(-gamma_L |dt| / m) and xi three standard normals from the
+ * Philox stream keyed by seed XOR ORC_LATTICE_KEY_TAG, counter (atom id,
+ * step, replica, 0). k_B T / m in eV/amu becomes (A/ps)^2 through 1/ORC_MVV2E. */
+static void drift(orc_sys *S, double dt)
+{
+    const orc_pot *p = &S->pot;
+    if (!(p->lat_gamma > 0.0)) {
+        for (int i = 0; i < 3 * S->N; ++i) S->r[i] += dt * S->v[i];
+        return;
+    }
+    const uint64_t key = S->seed ^ ORC_LATTICE_KEY_TAG;
+    for (int i = 0; i < S->N; ++i) {
+        double *ri = S->r + 3 * i, *vi = S->v + 3 * i;
+        const double c = exp(-p->lat_gamma * fabs(dt) / S->m[i]);
+        const double sig = sqrt((1.0 - c * c) * ORC_KB * p->lat_temperature / S->m[i] / ORC_MVV2E);
+        double xi[3];
+        orc_gauss3(key, (uint32_t)i, S->step, S->replica, 0, xi);
+        for (int a = 0; a < 3; ++a) {
+            ri[a] += 0.5 * dt * vi[a];
+            vi[a] = c * vi[a] + sig * xi[a];
+            ri[a] += 0.5 * dt * vi[a];
+        }
+    }
+}
+
 int orc_step(orc_sys *S, int64_t n, double dt)
 {
     const double ftm2v = 1.0 / ORC_MVV2E;
@@ -969,7 +1000,7 @@ int orc_step(orc_sys *S, int64_t n, double dt)
                 S->v[3 * i + a] += dt / 2.0 * S->F[3 * i + a] / S->m[i] * ftm2v;
         sweep(S, h, 0, 0);
         sweep(S, h, 1, 1);
-        for (int i = 0; i < 3 * S->N; ++i) S->r[i] += dt * S->v[i];
+        drift(S, dt);
         sweep(S, h, 0, 2);
         sweep(S, h, 1, 3);
         forces(S);

@@ -37,7 +37,12 @@ typedef struct {
     double aniso_n[3];           /* unit axis */
     double lambda;               /* transverse spin damping */
     double temperature;          /* spin bath temperature, K */
+    double lat_gamma;            /* lattice friction gamma_L, amu/ps (0: no bath) */
+    double lat_temperature;      /* lattice bath temperature, K */
 } orc_pot;
+
+/* Key tag of the lattice-noise Philox stream: key = seed XOR this value. */
+#define ORC_LATTICE_KEY_TAG 0x6C61747469636521ull
 
 enum { ORC_COLOUR = 0, ORC_SEQ = 1, ORC_SECT = 2, ORC_JACOBI = 3 };
 

@@ -22,6 +22,8 @@ MUB = 5.7883818060e-5
 MVV2E = 1.0364269652680506e-4
 
 COLOUR, SEQ, SECT, JACOBI = 0, 1, 2, 3
+# key tag of the lattice-noise Philox stream (key = seed XOR tag)
+LATTICE_KEY_TAG = 0x6C61747469636521
 
 
 def build(force: bool = True) -> str:
@@ -45,7 +47,8 @@ class Pot(C.Structure):
                 ("ex_delta", C.c_double), ("ex_rc", C.c_double),
                 ("zeeman_g", C.c_double), ("B", C.c_double * 3),
                 ("aniso_K", C.c_double), ("aniso_n", C.c_double * 3),
-                ("lam", C.c_double), ("temperature", C.c_double)]
+                ("lam", C.c_double), ("temperature", C.c_double),
+                ("lat_gamma", C.c_double), ("lat_temperature", C.c_double)]
 
 
 class MlpCfg(C.Structure):

@@ -222,6 +222,9 @@ void make_potconst(sl_system *S) {
   c.langevin = p.lambda > 0.0 ? 1 : 0;
   c.lam = p.lambda;
   c.lamfac = 1.0 / (1.0 + p.lambda * p.lambda);
+  c.lat_on = (p.lat_gamma > 0.0 && !S->prm.frozen) ? 1 : 0;
+  c.lat_g = p.lat_gamma;
+  c.lat_kT = kKb * p.lat_temperature;
 }
 
 template <typename real>
@@ -823,6 +826,9 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   F.err = S->err;
   F.wmask = A.wmask;
   F.frozen = S->prm.frozen;
+  F.seed = S->prm.seed;
+  F.replica = S->prm.replica;
+  F.step = boundary;
   CHK(ensure_table(S, posbuf));
   if (mode & kModeNext) S->tab_ok[1 - posbuf] = S->jc_ok[1 - posbuf] = false;
   const int slot = (int)(boundary & 3);
@@ -1098,11 +1104,12 @@ int sl_set_potential(sl_system *S, const sl_potential *pot) {
   const double vals[] = {pot->morse_D, pot->morse_alpha, pot->morse_r0, pot->morse_rc,
                          pot->ex_alpha, pot->ex_gamma, pot->ex_delta, pot->ex_rc, pot->zeeman_g,
                          pot->B[0], pot->B[1], pot->B[2], pot->aniso_K, pot->aniso_n[0],
-                         pot->aniso_n[1], pot->aniso_n[2], pot->lambda, pot->temperature};
+                         pot->aniso_n[1], pot->aniso_n[2], pot->lambda, pot->temperature,
+                         pot->lat_gamma, pot->lat_temperature};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(S, SL_E_ARG, "non-finite potential parameter");
   if (pot->ex_delta <= 0.0 || pot->ex_rc < 0.0 || pot->morse_rc < 0.0 || pot->lambda < 0.0 ||
-      pot->temperature < 0.0)
+      pot->temperature < 0.0 || pot->lat_gamma < 0.0 || pot->lat_temperature < 0.0)
     return fail(S, SL_E_ARG, "invalid potential parameter");
   S->pot = *pot;
   S->have_pot = true;
@@ -1582,6 +1589,37 @@ int fields_now(sl_system *S, double *F, double *hw, int where) {
   return sticky_code(S);
 }
 
+// Lattice temperature from the kinetic energy (Eq. lattice_temperature) and
+// spin temperature (Eq. spin_temperature): T_S = sum |s x h|^2 / (2 k_B sum
+// s.h) with h = hbar omega, both sums fixed-order device reductions.
+template <typename real>
+int temps_now(sl_system *S, double *TL, double *TS) {
+  const int n = S->n;
+  if (TL) {
+    double e[8];
+    CHK(energy_now<real>(S, e));
+    *TL = n > 0 ? 2.0 * e[0] / (3.0 * n * kKb) : 0.0;
+  }
+  if (TS) {
+    double *ts = nullptr;
+    HIPCHK(S, dalloc(&ts, 2 * (size_t)n + 2));
+    CHK(ensure_table(S, S->pos));
+    FieldArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.ts = ts;
+    launch_fields<real>(view<real>(S, S->pos), S->pc, A, S->st);
+    launch_sum_d(ts, n, ts + 2 * (size_t)n, S->st);
+    launch_sum_d(ts + n, n, ts + 2 * (size_t)n + 1, S->st);
+    double h[2] = {0.0, 0.0};
+    hipError_t e1 = hipMemcpyAsync(h, ts + 2 * (size_t)n, 2 * sizeof(double), hipMemcpyDeviceToHost, S->st);
+    hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(S->st) : e1;
+    dfree(ts);
+    HIPCHK(S, e2);
+    *TS = h[1] != 0.0 ? h[0] / (2.0 * kKb * h[1]) : 0.0;
+  }
+  return sticky_code(S);
+}
+
 int mlp_trainer(sl_mlp *m, const sl_dataset *d) {
   sl_system *S = m->trainer;
   if (S && (S->n != d->n_atoms || S->L[0] != d->box[0] || S->L[1] != d->box[1] || S->L[2] != d->box[2])) {
@@ -1629,6 +1667,14 @@ int mfail_str(sl_mlp *m, int code, const std::string &msg) {
 }
 
 extern "C" {
+
+int sl_get_temperatures(sl_system *S, double *T_lattice, double *T_spin) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  CHK(sl_synchronize(S));
+  CHK(ensure_ready(S));
+  return S->prec == SL_FP64 ? temps_now<double>(S, T_lattice, T_spin)
+                            : temps_now<float>(S, T_lattice, T_spin);
+}
 
 int sl_get_fields(sl_system *S, double *F, double *hw, int where) {
   if (!S) return fail(S, SL_E_ARG, "NULL system");
@@ -2028,6 +2074,8 @@ int fill_desc(sl_batch *B, int r, double dt, int64_t target, RepDesc<real> &d) {
   d.F.wmask = A.wmask;
   d.F.dslot = S->dslot;
   d.F.done = S->done;
+  d.F.seed = S->prm.seed;
+  d.F.replica = S->prm.replica;
   if (S->K > kMaxClass) return bfail(B, SL_E_COLOR, "replica " + std::to_string(r) + " has too many colours");
   d.K = S->K;
   for (int c = 0; c <= S->K; ++c) d.off[c] = S->class_off[c];
@@ -2375,6 +2423,12 @@ int sl_batch_get_state(sl_batch *B, int r, double *x, double *v, double *s, int 
 int sl_batch_get_energy(sl_batch *B, int r, sl_energy *e) {
   if (!B || r < 0 || r >= B->R) return bfail(B, SL_E_ARG, "bad replica");
   BSYS(B, r, sl_get_energy(B->sys[r], e));
+  return SL_OK;
+}
+
+int sl_batch_get_temperatures(sl_batch *B, int r, double *T_lattice, double *T_spin) {
+  if (!B || r < 0 || r >= B->R) return bfail(B, SL_E_ARG, "bad replica");
+  BSYS(B, r, sl_get_temperatures(B->sys[r], T_lattice, T_spin));
   return SL_OK;
 }
 

@@ -49,7 +49,13 @@ struct PotConst {
   int aniso_on;
   int langevin;
   double lam, lamfac;  // lambda, 1/(1+lambda^2)
+  int lat_on;          // lattice bath
+  double lat_g;        // gamma_L, amu/ps
+  double lat_kT;       // k_B T_L, eV
 };
+
+// Key tag of the lattice-noise Philox stream (key = seed ^ tag).
+constexpr uint64_t kLatticeKeyTag = 0x6C61747469636521ull;
 
 // Per-system geometry and arrays (device pointers).
 // Learned pair potential as a cubic Hermite spline of the network's raw
@@ -156,6 +162,9 @@ struct ForceArgs {
                                     // slot k holds a same-colour (watched) pair
   int *err;                   // sticky error word (device)
   int frozen;
+  uint64_t seed;              // Philox seed and replica of the lattice noise
+  uint32_t replica;
+  int64_t step;               // step whose drift this launch computes
 };
 
 enum : int { kModeFinal = 1, kModeNext = 2, kModeEnergy = 4 };

@@ -343,7 +343,23 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
       }
       if (MODE & kModeNext) {
         vx += kx; vy += ky; vz += kz;
-        const double nx = rix + A.dt * vx, ny = riy + A.dt * vy, nz = riz + A.dt * vz;
+        double nx, ny, nz;
+        if (P.lat_on) {
+          // lattice bath (Eq. p_advance_T): exact Ornstein-Uhlenbeck step of
+          // the friction and noise between two half drifts
+          const double hd = 0.5 * A.dt;
+          const double c = exp(-P.lat_g * fabs(A.dt) / m);
+          const double sg = sqrt((1.0 - c * c) * P.lat_kT / m * A.ftm2v);
+          double g[3];
+          gauss3(A.seed ^ kLatticeKeyTag, (uint32_t)S.id[i], A.step, A.replica, 0, g);
+          nx = rix + hd * vx; ny = riy + hd * vy; nz = riz + hd * vz;
+          vx = c * vx + sg * g[0];
+          vy = c * vy + sg * g[1];
+          vz = c * vz + sg * g[2];
+          nx += hd * vx; ny += hd * vy; nz += hd * vz;
+        } else {
+          nx = rix + A.dt * vx; ny = riy + A.dt * vy; nz = riz + A.dt * vz;
+        }
         A.nx[i] = nx; A.ny[i] = ny; A.nz[i] = nz;
         if (!isfinite(nx) || !isfinite(ny) || !isfinite(nz)) atomicOr(A.err, kErrNonFinite);
       }
@@ -488,6 +504,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
     // of the next step goes to buffer pos
     ForceArgs F = d.F;
     F.dt = d.dt;
+    F.step = step + 1;
     F.nx = d.V[pos].rx == nullptr ? nullptr : const_cast<double *>(d.V[pos].rx);
     F.ny = const_cast<double *>(d.V[pos].ry);
     F.nz = const_cast<double *>(d.V[pos].rz);
@@ -599,6 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, 
   const int64_t boundary = d.step + bp.kk + bp.after;
   ForceArgs F = d.F;
   F.dt = d.dt;
+  F.step = boundary;
   F.nx = const_cast<double *>(d.V[1 - cur].rx);
   F.ny = const_cast<double *>(d.V[1 - cur].ry);
   F.nz = const_cast<double *>(d.V[1 - cur].rz);

@@ -43,6 +43,8 @@ struct FieldArgs {
   double wF, wW;
   float *gF, *gW;                 // residual adjoints [3][n]
   double *lossp;                  // per-atom loss terms
+  double *ts;                     // spin-temperature terms [2][n]:
+                                  // |s x h_i|^2, s.h_i (h_i = hbar omega_i)
 };
 template <typename real>
 void launch_fields(const SysView<real> &S, const PotConst &P, const FieldArgs &A, hipStream_t st);

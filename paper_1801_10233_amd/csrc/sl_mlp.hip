@@ -657,6 +657,16 @@ __global__ void k_fields(SysView<real> S, PotConst P, FieldArgs A) {
     e += 0.5 * (V - J * sij);
   }
   const size_t n = S.n;
+  if (A.ts) {
+    // conservative field hbar omega_i: exchange, Zeeman and anisotropy
+    const double sn = P.an[0] * six + P.an[1] * siy + P.an[2] * siz;
+    const double wx = hw[0] + P.zB[0] + 2.0 * P.aK * sn * P.an[0];
+    const double wy = hw[1] + P.zB[1] + 2.0 * P.aK * sn * P.an[1];
+    const double wz = hw[2] + P.zB[2] + 2.0 * P.aK * sn * P.an[2];
+    const double cx = siy * wz - siz * wy, cy = siz * wx - six * wz, cz = six * wy - siy * wx;
+    A.ts[i] = cx * cx + cy * cy + cz * cz;
+    A.ts[n + i] = six * wx + siy * wy + siz * wz;
+  }
   if (A.F) { A.F[i] = f[0]; A.F[n + i] = f[1]; A.F[2 * n + i] = f[2]; }
   if (A.hw) { A.hw[i] = hw[0]; A.hw[n + i] = hw[1]; A.hw[2 * n + i] = hw[2]; }
   if (A.e) A.e[i] = e;

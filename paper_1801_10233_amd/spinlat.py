@@ -41,7 +41,8 @@ EXPORTS = [
     "sl_create", "sl_destroy", "sl_set_state", "sl_get_state", "sl_set_potential",
     "sl_set_neighbor", "sl_set_neighbor_list", "sl_get_neighbor_list",
     "sl_set_coloring", "sl_get_coloring", "sl_set_step", "sl_step",
-    "sl_get_energy", "sl_get_magnetization", "sl_get_thermo", "sl_get_stats",
+    "sl_get_energy", "sl_get_magnetization", "sl_get_temperatures", "sl_get_thermo",
+    "sl_get_stats",
     "sl_synchronize", "sl_set_tuning", "sl_get_tuning", "sl_autotune", "sl_set_profiling",
     "sl_set_mlp_mode",
     "sl_get_profile", "sl_last_error",
@@ -49,7 +50,7 @@ EXPORTS = [
     "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
     "sl_mlp_loss_grad", "sl_mlp_train",
     "sl_batch_create", "sl_batch_destroy", "sl_batch_set_state", "sl_batch_get_state",
-    "sl_batch_get_energy", "sl_batch_step", "sl_batch_set_lanes", "sl_batch_get_stats",
+    "sl_batch_get_energy", "sl_batch_get_temperatures", "sl_batch_step", "sl_batch_set_lanes", "sl_batch_get_stats",
     "sl_batch_last_error", "sl_batch_set_mode", "sl_batch_get_mode", "sl_batch_autotune",
 ]
 
@@ -69,7 +70,8 @@ class sl_potential(C.Structure):
                 ("ex_alpha", C.c_double), ("ex_gamma", C.c_double), ("ex_delta", C.c_double),
                 ("ex_rc", C.c_double), ("zeeman_g", C.c_double), ("B", C.c_double * 3),
                 ("aniso_K", C.c_double), ("aniso_n", C.c_double * 3), ("lam", C.c_double),
-                ("temperature", C.c_double)]
+                ("temperature", C.c_double), ("lat_gamma", C.c_double),
+                ("lat_temperature", C.c_double)]
 
 
 class sl_energy(C.Structure):
@@ -144,6 +146,7 @@ def lib():
         "sl_step": ([vp, i64, C.c_double], C.c_int),
         "sl_get_energy": ([vp, C.POINTER(sl_energy)], C.c_int),
         "sl_get_magnetization": ([vp, dp], C.c_int),
+        "sl_get_temperatures": ([vp, dp, dp], C.c_int),
         "sl_get_thermo": ([vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(sl_energy), dp, ip],
                           C.c_int),
         "sl_get_stats": ([vp, C.POINTER(sl_stats)], C.c_int),
@@ -172,6 +175,7 @@ def lib():
         "sl_batch_set_state": ([vp, C.c_int, vp, vp, vp, vp, C.c_int], C.c_int),
         "sl_batch_get_state": ([vp, C.c_int, vp, vp, vp, C.c_int], C.c_int),
         "sl_batch_get_energy": ([vp, C.c_int, C.POINTER(sl_energy)], C.c_int),
+        "sl_batch_get_temperatures": ([vp, C.c_int, dp, dp], C.c_int),
         "sl_batch_step": ([vp, i64, C.c_double], C.c_int),
         "sl_batch_set_lanes": ([vp, C.c_int], C.c_int),
         "sl_batch_get_stats": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), ip], C.c_int),
@@ -332,6 +336,12 @@ class System:
         M = (C.c_double * 3)()
         self._check(lib().sl_get_magnetization(self.h, M))
         return np.array(list(M))
+
+    def temperatures(self):
+        """(T_L, T_S) of the current state in K."""
+        tl, ts = C.c_double(), C.c_double()
+        self._check(lib().sl_get_temperatures(self.h, C.byref(tl), C.byref(ts)))
+        return tl.value, ts.value
 
     def thermo(self, max_samples=1 << 16):
         steps = (C.c_int64 * max_samples)()
@@ -528,6 +538,12 @@ class Batch:
         self._check(lib().sl_batch_get_energy(self.h, int(r), C.byref(e)))
         return dict(kin=e.kin, pair=e.pair, exchange=e.exchange, zeeman=e.zeeman,
                     aniso=e.aniso, total=e.total)
+
+    def temperatures(self, r):
+        """(T_L, T_S) of replica r in K."""
+        tl, ts = C.c_double(), C.c_double()
+        self._check(lib().sl_batch_get_temperatures(self.h, int(r), C.byref(tl), C.byref(ts)))
+        return tl.value, ts.value
 
     def step(self, n, dt):
         self._check(lib().sl_batch_step(self.h, int(n), float(dt)))

@@ -122,7 +122,7 @@ def _pot(**kw):
                 morse_rc=0.0, morse_shift=1, ex_alpha=0.0, ex_gamma=0.0,
                 ex_delta=1.0, ex_rc=0.0, zeeman_g=2.0, B=(0.0, 0.0, 0.0),
                 aniso_K=0.0, aniso_n=(0.0, 0.0, 1.0), lam=0.0,
-                temperature=0.0)
+                temperature=0.0, lat_gamma=0.0, lat_temperature=0.0)
     base.update(kw)
     return base
 
@@ -158,6 +158,42 @@ def large_langevin(n: int = 60, nve: bool = False, spin_seed: int = 3001,
                     maxwell_velocities(m, 300.0, vel_seed),
                     random_unit_spins(N, spin_seed), m, box, pot, False, 1e-4,
                     1000, 0.3, key)
+
+
+def two_thermostat(n: int = 10, bath: str = "spin", T: float = 300.0,
+                   lam: float = 0.01, lat_gamma: float = 50.0,
+                   spin_seed: int = 6001, vel_seed: int = 6002,
+                   key: int = 6003) -> Workload:
+    """Relaxation with one bath (Sec. 4.2): bath="spin" starts a lattice at
+    rest (T_L = 0) with random spins under a spin bath at T; bath="lattice"
+    starts spins aligned along z (T_S = 0) and Maxwell velocities at T under
+    a lattice bath at T (friction lat_gamma, amu/ps)."""
+    r, box = bcc_lattice(n)
+    N = r.shape[0]
+    m = np.full(N, FE_MASS)
+    if bath == "spin":
+        v = np.zeros((N, 3))
+        s = random_unit_spins(N, spin_seed)
+        pot = _pot(**EXCHANGE_BJ, **MORSE_BJ, lam=lam, temperature=T)
+    else:
+        v = maxwell_velocities(m, T, vel_seed)
+        s = np.tile([0.0, 0.0, 1.0], (N, 1))
+        pot = _pot(**EXCHANGE_BJ, **MORSE_BJ, lat_gamma=lat_gamma,
+                   lat_temperature=T)
+    return Workload("two_thermostat_" + bath, n, r, v, s, m, box, pot, False,
+                    1e-4, 10000, 0.3, key)
+
+
+def energy_repartition(n: int = 10, T: float = 200.0, spin_seed: int = 7001,
+                       vel_seed: int = 7002) -> Workload:
+    """NVE run from random (paramagnetic) spins and Maxwell velocities at T
+    on the perfect lattice (Sec. 4.2, the energy-repartition run)."""
+    r, box = bcc_lattice(n)
+    N = r.shape[0]
+    m = np.full(N, FE_MASS)
+    return Workload("energy_repartition", n, r, maxwell_velocities(m, T, vel_seed),
+                    random_unit_spins(N, spin_seed), m, box,
+                    _pot(**EXCHANGE_BJ, **MORSE_BJ), False, 1e-4, 10000, 0.3, 0)
 
 
 def batched_replicas(R: int = 64, seed: int = 4004, n_lo: int = 8,

@@ -25,7 +25,8 @@ GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
 ZERO_POT = dict(morse_on=0, morse_D=0.0, morse_alpha=0.0, morse_r0=0.0,
                 morse_rc=0.0, morse_shift=1, ex_alpha=0.0, ex_gamma=0.0,
                 ex_delta=1.0, ex_rc=0.0, zeeman_g=2.0, B=(0.0, 0.0, 0.0),
-                aniso_K=0.0, aniso_n=(0.0, 0.0, 1.0), lam=0.0, temperature=0.0)
+                aniso_K=0.0, aniso_n=(0.0, 0.0, 1.0), lam=0.0, temperature=0.0,
+                lat_gamma=0.0, lat_temperature=0.0)
 
 
 def pot(**kw):
@@ -385,6 +386,87 @@ def test_langevin_equilibrium_strong_damping():
 def test_langevin_equilibrium_weak_damping():
     mz, ts, Lx = _langevin_run(0.01, 100.0, 100.0, 1e-3, 20.0, 30.0, N=128)
     assert abs(mz.mean() - Lx) < 0.06, (mz.mean(), Lx)
+
+
+# --------------------------------------------------------------------------
+# P17: lattice bath (Sec. 4.2, Eq. p_advance_T). Free atoms (no pair terms)
+# turn the lattice step into the Ornstein-Uhlenbeck process of the bath
+# alone. Its exact moments: started at v0, after n steps of dt every
+# velocity component has mean c^n v0 and variance (1 - c^2n) k_B T/m, with
+# c = exp(-gamma_L dt/m), for any dt; the mean displacement tends to the
+# continuous m v0 (1 - e^(-gamma t/m))/gamma to O(dt^2). A wrong friction
+# rate, noise strength (the Einstein relation D_L = 2 gamma_L k_B T), unit
+# conversion or noise-stream reuse across atoms moves one of these by many
+# standard errors.
+def _free_atoms(N, gamma, T, seed=7):
+    p = pot(lat_gamma=gamma, lat_temperature=T)
+    rng = np.random.default_rng(3)
+    box = [60.0, 60.0, 60.0]
+    r = rng.random((N, 3)) * 60.0
+    v = np.zeros((N, 3)); v[:, 0] = 10.0
+    s = np.tile([0.0, 0.0, 1.0], (N, 1))
+    m = np.full(N, W.FE_MASS)
+    return O.Oracle(r, v, s, m, box, p, frozen=False, skin=0.3, seed=seed), r, m
+
+
+def test_lattice_bath_ornstein_uhlenbeck_moments():
+    N, T, dt, n = 6000, 500.0, 1e-3, 40
+    gamma = math.log(2.0) * W.FE_MASS / (n * dt)      # c^n = 1/2
+    o, r0, m = _free_atoms(N, gamma, T)
+    o.step(n, dt)
+    r, v, _ = o.get_state()
+    c = math.exp(-gamma * dt / W.FE_MASS)
+    var = (1 - c ** (2 * n)) * O.KB * T / W.FE_MASS / O.MVV2E
+    mean = c ** n * 10.0
+    se = math.sqrt(var / N)
+    assert abs(v[:, 0].mean() - mean) < 5 * se, (v[:, 0].mean(), mean)
+    assert abs(v[:, 1].mean()) < 5 * se and abs(v[:, 2].mean()) < 5 * se
+    dv = v - np.array([mean, 0.0, 0.0])
+    sv = (dv ** 2).mean()
+    assert abs(sv / var - 1) < 5 * math.sqrt(2.0 / (3 * N)), (sv, var)
+    # components independent and Gaussian (fourth moment 3 var^2)
+    k4 = (dv ** 4).mean() / sv ** 2
+    assert abs(k4 - 3.0) < 0.2
+    # mean drift against the continuous process (relative O(dt^2) error)
+    t = n * dt
+    x_ct = W.FE_MASS * 10.0 * (1 - math.exp(-gamma * t / W.FE_MASS)) / gamma
+    dx = (r - r0)[:, 0].mean()
+    assert abs(dx - x_ct) < 5 * math.sqrt(var) * t / math.sqrt(N) + 1e-3 * x_ct
+
+
+def test_lattice_bath_stationary_temperature_any_dt():
+    # exact OU update: the stationary kinetic temperature is T at any step
+    # size (a first-order Euler noise term would heat by a factor 1/(1-c/2...))
+    for dt in (1e-3, 2e-2):
+        N, T = 3000, 800.0
+        gamma = 4.0 * W.FE_MASS / (50 * 1e-3)
+        o, _, _ = _free_atoms(N, gamma, T)
+        o.step(60, dt)
+        TL = []
+        for _ in range(10):
+            o.step(3, dt)
+            TL.append(o.temperatures()[0])
+        assert abs(np.mean(TL) / T - 1) < 5 * math.sqrt(2.0 / (3 * N * 10)) + 0.01, (dt, np.mean(TL))
+
+
+def test_lattice_bath_off_is_nve_and_noise_uses_tagged_stream():
+    w = W.coupled_nve(n=4)
+    a = O.Oracle(w.r, w.v, w.s, w.mass, w.box, dict(w.pot, lat_gamma=0.0, lat_temperature=300.0),
+                 frozen=False, skin=w.skin)
+    b = O.Oracle(w.r, w.v, w.s, w.mass, w.box, w.pot, frozen=False, skin=w.skin)
+    a.step(20, 1e-4); b.step(20, 1e-4)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+    # one step of free atoms: v1 = c v0 + sig xi with xi from the tagged
+    # stream at (atom id, step 0, replica 0, sub 0)
+    o, _, _ = _free_atoms(4, 100.0, 300.0, seed=11)
+    o.step(1, 1e-3)
+    _, v, _ = o.get_state()
+    c = math.exp(-100.0 * 1e-3 / W.FE_MASS)
+    sig = math.sqrt((1 - c * c) * O.KB * 300.0 / W.FE_MASS / O.MVV2E)
+    for i in range(4):
+        xi = O.gauss3(11 ^ O.LATTICE_KEY_TAG, i, 0, 0, 0)
+        np.testing.assert_allclose(v[i], c * np.array([10.0, 0, 0]) + sig * xi, rtol=1e-13, atol=1e-13)
 
 
 # --------------------------------------------------------------------------
