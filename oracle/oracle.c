@@ -93,6 +93,22 @@ double orc_J(const orc_pot *p, double r, double *dJdr)
     return J;
 }
 
+/* The three-parameter Bethe-Slater radial form 4 a u (1 - g u) e^{-u},
+ * u = (r/d)^2, cut at rc, and its derivative: the exchange J(r) above, and
+ * also the Neel function g1(r) (appendix A, spin-orbit coupling) and the
+ * magnitude of the Dzyaloshinskii-Moriya vector. */
+static double bethe_slater(double a, double g, double dl, double rc, double r, double *dfdr)
+{
+    if (!(r < rc) || a == 0.0) {
+        *dfdr = 0.0;
+        return 0.0;
+    }
+    double u = (r / dl) * (r / dl);
+    double e = exp(-u);
+    *dfdr = 8.0 * a * r / (dl * dl) * e * (1.0 - (1.0 + 2.0 * g) * u + g * u * u);
+    return 4.0 * a * u * (1.0 - g * u) * e;
+}
+
 /* Morse pair potential M(r) = D (exp(-2 a (r-r0)) - 2 exp(-a (r-r0))) and
  * its derivative. */
 static double morse_raw(const orc_pot *p, double r, double *dM)
@@ -692,10 +708,74 @@ int orc_build_now(orc_sys *S)
  * Each unordered pair enters the energy once (the paper writes ordered-pair
  * sums but its force equation has no factor two).
  * ---------------------------------------------------------------------- */
+/* Spin-orbit pair terms of one pair (appendix A), with d = r_i - r_j:
+ *   Neel:  E = -g1(r) [(e.s_i)(e.s_j) - s_i.s_j/3]   (any sign of e)
+ *   DMI:   E = D_ij . (s_i x s_j),  D_ij = dm(r) (n x e_ij), e_ij = -d/r.
+ * Each unordered pair counts once (as the exchange, G4 reading). soc_field
+ * adds -dE/ds_i (the pair's share of hbar omega_i), soc_force adds -dE/dr_i,
+ * soc_pair_energy returns (E_Neel, E_DMI). */
+static void soc_radial(const orc_pot *p, double r, double *g1, double *dg1, double *dm, double *ddm)
+{
+    *g1 = bethe_slater(p->neel_alpha, p->neel_gamma, p->neel_delta, p->neel_rc, r, dg1);
+    *dm = bethe_slater(p->dmi_alpha, p->dmi_gamma, p->dmi_delta, p->dmi_rc, r, ddm);
+}
+
+static void soc_field(const orc_pot *p, const double d[3], const double *sj, double acc[3])
+{
+    double r = norm3(d), g1, dg1, dm, ddm;
+    soc_radial(p, r, &g1, &dg1, &dm, &ddm);
+    double e[3] = {-d[0] / r, -d[1] / r, -d[2] / r};
+    double es = dot3(e, sj);
+    double D[3], Dxs[3];
+    cross3(p->dmi_n, e, D);
+    for (int a = 0; a < 3; ++a) D[a] *= dm;
+    cross3(D, sj, Dxs);            /* -d/ds_i [D.(s_i x s_j)] = D x s_j */
+    for (int a = 0; a < 3; ++a)
+        acc[a] += g1 * (es * e[a] - sj[a] / 3.0) + Dxs[a];
+}
+
+static void soc_force(const orc_pot *p, const double d[3], const double *si, const double *sj,
+                      double f[3])
+{
+    double r = norm3(d), g1, dg1, dm, ddm;
+    soc_radial(p, r, &g1, &dg1, &dm, &ddm);
+    double a = dot3(si, d), b = dot3(sj, d), c = dot3(si, sj), r2 = r * r;
+    /* Neel: E = -g1 (a b / r^2 - c/3) */
+    for (int k = 0; k < 3; ++k)
+        f[k] += dg1 * (d[k] / r) * (a * b / r2 - c / 3.0) +
+                g1 * ((si[k] * b + sj[k] * a) / r2 - 2.0 * a * b * d[k] / (r2 * r2));
+    /* DMI: E = -(dm/r) d.Y with Y = (s_i x s_j) x n */
+    double X[3], Y[3];
+    cross3(si, sj, X);
+    cross3(X, p->dmi_n, Y);
+    double dY = dot3(d, Y);
+    for (int k = 0; k < 3; ++k)
+        f[k] += (ddm / r - dm / r2) * dY * d[k] / r + dm / r * Y[k];
+}
+
+static void soc_pair_energy(const orc_pot *p, const double d[3], const double *si,
+                            const double *sj, double *en, double *ed)
+{
+    double r = norm3(d), g1, dg1, dm, ddm;
+    soc_radial(p, r, &g1, &dg1, &dm, &ddm);
+    double e[3] = {-d[0] / r, -d[1] / r, -d[2] / r};
+    *en = -g1 * (dot3(e, si) * dot3(e, sj) - dot3(si, sj) / 3.0);
+    double D[3], X[3];
+    cross3(p->dmi_n, e, D);
+    cross3(si, sj, X);
+    *ed = dm * dot3(D, X);
+}
+
+static int soc_on(const orc_pot *p)
+{
+    return p->neel_alpha != 0.0 || p->dmi_alpha != 0.0;
+}
+
 static void omega_i(const orc_sys *S, int i, double w[3])
 {
     const orc_pot *p = &S->pot;
     double acc[3] = {0.0, 0.0, 0.0};
+    const int soc = soc_on(p);
     for (int k = S->off[i]; k < S->off[i] + S->nspin[i]; ++k) {
         int j = S->idx[k];
         double d[3];
@@ -704,6 +784,7 @@ static void omega_i(const orc_sys *S, int i, double w[3])
         double J, dJ, V, dV;
         pair_terms(S, r, &J, &dJ, &V, &dV);
         for (int a = 0; a < 3; ++a) acc[a] += J * S->s[3 * j + a];
+        if (soc) soc_field(p, d, S->s + 3 * j, acc);
     }
     const double *si = S->s + 3 * i;
     double sn = dot3(si, p->aniso_n);
@@ -733,6 +814,8 @@ static void forces(orc_sys *S)
             pair_terms(S, r, &J, &dJ, &V, &dV);
             double c = -dV + dJ * dot3(S->s + 3 * i, S->s + 3 * j);
             for (int a = 0; a < 3; ++a) f[a] += c * d[a] / r;
+            if (soc_on(&S->pot) && k < S->off[i] + S->nspin[i])
+                soc_force(&S->pot, d, S->s + 3 * i, S->s + 3 * j, f);
         }
         for (int a = 0; a < 3; ++a) S->F[3 * i + a] = f[a];
     }
@@ -1033,6 +1116,11 @@ void orc_energy(orc_sys *S, double e[6])
             pair_terms(S, r, &J, &dJ, &V, &dV);
             if (!S->frozen) pair += V;
             ex -= J * dot3(S->s + 3 * i, S->s + 3 * j);
+            if (soc_on(p) && k < S->off[i] + S->nspin[i]) {
+                double en, ed;
+                soc_pair_energy(p, d, S->s + 3 * i, S->s + 3 * j, &en, &ed);
+                ex += en + ed;
+            }
         }
         const double *si = S->s + 3 * i;
         zee -= p->zeeman_g * ORC_MUB * dot3(p->B, si);
@@ -1041,6 +1129,24 @@ void orc_energy(orc_sys *S, double e[6])
     }
     e[0] = kin; e[1] = pair; e[2] = ex; e[3] = zee; e[4] = an;
     e[5] = kin + pair + ex + zee + an;
+}
+
+void orc_soc_energy(orc_sys *S, double *neel, double *dmi)
+{
+    if (!S->have_list) orc_build_now(S);
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < S->N; ++i)
+        for (int k = S->off[i]; k < S->off[i] + S->nspin[i]; ++k) {
+            int j = S->idx[k];
+            if (j <= i) continue;
+            double d[3], en, ed;
+            min_image(S->L, S->r + 3 * i, S->r + 3 * j, d);
+            soc_pair_energy(&S->pot, d, S->s + 3 * i, S->s + 3 * j, &en, &ed);
+            a += en;
+            b += ed;
+        }
+    *neel = a;
+    *dmi = b;
 }
 
 void orc_magnetization(const orc_sys *S, double M[3])

@@ -39,6 +39,12 @@ typedef struct {
     double temperature;          /* spin bath temperature, K */
     double lat_gamma;            /* lattice friction gamma_L, amu/ps (0: no bath) */
     double lat_temperature;      /* lattice bath temperature, K */
+    /* Neel pseudo-dipolar pair anisotropy, g1(r) of Bethe-Slater form */
+    double neel_alpha, neel_gamma, neel_delta, neel_rc;
+    /* Dzyaloshinskii-Moriya pair term, D_ij = d(r) (dmi_n x e_ij) with d(r)
+     * of Bethe-Slater form and e_ij = (r_j - r_i)/r_ij */
+    double dmi_alpha, dmi_gamma, dmi_delta, dmi_rc;
+    double dmi_n[3];
 } orc_pot;
 
 /* Key tag of the lattice-noise Philox stream: key = seed XOR this value. */
@@ -78,6 +84,9 @@ int orc_step(orc_sys *S, int64_t n, double dt);
 /* Observables of the current state. e = {kin, pair, exchange, zeeman, aniso,
  * total} in eV; M = sum_i s_i. */
 void orc_energy(orc_sys *S, double e[6]);
+/* The Neel and DMI parts of the magnetic pair energy (both are included in
+ * e[2] of orc_energy). */
+void orc_soc_energy(orc_sys *S, double *neel, double *dmi);
 void orc_magnetization(const orc_sys *S, double M[3]);
 void orc_temperatures(orc_sys *S, double *T_lattice, double *T_spin);
 void orc_omega_all(orc_sys *S, double *w);     /* conservative omega, rad/ps */

@@ -48,7 +48,12 @@ class Pot(C.Structure):
                 ("zeeman_g", C.c_double), ("B", C.c_double * 3),
                 ("aniso_K", C.c_double), ("aniso_n", C.c_double * 3),
                 ("lam", C.c_double), ("temperature", C.c_double),
-                ("lat_gamma", C.c_double), ("lat_temperature", C.c_double)]
+                ("lat_gamma", C.c_double), ("lat_temperature", C.c_double),
+                ("neel_alpha", C.c_double), ("neel_gamma", C.c_double),
+                ("neel_delta", C.c_double), ("neel_rc", C.c_double),
+                ("dmi_alpha", C.c_double), ("dmi_gamma", C.c_double),
+                ("dmi_delta", C.c_double), ("dmi_rc", C.c_double),
+                ("dmi_n", C.c_double * 3)]
 
 
 class MlpCfg(C.Structure):
@@ -59,7 +64,7 @@ class MlpCfg(C.Structure):
 def make_pot(d: dict) -> Pot:
     p = Pot()
     for k, v in d.items():
-        if k in ("B", "aniso_n"):
+        if k in ("B", "aniso_n", "dmi_n"):
             setattr(p, k, (C.c_double * 3)(*v))
         else:
             setattr(p, k, v)
@@ -98,6 +103,7 @@ def lib():
         L.orc_energy.argtypes = [C.c_void_p, dp]
         L.orc_magnetization.argtypes = [C.c_void_p, dp]
         L.orc_temperatures.argtypes = [C.c_void_p, dp, dp]
+        L.orc_soc_energy.argtypes = [C.c_void_p, dp, dp]
         L.orc_omega_all.argtypes = [C.c_void_p, dp]
         L.orc_force_all.argtypes = [C.c_void_p, dp]
         L.orc_J.restype = C.c_double
@@ -254,6 +260,11 @@ class Oracle:
         M = np.zeros(3)
         lib().orc_magnetization(self.h, _dp(M))
         return M
+
+    def soc_energy(self):
+        a = C.c_double(); b = C.c_double()
+        lib().orc_soc_energy(self.h, C.byref(a), C.byref(b))
+        return a.value, b.value
 
     def temperatures(self):
         tl = C.c_double(); ts = C.c_double()

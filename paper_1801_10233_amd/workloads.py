@@ -93,6 +93,12 @@ def thermal_displacements(N: int, sigma: float, seed: int):
 EXCHANGE_BJ = dict(ex_alpha=0.1, ex_gamma=0.2, ex_delta=1.2, ex_rc=3.5)
 MORSE_BJ = dict(morse_on=1, morse_D=0.4174, morse_alpha=1.3885, morse_r0=2.845,
                 morse_rc=5.0, morse_shift=1)
+# Spin-orbit pair terms (appendix A; the paper's Co parameters are not
+# available): Neel g1(r) and the DMI magnitude in the Bethe-Slater form,
+# a tenth and a twentieth of the exchange scale, DMI vector n x e_ij, n = z.
+NEEL_BJ = dict(neel_alpha=0.01, neel_gamma=0.2, neel_delta=1.2, neel_rc=3.5)
+DMI_BJ = dict(dmi_alpha=0.005, dmi_gamma=0.0, dmi_delta=1.4, dmi_rc=3.5,
+              dmi_n=(0.0, 0.0, 1.0))
 
 
 @dataclasses.dataclass
@@ -122,7 +128,10 @@ def _pot(**kw):
                 morse_rc=0.0, morse_shift=1, ex_alpha=0.0, ex_gamma=0.0,
                 ex_delta=1.0, ex_rc=0.0, zeeman_g=2.0, B=(0.0, 0.0, 0.0),
                 aniso_K=0.0, aniso_n=(0.0, 0.0, 1.0), lam=0.0,
-                temperature=0.0, lat_gamma=0.0, lat_temperature=0.0)
+                temperature=0.0, lat_gamma=0.0, lat_temperature=0.0,
+                neel_alpha=0.0, neel_gamma=0.0, neel_delta=1.0, neel_rc=0.0,
+                dmi_alpha=0.0, dmi_gamma=0.0, dmi_delta=1.0, dmi_rc=0.0,
+                dmi_n=(0.0, 0.0, 1.0))
     base.update(kw)
     return base
 
@@ -194,6 +203,23 @@ def energy_repartition(n: int = 10, T: float = 200.0, spin_seed: int = 7001,
     return Workload("energy_repartition", n, r, maxwell_velocities(m, T, vel_seed),
                     random_unit_spins(N, spin_seed), m, box,
                     _pot(**EXCHANGE_BJ, **MORSE_BJ), False, 1e-4, 10000, 0.3, 0)
+
+
+def soc_coupled(n: int = 8, T: float = 300.0, frozen: bool = False,
+                spin_seed: int = 8001, vel_seed: int = 8002, key: int = 8003,
+                lam: float = 0.0) -> Workload:
+    """Coupled run with the Neel and DMI pair terms added to the exchange
+    (Sec. 2, appendix A): Maxwell velocities at T (zero when frozen), random
+    spins, optional spin bath."""
+    r, box = bcc_lattice(n)
+    N = r.shape[0]
+    m = np.full(N, FE_MASS)
+    v = np.zeros((N, 3)) if frozen else maxwell_velocities(m, T, vel_seed)
+    pot = _pot(**EXCHANGE_BJ, **({} if frozen else MORSE_BJ), **NEEL_BJ, **DMI_BJ,
+               B=(0.0, 0.0, 0.5), lam=lam, temperature=T if lam > 0 else 0.0)
+    return Workload("soc_frozen" if frozen else "soc_coupled", n, r, v,
+                    random_unit_spins(N, spin_seed), m, box, pot, frozen, 1e-4,
+                    1000, 0.0 if frozen else 0.3, key)
 
 
 def batched_replicas(R: int = 64, seed: int = 4004, n_lo: int = 8,
