@@ -91,7 +91,17 @@ typedef struct {
  *    the middle of each drift: half drift, bath, half drift. The normals
  *    come from Philox4x32-10 keyed by seed XOR 0x6C61747469636521 with
  *    counter (atom id, step low, step high, replica << 2), Box-Muller as
- *    for the spin noise. Ignored on a frozen lattice. */
+ *    for the spin noise. Ignored on a frozen lattice.
+ *  - Spin-orbit pair terms (appendix A), each unordered pair once, with
+ *    g1(r) and d(r) of the Bethe-Slater form above (neel_* and dmi_*
+ *    parameters, each cut at its own rc, which must not exceed ex_rc: the
+ *    exchange cutoff is the radius of every magnetic pair term):
+ *      Neel pseudo-dipolar: -sum_{i<j} g1(r) [(e.s_i)(e.s_j) - s_i.s_j/3]
+ *      Dzyaloshinskii-Moriya: sum_{i<j} D_ij.(s_i x s_j),
+ *        D_ij = d(r) (dmi_n x e_ij), e_ij = (r_j - r_i)/r_ij, |dmi_n| = 1.
+ *    Available with the analytic exchange only (not with a learned pair
+ *    potential); their field on s_i depends on s_j only, so the colour
+ *    sweeps keep their exact properties. */
 typedef struct {
     int morse_on;
     double morse_D, morse_alpha, morse_r0, morse_rc;
@@ -105,9 +115,14 @@ typedef struct {
     double temperature;
     double lat_gamma;
     double lat_temperature;
+    double neel_alpha, neel_gamma, neel_delta, neel_rc;
+    double dmi_alpha, dmi_gamma, dmi_delta, dmi_rc;
+    double dmi_n[3];
 } sl_potential;
 
-/* Energies in eV: kinetic sum_i m v^2/2, pair, exchange, Zeeman, anisotropy. */
+/* Energies in eV: kinetic sum_i m v^2/2, pair, exchange (the magnetic pair
+ * energy: exchange plus the Neel and DMI terms when set), Zeeman,
+ * anisotropy. */
 typedef struct {
     double kin, pair, exchange, zeeman, aniso, total;
 } sl_energy;

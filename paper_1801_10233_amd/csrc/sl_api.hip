@@ -225,6 +225,24 @@ void make_potconst(sl_system *S) {
   c.lat_on = (p.lat_gamma > 0.0 && !S->prm.frozen) ? 1 : 0;
   c.lat_g = p.lat_gamma;
   c.lat_kT = kKb * p.lat_temperature;
+  const bool neel = p.neel_alpha != 0.0 && p.neel_rc > 0.0;
+  const bool dmi = p.dmi_alpha != 0.0 && p.dmi_rc > 0.0;
+  c.soc_on = (neel || dmi) ? 1 : 0;
+  if (neel) {
+    c.nA4 = 4.0 * p.neel_alpha;
+    c.nG = p.neel_gamma;
+    c.nInvD2 = 1.0 / (p.neel_delta * p.neel_delta);
+    c.nRc2 = p.neel_rc * p.neel_rc;
+    c.nA8InvD2 = 8.0 * p.neel_alpha / (p.neel_delta * p.neel_delta);
+  }
+  if (dmi) {
+    c.dA4 = 4.0 * p.dmi_alpha;
+    c.dG = p.dmi_gamma;
+    c.dInvD2 = 1.0 / (p.dmi_delta * p.dmi_delta);
+    c.dRc2 = p.dmi_rc * p.dmi_rc;
+    c.dA8InvD2 = 8.0 * p.dmi_alpha / (p.dmi_delta * p.dmi_delta);
+    for (int d = 0; d < 3; ++d) c.dn[d] = p.dmi_n[d];
+  }
 }
 
 template <typename real>
@@ -250,7 +268,7 @@ SysView<real> view(sl_system *S, int posbuf) {
   v.id = A.id;
   v.tab = nullptr;
   v.spl = SplineView{};
-  const bool jc_use = (!S->mlp || S->mlp_mode == SL_MLP_SPLINE) && S->jcache > 0;
+  const bool jc_use = (!S->mlp || S->mlp_mode == SL_MLP_SPLINE) && S->jcache > 0 && !S->pc.soc_on;
   v.jc = (jc_use && S->jc_ok[posbuf]) ? (const real *)S->jc[posbuf] : nullptr;
   if (S->mlp && S->mlp_mode == SL_MLP_SPLINE) v.spl = S->mlp->spline_view();
   else if (S->mlp) v.tab = S->tab[posbuf];
@@ -516,7 +534,8 @@ int ensure_table(sl_system *S, int b) {
 // per drift; the analytic potential only).
 template <typename real>
 int ensure_jcache(sl_system *S, int b) {
-  if ((S->mlp && S->mlp_mode != SL_MLP_SPLINE) || S->jcache <= 0 || S->jc_ok[b]) return SL_OK;
+  if ((S->mlp && S->mlp_mode != SL_MLP_SPLINE) || S->jcache <= 0 || S->pc.soc_on || S->jc_ok[b])
+    return SL_OK;
   if (!S->jc[b]) {
     real *p = nullptr;
     HIPCHK(S, dalloc(&p, (size_t)S->ld * S->max_nbr));
@@ -1105,12 +1124,27 @@ int sl_set_potential(sl_system *S, const sl_potential *pot) {
                          pot->ex_alpha, pot->ex_gamma, pot->ex_delta, pot->ex_rc, pot->zeeman_g,
                          pot->B[0], pot->B[1], pot->B[2], pot->aniso_K, pot->aniso_n[0],
                          pot->aniso_n[1], pot->aniso_n[2], pot->lambda, pot->temperature,
-                         pot->lat_gamma, pot->lat_temperature};
+                         pot->lat_gamma, pot->lat_temperature, pot->neel_alpha,
+                         pot->neel_gamma, pot->neel_delta, pot->neel_rc, pot->dmi_alpha,
+                         pot->dmi_gamma, pot->dmi_delta, pot->dmi_rc, pot->dmi_n[0],
+                         pot->dmi_n[1], pot->dmi_n[2]};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(S, SL_E_ARG, "non-finite potential parameter");
   if (pot->ex_delta <= 0.0 || pot->ex_rc < 0.0 || pot->morse_rc < 0.0 || pot->lambda < 0.0 ||
       pot->temperature < 0.0 || pot->lat_gamma < 0.0 || pot->lat_temperature < 0.0)
     return fail(S, SL_E_ARG, "invalid potential parameter");
+  const bool neel = pot->neel_alpha != 0.0 && pot->neel_rc > 0.0;
+  const bool dmi = pot->dmi_alpha != 0.0 && pot->dmi_rc > 0.0;
+  if ((neel && (pot->neel_delta <= 0.0 || pot->neel_rc > pot->ex_rc)) ||
+      (dmi && (pot->dmi_delta <= 0.0 || pot->dmi_rc > pot->ex_rc)))
+    return fail(S, SL_E_ARG, "Neel/DMI terms need delta > 0 and a cutoff within ex_rc");
+  if (dmi) {
+    const double nn = pot->dmi_n[0] * pot->dmi_n[0] + pot->dmi_n[1] * pot->dmi_n[1] +
+                      pot->dmi_n[2] * pot->dmi_n[2];
+    if (std::fabs(nn - 1.0) > 1e-12) return fail(S, SL_E_ARG, "dmi_n must be a unit vector");
+  }
+  if ((neel || dmi) && S->mlp)
+    return fail(S, SL_E_ARG, "Neel/DMI terms need the analytic exchange (a learned pair potential is set)");
   S->pot = *pot;
   S->have_pot = true;
   make_potconst(S);
@@ -1477,6 +1511,7 @@ int sl_set_mlp(sl_system *S, sl_mlp *m) {
   if (m) {
     if (S->prec != SL_FP32) return fail(S, SL_E_ARG, "the learned potential runs in the FP32 form");
     if (!m->have_weights) return fail(S, SL_E_STATE, "the MLP has no weights");
+    if (S->pc.soc_on) return fail(S, SL_E_ARG, "the Neel/DMI terms need the analytic exchange");
     (void)hipStreamSynchronize(m->st);
     for (int b = 0; b < 2; ++b)
       if (!S->tab[b]) HIPCHK(S, dalloc(&S->tab[b], (size_t)S->ld * S->max_nbr));
@@ -2056,6 +2091,14 @@ int bfail(sl_batch *B, int code, const std::string &msg) {
     if (rc_) return bfail((B), rc_, "replica " + std::to_string(r) + ": " + (B)->sys[r]->last_err); \
   } while (0)
 
+// Whether any replica has the spin-orbit pair terms (their kernel variants
+// then serve every replica; zero coefficients leave the others unchanged).
+bool batch_soc(const sl_batch *B) {
+  for (const sl_system *S : B->sys)
+    if (S->pc.soc_on) return true;
+  return false;
+}
+
 // Descriptor of replica r for the batched kernels (current buffers, class
 // offsets, step, predictor state of the last two boundaries).
 template <typename real>
@@ -2109,7 +2152,7 @@ int batch_launch(sl_batch *B) {
     B->exec = nullptr;
     B->graph = nullptr;
     BCHK(B, hipStreamBeginCapture(B->st, hipStreamCaptureModeThreadLocal));
-    launch_batch_run<real>((RepDesc<real> *)B->d_desc, B->R, B->lanes, B->st);
+    launch_batch_run<real>((RepDesc<real> *)B->d_desc, B->R, B->lanes, batch_soc(B), B->st);
     BCHK(B, hipStreamEndCapture(B->st, &B->graph));
     BCHK(B, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     B->graph_lanes = B->lanes;
@@ -2246,7 +2289,7 @@ int batch_step_phased(sl_batch *B, int64_t n, double dt) {
   BatchPhase bp{};
   bp.kk = 0;
   bp.after = 0;
-  launch_batch_force<real>(D, R, max_n, kModeNext, bp, B->lanes, B->st);
+  launch_batch_force<real>(D, R, max_n, kModeNext, bp, B->lanes, batch_soc(B), B->st);
   BCHK(B, hipEventRecord(B->ev[0], B->st));
   for (int64_t kk = 0; kk < n; ++kk) {
     if (kk > 0) {
@@ -2291,7 +2334,7 @@ int batch_step_phased(sl_batch *B, int64_t n, double dt) {
       bp.Kmax = Kmax;
       for (int p = 0; p < 2 * Kmax - 1; ++p) {
         bp.p = p;
-        launch_batch_spin<real>(D, R, max_class, bp, B->lanes, B->st);
+        launch_batch_spin<real>(D, R, max_class, bp, B->lanes, batch_soc(B), B->st);
       }
     }
     const int mode = kk + 1 < n ? (kModeFinal | kModeNext) : kModeFinal;
@@ -2307,7 +2350,7 @@ int batch_step_phased(sl_batch *B, int64_t n, double dt) {
       S->step = b;
     }
     bp.after = 1;
-    launch_batch_force<real>(D, R, max_n, mode, bp, B->lanes, B->st);
+    launch_batch_force<real>(D, R, max_n, mode, bp, B->lanes, batch_soc(B), B->st);
     bp.after = 0;
     BCHK(B, hipEventRecord(B->ev[(kk + 1) & 3], B->st));
     B->launches += 2 * (2 * Kmax - 1) + 1;

@@ -52,6 +52,12 @@ struct PotConst {
   int lat_on;          // lattice bath
   double lat_g;        // gamma_L, amu/ps
   double lat_kT;       // k_B T_L, eV
+  // spin-orbit pair terms (Neel g1 and DMI magnitude, Bethe-Slater form:
+  // 4 alpha, gamma, 1/delta^2, rc^2, 8 alpha/delta^2) and the DMI axis
+  int soc_on;
+  double nA4, nG, nInvD2, nRc2, nA8InvD2;
+  double dA4, dG, dInvD2, dRc2, dA8InvD2;
+  double dn[3];
 };
 
 // Key tag of the lattice-noise Philox stream (key = seed ^ tag).
@@ -234,6 +240,79 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   e = fma(-x * y, y, 1.0);
   y = fma(0.5 * y, e, y);
   return y;
+}
+
+// -------------------------------------------------------------------------
+// Spin-orbit pair terms (appendix A) of one pair, d = r_i - r_j, r2 = |d|^2:
+//   Neel: E = -g1(r) [(e.s_i)(e.s_j) - s_i.s_j/3]
+//   DMI:  E = D_ij.(s_i x s_j), D_ij = dm(r) (n x e_ij), e_ij = -d/r
+// with g1 and dm of the Bethe-Slater form. soc_field adds the pair's share
+// of hbar omega_i (-dE/ds_i, a function of s_j only); soc_force adds
+// -dE/dr_i and returns E.
+template <typename real>
+__device__ __forceinline__ void soc_field(const PotConst &P, double dxd, double dyd, double dzd,
+                                          double r2d, real sx, real sy, real sz, real &hx,
+                                          real &hy, real &hz) {
+  const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd;
+  if (r2d < P.nRc2) {
+    const real u = (real)(r2d * P.nInvD2);
+    const real g1 = (real)P.nA4 * u * ((real)1 - (real)P.nG * u) * exp(-u);
+    const real t = g1 * (dx * sx + dy * sy + dz * sz) / (real)r2d;
+    const real th = g1 / (real)3;
+    hx += t * dx - th * sx;
+    hy += t * dy - th * sy;
+    hz += t * dz - th * sz;
+  }
+  if (r2d < P.dRc2) {
+    const real u = (real)(r2d * P.dInvD2);
+    const real dm = (real)P.dA4 * u * ((real)1 - (real)P.dG * u) * exp(-u);
+    const real f = -dm * (real)(1.0 / sqrt(r2d));
+    const real n0 = (real)P.dn[0], n1 = (real)P.dn[1], n2 = (real)P.dn[2];
+    const real Dx = f * (n1 * dz - n2 * dy), Dy = f * (n2 * dx - n0 * dz), Dz = f * (n0 * dy - n1 * dx);
+    hx += Dy * sz - Dz * sy;
+    hy += Dz * sx - Dx * sz;
+    hz += Dx * sy - Dy * sx;
+  }
+}
+
+template <typename real>
+__device__ __forceinline__ real soc_force(const PotConst &P, double dxd, double dyd, double dzd,
+                                          double r2d, real six, real siy, real siz, real sjx,
+                                          real sjy, real sjz, real &fx, real &fy, real &fz) {
+  const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd, r2 = (real)r2d;
+  const real rinv = (real)(1.0 / sqrt(r2d)), r = r2 * rinv;
+  real en = 0;
+  if (r2d < P.nRc2) {
+    const real u = (real)(r2d * P.nInvD2), eu = exp(-u);
+    const real g1 = (real)P.nA4 * u * ((real)1 - (real)P.nG * u) * eu;
+    const real dg1 = (real)P.nA8InvD2 * r * eu *
+                     ((real)1 - ((real)1 + (real)2 * (real)P.nG) * u + (real)P.nG * u * u);
+    const real a = six * dx + siy * dy + siz * dz, b = sjx * dx + sjy * dy + sjz * dz;
+    const real c = six * sjx + siy * sjy + siz * sjz;
+    const real ang = a * b / r2 - c / (real)3;
+    const real kr = dg1 * rinv * ang - (real)2 * g1 * a * b / (r2 * r2);
+    const real kb = g1 / r2;
+    fx += kr * dx + kb * (six * b + sjx * a);
+    fy += kr * dy + kb * (siy * b + sjy * a);
+    fz += kr * dz + kb * (siz * b + sjz * a);
+    en -= g1 * ang;
+  }
+  if (r2d < P.dRc2) {
+    const real u = (real)(r2d * P.dInvD2), eu = exp(-u);
+    const real dm = (real)P.dA4 * u * ((real)1 - (real)P.dG * u) * eu;
+    const real ddm = (real)P.dA8InvD2 * r * eu *
+                     ((real)1 - ((real)1 + (real)2 * (real)P.dG) * u + (real)P.dG * u * u);
+    const real n0 = (real)P.dn[0], n1 = (real)P.dn[1], n2 = (real)P.dn[2];
+    const real Xx = siy * sjz - siz * sjy, Xy = siz * sjx - six * sjz, Xz = six * sjy - siy * sjx;
+    const real Yx = Xy * n2 - Xz * n1, Yy = Xz * n0 - Xx * n2, Yz = Xx * n1 - Xy * n0;
+    const real dY = dx * Yx + dy * Yy + dz * Yz;
+    const real kr = (ddm * rinv - dm / r2) * dY * rinv, ky = dm * rinv;
+    fx += kr * dx + ky * Yx;
+    fy += kr * dy + ky * Yy;
+    fz += kr * dz + ky * Yz;
+    en -= dm * rinv * dY;
+  }
+  return en;
 }
 
 // -------------------------------------------------------------------------

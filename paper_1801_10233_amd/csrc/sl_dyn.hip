@@ -66,6 +66,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
         jj[c] = (unsigned)j < (unsigned)S.n ? j : i;
       }
       real qx[CH], qy[CH], qz[CH], J[CH];
+      real hx[CH], hy[CH], hz[CH];  // MLP == 4: Neel and DMI field of the pair
       double px[CH], py[CH], pz[CH];
       float jt[CH];
       real jr[CH];
@@ -105,6 +106,10 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
           const real u = (real)(r2 * P.eInvD2);
           const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
           J[c] = (in && r2 < rs2) ? Jc : (real)0;
+          if (MLP == 4) {
+            hx[c] = hy[c] = hz[c] = (real)0;
+            if (in) soc_field<real>(P, dx, dy, dz, r2, qx[c], qy[c], qz[c], hx[c], hy[c], hz[c]);
+          }
         }
       }
 #pragma unroll
@@ -112,6 +117,11 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
         ax += J[c] * qx[c];
         ay += J[c] * qy[c];
         az += J[c] * qz[c];
+        if (MLP == 4) {
+          ax += hx[c];
+          ay += hy[c];
+          az += hz[c];
+        }
       }
     }
   }
@@ -245,12 +255,19 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
         }
         double px[kForceChunk], py[kForceChunk], pz[kForceChunk];
         real sij[kForceChunk];
+        real qx[kForceChunk], qy[kForceChunk], qz[kForceChunk];  // MLP == 4
         float4 tt[kForceChunk];
 #pragma unroll
         for (int c = 0; c < kForceChunk; ++c) {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
         }
-        if (seg == 0) {
+        if (seg == 0 && MLP == 4) {
+#pragma unroll
+          for (int c = 0; c < kForceChunk; ++c) {
+            qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
+            sij[c] = six * qx[c] + siy * qy[c] + siz * qz[c];
+          }
+        } else if (seg == 0) {
 #pragma unroll
           for (int c = 0; c < kForceChunk; ++c)
             sij[c] = six * S.sx[jj[c]] + siy * S.sy[jj[c]] + siz * S.sz[jj[c]];
@@ -278,7 +295,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           const real r = (real)(r2d * rinvd), rinv = (real)rinvd;
           real cc = 0;
           if (MLP == 2) tt[c] = use ? spline_phys(S.spl, (float)r) : make_float4(0.f, 0.f, 0.f, 0.f);
-          if (MLP) {
+          if (MLP == 1 || MLP == 2) {
             // learned phi'(r), J'(r) (and phi, J for energies) from the table
             cc = -(real)tt[c].w + (real)tt[c].y * sij[c];
             if (MODE & kModeEnergy) {
@@ -310,6 +327,11 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           fx += cr * dx;
           fy += cr * dy;
           fz += cr * dz;
+          if (MLP == 4 && seg == 0 && use) {
+            const real es = soc_force<real>(P, dxd, dyd, dzd, r2d, six, siy, siz, qx[c], qy[c],
+                                            qz[c], fx, fy, fz);
+            if (MODE & kModeEnergy) ee += (real)0.5 * es;
+          }
         }
       }
     }
@@ -459,7 +481,7 @@ __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, 
 // before the previous one decides; if a rebuild is due the replica stops
 // and the host rebuilds it before the next launch. Replicas are
 // independent, so no two workgroups ever wait on each other.
-template <typename real, int LANES>
+template <typename real, int LANES, int MLP>
 __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
   __shared__ double redm[kBatchBlock / 64][3];
   __shared__ double bcast[3];
@@ -494,7 +516,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
         const int b0 = d.off[c], b1 = d.off[c + 1];
         for (int base = b0; base < b1; base += per) {
           const int i = base + t / LANES;
-          spin_update<real, true, true, LANES, 0>(V, d.P, i, i < b1, l, nrep, st, sb, d.h, d.amp,
+          spin_update<real, true, true, LANES, MLP>(V, d.P, i, i < b1, l, nrep, st, sb, d.h, d.amp,
                                                      d.seed, d.replica, d.rs2);
         }
         __syncthreads();
@@ -514,8 +536,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
     for (int base = 0; base < W.n; base += per) {
       const int i = base + t / LANES;
       double e[8], dm = 0.0, vm = 0.0, wm = kInf;
-      if (next) force_atom<real, kModeFinal | kModeNext, LANES, 0>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
-      else force_atom<real, kModeFinal, LANES, 0>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
+      if (next) force_atom<real, kModeFinal | kModeNext, LANES, MLP>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
+      else force_atom<real, kModeFinal, LANES, MLP>(W, d.P, F, i, i < W.n, l, e, dm, vm, wm);
       bdm = fmax(bdm, dm);
       bvm = fmax(bvm, vm);
       bwm = fmin(bwm, wm);
@@ -553,17 +575,23 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_run(RepDesc<real> *D) {
   }
 }
 
-template <typename real>
-void launch_batch_run(RepDesc<real> *D, int R, int lanes, hipStream_t st) {
-  if (R <= 0) return;
+template <typename real, int MLP>
+static void batch_run_lanes(RepDesc<real> *D, int R, int lanes, hipStream_t st) {
   switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_batch_run<real, 1>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
-    case 2: hipLaunchKernelGGL((k_batch_run<real, 2>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
-    default: hipLaunchKernelGGL((k_batch_run<real, 4>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
+    case 1: hipLaunchKernelGGL((k_batch_run<real, 1, MLP>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
+    case 2: hipLaunchKernelGGL((k_batch_run<real, 2, MLP>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
+    default: hipLaunchKernelGGL((k_batch_run<real, 4, MLP>), dim3(R), dim3(kBatchBlock), 0, st, D); break;
   }
 }
-template void launch_batch_run<double>(RepDesc<double> *, int, int, hipStream_t);
-template void launch_batch_run<float>(RepDesc<float> *, int, int, hipStream_t);
+
+template <typename real>
+void launch_batch_run(RepDesc<real> *D, int R, int lanes, bool soc, hipStream_t st) {
+  if (R <= 0) return;
+  if (soc) batch_run_lanes<real, 4>(D, R, lanes, st);
+  else batch_run_lanes<real, 0>(D, R, lanes, st);
+}
+template void launch_batch_run<double>(RepDesc<double> *, int, int, bool, hipStream_t);
+template void launch_batch_run<float>(RepDesc<float> *, int, int, bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Phase-batched replicas: one launch covers every replica's share of one
@@ -571,7 +599,7 @@ template void launch_batch_run<float>(RepDesc<float> *, int, int, hipStream_t);
 // the whole device works on each phase instead of one workgroup per replica.
 // All replicas advance in lockstep inside a call; replica r is at step
 // d.step + kk with its current positions in buffer d.pos ^ (kk & 1).
-template <typename real, int LANES>
+template <typename real, int LANES, int MLP>
 __global__ __launch_bounds__(kBlock) void k_batch_spin(const RepDesc<real> *D, BatchPhase bp) {
   const RepDesc<real> &d = D[blockIdx.y];
   const int K = d.K;
@@ -594,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_spin(const RepDesc<real> *D, B
   const int64_t step = d.step + bp.kk;
   const int64_t st[kMaxRep] = {step, step, step, step};
   const int sb[kMaxRep] = {s0, s1, 0, 0};
-  spin_update<real, true, true, LANES, 0>(d.V[bp.half == 0 ? pos : 1 - pos], d.P, i, i < b1,
+  spin_update<real, true, true, LANES, MLP>(d.V[bp.half == 0 ? pos : 1 - pos], d.P, i, i < b1,
                                              l, nrep, st, sb, d.h, d.amp, d.seed, d.replica,
                                              d.rs2);
 }
@@ -602,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_spin(const RepDesc<real> *D, B
 // Force, kicks and drift of every replica at one boundary, with each
 // replica's rebuild predictor reduced by its own last block into its own
 // pinned slot (as k_force does for one system).
-template <typename real, int MODE, int LANES>
+template <typename real, int MODE, int LANES, int MLP>
 __global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, BatchPhase bp) {
   __shared__ double redm[kBlock / 64][3];
   __shared__ int last;
@@ -623,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, 
   F.host_out = d.ring + 8 * (int)(boundary & 3);
   const int i = (int)blockIdx.x * per + (int)threadIdx.x / LANES, l = threadIdx.x & (LANES - 1);
   double e[8], dm = 0.0, vm = 0.0, wm = kInf;
-  force_atom<real, MODE, LANES, 0>(d.V[cur], d.P, F, i, i < n, l, e, dm, vm, wm);
+  force_atom<real, MODE, LANES, MLP>(d.V[cur], d.P, F, i, i < n, l, e, dm, vm, wm);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double a = wave_max(dm), b = wave_max(vm), c = wave_min(wm);
   if (lane == 0) { redm[wv][0] = a; redm[wv][1] = b; redm[wv][2] = c; }
@@ -657,43 +685,57 @@ __global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, 
   }
 }
 
-template <typename real>
-void launch_batch_spin(const RepDesc<real> *D, int R, int max_class, const BatchPhase &bp,
-                       int lanes, hipStream_t st) {
-  if (R <= 0 || max_class <= 0) return;
-  const int per = kBlock / lanes;
-  const dim3 grid((max_class + per - 1) / per, R);
+template <typename real, int MLP>
+static void batch_spin_lanes(const RepDesc<real> *D, const dim3 &grid, const BatchPhase &bp,
+                             int lanes, hipStream_t st) {
   switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_batch_spin<real, 1>), grid, dim3(kBlock), 0, st, D, bp); break;
-    case 4: hipLaunchKernelGGL((k_batch_spin<real, 4>), grid, dim3(kBlock), 0, st, D, bp); break;
-    default: hipLaunchKernelGGL((k_batch_spin<real, 2>), grid, dim3(kBlock), 0, st, D, bp); break;
+    case 1: hipLaunchKernelGGL((k_batch_spin<real, 1, MLP>), grid, dim3(kBlock), 0, st, D, bp); break;
+    case 4: hipLaunchKernelGGL((k_batch_spin<real, 4, MLP>), grid, dim3(kBlock), 0, st, D, bp); break;
+    default: hipLaunchKernelGGL((k_batch_spin<real, 2, MLP>), grid, dim3(kBlock), 0, st, D, bp); break;
   }
 }
 
-template <typename real, int MODE>
+template <typename real>
+void launch_batch_spin(const RepDesc<real> *D, int R, int max_class, const BatchPhase &bp,
+                       int lanes, bool soc, hipStream_t st) {
+  if (R <= 0 || max_class <= 0) return;
+  const int per = kBlock / lanes;
+  const dim3 grid((max_class + per - 1) / per, R);
+  if (soc) batch_spin_lanes<real, 4>(D, grid, bp, lanes, st);
+  else batch_spin_lanes<real, 0>(D, grid, bp, lanes, st);
+}
+
+template <typename real, int MODE, int MLP>
 static void batch_force_mode(const RepDesc<real> *D, const dim3 &grid, const BatchPhase &bp,
                              int lanes, hipStream_t st) {
   switch (lanes) {
-    case 2: hipLaunchKernelGGL((k_batch_force<real, MODE, 2>), grid, dim3(kBlock), 0, st, D, bp); break;
-    case 4: hipLaunchKernelGGL((k_batch_force<real, MODE, 4>), grid, dim3(kBlock), 0, st, D, bp); break;
-    default: hipLaunchKernelGGL((k_batch_force<real, MODE, 1>), grid, dim3(kBlock), 0, st, D, bp); break;
+    case 2: hipLaunchKernelGGL((k_batch_force<real, MODE, 2, MLP>), grid, dim3(kBlock), 0, st, D, bp); break;
+    case 4: hipLaunchKernelGGL((k_batch_force<real, MODE, 4, MLP>), grid, dim3(kBlock), 0, st, D, bp); break;
+    default: hipLaunchKernelGGL((k_batch_force<real, MODE, 1, MLP>), grid, dim3(kBlock), 0, st, D, bp); break;
   }
+}
+
+template <typename real, int MLP>
+static void batch_force_any(const RepDesc<real> *D, const dim3 &grid, int mode,
+                            const BatchPhase &bp, int lanes, hipStream_t st) {
+  if (mode == kModeNext) batch_force_mode<real, kModeNext, MLP>(D, grid, bp, lanes, st);
+  else if (mode == kModeFinal) batch_force_mode<real, kModeFinal, MLP>(D, grid, bp, lanes, st);
+  else batch_force_mode<real, kModeFinal | kModeNext, MLP>(D, grid, bp, lanes, st);
 }
 
 template <typename real>
 void launch_batch_force(const RepDesc<real> *D, int R, int max_n, int mode, const BatchPhase &bp,
-                        int lanes, hipStream_t st) {
+                        int lanes, bool soc, hipStream_t st) {
   if (R <= 0 || max_n <= 0) return;
   const int per = kBlock / lanes;
   const dim3 grid((max_n + per - 1) / per, R);
-  if (mode == kModeNext) batch_force_mode<real, kModeNext>(D, grid, bp, lanes, st);
-  else if (mode == kModeFinal) batch_force_mode<real, kModeFinal>(D, grid, bp, lanes, st);
-  else batch_force_mode<real, kModeFinal | kModeNext>(D, grid, bp, lanes, st);
+  if (soc) batch_force_any<real, 4>(D, grid, mode, bp, lanes, st);
+  else batch_force_any<real, 0>(D, grid, mode, bp, lanes, st);
 }
-template void launch_batch_spin<double>(const RepDesc<double> *, int, int, const BatchPhase &, int, hipStream_t);
-template void launch_batch_spin<float>(const RepDesc<float> *, int, int, const BatchPhase &, int, hipStream_t);
-template void launch_batch_force<double>(const RepDesc<double> *, int, int, int, const BatchPhase &, int, hipStream_t);
-template void launch_batch_force<float>(const RepDesc<float> *, int, int, int, const BatchPhase &, int, hipStream_t);
+template void launch_batch_spin<double>(const RepDesc<double> *, int, int, const BatchPhase &, int, bool, hipStream_t);
+template void launch_batch_spin<float>(const RepDesc<float> *, int, int, const BatchPhase &, int, bool, hipStream_t);
+template void launch_batch_force<double>(const RepDesc<double> *, int, int, int, const BatchPhase &, int, bool, hipStream_t);
+template void launch_batch_force<float>(const RepDesc<float> *, int, int, int, const BatchPhase &, int, bool, hipStream_t);
 
 // Exchange coefficients at one set of positions (the optional pair
 // coefficient cache): J(r_ij) for every spin-segment entry, with the same
@@ -777,7 +819,8 @@ __global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, 
 
 // ---------------------------------------------------------------------------
 // Host launchers. The learned-potential variants (table lookups instead of
-// the analytic J and V) exist in the FP32 form only.
+// the analytic J and V) exist in the FP32 form only; variant 4 is the
+// analytic potential with the spin-orbit pair terms.
 template <typename real, int LANES, int MLP>
 static void spin_phase_lanes2(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
                               hipStream_t st) {
@@ -793,7 +836,8 @@ static void spin_phase_lanes2(const SysView<real> &S, const PotConst &P, const S
 template <typename real, int LANES>
 static void spin_phase_lanes(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
                              hipStream_t st) {
-  if (S.jc) spin_phase_lanes2<real, LANES, 3>(S, P, A, st);
+  if (P.soc_on) spin_phase_lanes2<real, LANES, 4>(S, P, A, st);
+  else if (S.jc) spin_phase_lanes2<real, LANES, 3>(S, P, A, st);
   else if (sizeof(real) == 4 && S.spl.t) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
   else if (sizeof(real) == 4 && S.tab) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, st);
   else spin_phase_lanes2<real, LANES, 0>(S, P, A, st);
@@ -824,7 +868,8 @@ static void spin_tail_lanes2(const SysView<real> &S, const PotConst &P, const Ta
 template <typename real, int LANES>
 static void spin_tail_lanes(const SysView<real> &S, const PotConst &P, const TailArgs &T,
                             hipStream_t st) {
-  if (S.jc) spin_tail_lanes2<real, LANES, 3>(S, P, T, st);
+  if (P.soc_on) spin_tail_lanes2<real, LANES, 4>(S, P, T, st);
+  else if (S.jc) spin_tail_lanes2<real, LANES, 3>(S, P, T, st);
   else if (sizeof(real) == 4 && S.spl.t) spin_tail_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, T, st);
   else if (sizeof(real) == 4 && S.tab) spin_tail_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, T, st);
   else spin_tail_lanes2<real, LANES, 0>(S, P, T, st);
@@ -860,7 +905,8 @@ static void force_lanes2(const SysView<real> &S, const PotConst &P, const ForceA
 template <typename real, int LANES>
 static void force_lanes(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
                         hipStream_t st) {
-  if (sizeof(real) == 4 && S.spl.t) force_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
+  if (P.soc_on) force_lanes2<real, LANES, 4>(S, P, A, st);
+  else if (sizeof(real) == 4 && S.spl.t) force_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
   else if (sizeof(real) == 4 && S.tab) force_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, st);
   else force_lanes2<real, LANES, 0>(S, P, A, st);
 }

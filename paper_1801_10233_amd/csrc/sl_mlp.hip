@@ -655,6 +655,11 @@ __global__ void k_fields(SysView<real> S, PotConst P, FieldArgs A) {
     f[0] += c * dx; f[1] += c * dy; f[2] += c * dz;
     hw[0] += J * sjx; hw[1] += J * sjy; hw[2] += J * sjz;
     e += 0.5 * (V - J * sij);
+    if (!MLP && P.soc_on) {
+      // Neel and DMI pair terms (appendix A)
+      soc_field<double>(P, dx, dy, dz, r2, sjx, sjy, sjz, hw[0], hw[1], hw[2]);
+      e += 0.5 * soc_force<double>(P, dx, dy, dz, r2, six, siy, siz, sjx, sjy, sjz, f[0], f[1], f[2]);
+    }
   }
   const size_t n = S.n;
   if (A.ts) {

@@ -71,7 +71,12 @@ class sl_potential(C.Structure):
                 ("ex_rc", C.c_double), ("zeeman_g", C.c_double), ("B", C.c_double * 3),
                 ("aniso_K", C.c_double), ("aniso_n", C.c_double * 3), ("lam", C.c_double),
                 ("temperature", C.c_double), ("lat_gamma", C.c_double),
-                ("lat_temperature", C.c_double)]
+                ("lat_temperature", C.c_double),
+                ("neel_alpha", C.c_double), ("neel_gamma", C.c_double),
+                ("neel_delta", C.c_double), ("neel_rc", C.c_double),
+                ("dmi_alpha", C.c_double), ("dmi_gamma", C.c_double),
+                ("dmi_delta", C.c_double), ("dmi_rc", C.c_double),
+                ("dmi_n", C.c_double * 3)]
 
 
 class sl_energy(C.Structure):
@@ -206,7 +211,7 @@ def _ptr(a):
 def make_potential(d: dict) -> sl_potential:
     p = sl_potential()
     for k, v in d.items():
-        if k in ("B", "aniso_n"):
+        if k in ("B", "aniso_n", "dmi_n"):
             setattr(p, k, (C.c_double * 3)(*v))
         else:
             setattr(p, k, v)

@@ -1,0 +1,135 @@
+"""Spin-orbit pair terms (appendix A: Neel pseudo-dipolar anisotropy and the
+Dzyaloshinskii-Moriya interaction) on the GPU against the oracle.
+
+FP64 bar as for the plain path (1e-10 over 100 steps, identical colourings
+and rebuilds), on a frozen lattice (where the energy must also stay exact),
+coupled, with both baths, for every launch shape and for batched replicas;
+the FP32 form within its own tolerance; argument errors are rejected."""
+import numpy as np
+import pytest
+
+from paper_1801_10233_amd import workloads as W
+from tests.common import make_gpu, make_oracle, parity
+
+pytestmark = pytest.mark.gpu
+
+
+def test_soc_frozen_parity_and_exact_energy():
+    w = W.soc_coupled(n=7, frozen=True)            # 686 atoms, K = 9
+    o, g = make_oracle(w), make_gpu(w)
+    e0 = g.energy()["total"]
+    assert e0 == pytest.approx(o.energy()["total"], rel=1e-12)
+    o.step(100, w.dt)
+    g.step(100, w.dt)
+    p = parity(w, o, g)
+    print("soc frozen parity", p, flush=True)
+    assert p["ok"], p
+    assert abs(g.energy()["total"] / e0 - 1) < 1e-12
+    g.step(10, 3e-2)                               # exact for any dt
+    assert abs(g.energy()["total"] / e0 - 1) < 1e-12
+
+
+@pytest.mark.parametrize("n", [6, 7])
+def test_soc_coupled_parity(n):
+    w = W.soc_coupled(n=n)
+    o, g = make_oracle(w), make_gpu(w)
+    for chunk in (40, 60):
+        o.step(chunk, w.dt)
+        g.step(chunk, w.dt)
+    p = parity(w, o, g)
+    print("soc coupled parity", n, p, flush=True)
+    assert p["ok"], p
+    assert g.stats()["rebuilds"] == o.num_rebuilds
+    assert np.array_equal(g.coloring()[0], o.coloring()[0])
+    eo, eg = o.energy(), g.energy()
+    for k in eo:
+        assert eg[k] == pytest.approx(eo[k], rel=1e-11, abs=1e-11), k
+    neel, dmi = o.soc_energy()
+    assert abs(neel) > 1e-4 and abs(dmi) > 1e-5      # the terms are really on
+
+
+def test_soc_with_both_baths_parity():
+    w = W.soc_coupled(n=6, lam=0.05)
+    w.pot = dict(w.pot, lat_gamma=200.0, lat_temperature=500.0, aniso_K=1e-4)
+    o, g = make_oracle(w), make_gpu(w)
+    o.step(100, w.dt)
+    g.step(100, w.dt)
+    p = parity(w, o, g)
+    print("soc + baths parity", p, flush=True)
+    assert p["ok"], p
+
+
+@pytest.mark.parametrize("spin_lanes,force_lanes,small", [
+    (1, 1, -1), (2, 4, 4096), (8, 8, -1)])
+def test_soc_launch_shapes(spin_lanes, force_lanes, small):
+    w = W.soc_coupled(n=6, lam=0.01)
+    o, g = make_oracle(w), make_gpu(w)
+    g.set_tuning(spin_lanes, force_lanes, small, 1)   # cache request ignored with SOC
+    o.step(50, w.dt)
+    g.step(50, w.dt)
+    p = parity(w, o, g)
+    assert p["ok"], p
+
+
+def test_soc_fields_and_temperatures():
+    w = W.soc_coupled(n=6)
+    o, g = make_oracle(w), make_gpu(w)
+    o.step(20, w.dt); g.step(20, w.dt)
+    Fo = o.forces()
+    Fg, _ = g.fields()
+    assert np.abs(Fg - Fo).max() < 1e-10 * np.abs(Fo).max()
+    TLo, TSo = o.temperatures()
+    TLg, TSg = g.temperatures()
+    assert TLg == pytest.approx(TLo, rel=1e-10)
+    assert TSg == pytest.approx(TSo, rel=1e-9)
+
+
+def test_soc_fp32_form_close():
+    from paper_1801_10233_amd import spinlat as sl
+    w = W.soc_coupled(n=6)
+    o, g = make_oracle(w), make_gpu(w, precision=sl.SL_FP32)
+    o.step(50, w.dt); g.step(50, w.dt)
+    ro, vo, so = o.get_state()
+    rg, vg, sg = g.get_state()
+    assert np.abs(sg - so).max() < 1e-4
+    assert np.abs(vg - vo).max() < 1e-4 * np.abs(vo).max()
+    eo, eg = o.energy()["total"], g.energy()["total"]
+    assert abs(eg - eo) / w.N < 1e-6
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_soc_batch_matches_oracle(mode):
+    from paper_1801_10233_amd import spinlat as sl
+    ws = W.batched_replicas(R=3, seed=41, n_lo=5, n_hi=7)
+    for k, w in enumerate(ws):
+        if k != 1:                                 # one replica without the terms
+            w.pot = dict(w.pot, **W.NEEL_BJ, **W.DMI_BJ)
+    b = sl.Batch(ws, precision=sl.SL_FP64)
+    b.set_mode(mode)
+    b.step(30, 1e-4)
+    b.step(30, 1e-4)
+    for r, w in enumerate(ws):
+        o = make_oracle(w)
+        o.step(60, 1e-4)
+        ro, vo, so = o.get_state()
+        rg, vg, sg = b.get_state(r)
+        dr = np.abs(rg - ro).max() / w.box[0]
+        ds = np.abs(sg - so).max()
+        dv = np.abs(vg - vo).max() / np.abs(vo).max()
+        print("soc replica", r, dr, ds, dv, flush=True)
+        assert dr < 1e-10 and ds < 1e-10 and dv < 1e-10
+
+
+def test_soc_argument_errors():
+    from paper_1801_10233_amd import spinlat as sl
+    w = W.soc_coupled(n=5)
+    g = make_gpu(w)
+    for bad in (dict(neel_rc=3.6), dict(dmi_rc=4.0), dict(dmi_n=(0.0, 0.0, 2.0)),
+                dict(neel_delta=0.0)):
+        with pytest.raises(sl.SpinLatError):
+            g.set_potential(dict(w.pot, **bad))
+    f = make_gpu(w, precision=sl.SL_FP32)
+    m = sl.Mlp()
+    m.set_weights(np.zeros(sl.SL_MLP_NPARAM, dtype=np.float32) + 0.01)
+    with pytest.raises(sl.SpinLatError):
+        f.set_mlp(m)
