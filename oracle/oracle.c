@@ -66,6 +66,7 @@ struct orc_sys {
 
     /* scratch */
     double *w_tmp;
+    double *rho;           /* embedded-atom densities of the current state */
     int *cls, *cls_off;
     int ncls;
 };
@@ -276,6 +277,7 @@ orc_sys *orc_create(int N, const double L[3], int frozen, double skin,
     S->F = (double *)calloc(n3, sizeof(double));
     S->rbuild = (double *)calloc(n3, sizeof(double));
     S->w_tmp = (double *)calloc(n3, sizeof(double));
+    S->rho = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
     S->m = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
     S->off = (int *)calloc((size_t)N + 1, sizeof(int));
     S->nspin = (int *)calloc((size_t)(N > 0 ? N : 1), sizeof(int));
@@ -304,7 +306,7 @@ void orc_destroy(orc_sys *S)
 {
     if (!S) return;
     free(S->mparams);
-    free(S->r); free(S->v); free(S->s); free(S->F); free(S->rbuild);
+    free(S->r); free(S->v); free(S->s); free(S->F); free(S->rbuild); free(S->rho);
     free(S->w_tmp); free(S->m); free(S->off); free(S->idx); free(S->nspin);
     free(S->colour); free(S->cls); free(S->cls_off);
     free(S);
@@ -367,6 +369,10 @@ static double list_radius(const orc_sys *S)
 {
     double rc = S->pot.ex_rc;
     if (!S->frozen && S->pot.morse_on && S->pot.morse_rc > rc) rc = S->pot.morse_rc;
+    if (!S->frozen && S->pot.eam_on) {
+        if (S->pot.eam_d > rc) rc = S->pot.eam_d;
+        if (S->pot.eam_c > rc) rc = S->pot.eam_c;
+    }
     return rc + S->skin;
 }
 
@@ -801,8 +807,56 @@ void orc_omega_all(orc_sys *S, double *w)
 
 /* Force on atom i (Eq. p_advance): F_i = sum_j [-V'(r) + J'(r) s_i.s_j] e_ij
  * with e_ij = (r_i - r_j)/r_ij, so that F_i = -dH/dr_i. */
+/* Embedded-atom terms of the Finnis-Sinclair form (the paper's mechanical
+ * model is an EAM, Sec. 2 and the mechanical-potential appendix; its tables
+ * are not available, so an analytic form of the same two-pass structure
+ * stands in): the density function f(r), the pair term phi(r), the
+ * embedding F(rho) = -A sqrt(rho), each with its derivative. */
+static double eam_f(const orc_pot *p, double r, double *df)
+{
+    if (!(r < p->eam_d)) { *df = 0.0; return 0.0; }
+    double x = r - p->eam_d;
+    *df = 2.0 * x + 3.0 * p->eam_beta * x * x / p->eam_d;
+    return x * x + p->eam_beta * x * x * x / p->eam_d;
+}
+
+static double eam_phi(const orc_pot *p, double r, double *dphi)
+{
+    if (!(r < p->eam_c)) { *dphi = 0.0; return 0.0; }
+    double x = r - p->eam_c;
+    double q = p->eam_c0 + p->eam_c1 * r + p->eam_c2 * r * r;
+    *dphi = 2.0 * x * q + x * x * (p->eam_c1 + 2.0 * p->eam_c2 * r);
+    return x * x * q;
+}
+
+static double eam_embed(const orc_pot *p, double rho, double *dF)
+{
+    if (!(rho > 0.0)) { *dF = 0.0; return 0.0; }
+    double sq = sqrt(rho);
+    *dF = -0.5 * p->eam_A / sq;
+    return -p->eam_A * sq;
+}
+
+static int eam_active(const orc_sys *S) { return S->pot.eam_on && !S->frozen; }
+
+/* First pass: rho_i over the whole list. */
+static void eam_density(orc_sys *S)
+{
+    for (int i = 0; i < S->N; ++i) {
+        double rho = 0.0;
+        for (int k = S->off[i]; k < S->off[i + 1]; ++k) {
+            double d[3], df;
+            min_image(S->L, S->r + 3 * i, S->r + 3 * S->idx[k], d);
+            rho += eam_f(&S->pot, norm3(d), &df);
+        }
+        S->rho[i] = rho;
+    }
+}
+
 static void forces(orc_sys *S)
 {
+    const int eam = eam_active(S);
+    if (eam) eam_density(S);
     for (int i = 0; i < S->N; ++i) {
         double f[3] = {0.0, 0.0, 0.0};
         for (int k = S->off[i]; k < S->off[i + 1]; ++k) {
@@ -813,6 +867,15 @@ static void forces(orc_sys *S)
             double J, dJ, V, dV;
             pair_terms(S, r, &J, &dJ, &V, &dV);
             double c = -dV + dJ * dot3(S->s + 3 * i, S->s + 3 * j);
+            if (eam) {
+                /* second pass: -[phi'(r) + (F'(rho_i) + F'(rho_j)) f'(r)] */
+                double df, dphi, dFi, dFj;
+                (void)eam_f(&S->pot, r, &df);
+                (void)eam_phi(&S->pot, r, &dphi);
+                (void)eam_embed(&S->pot, S->rho[i], &dFi);
+                (void)eam_embed(&S->pot, S->rho[j], &dFj);
+                c -= dphi + (dFi + dFj) * df;
+            }
             for (int a = 0; a < 3; ++a) f[a] += c * d[a] / r;
             if (soc_on(&S->pot) && k < S->off[i] + S->nspin[i])
                 soc_force(&S->pot, d, S->s + 3 * i, S->s + 3 * j, f);
@@ -1103,9 +1166,15 @@ void orc_energy(orc_sys *S, double e[6])
     if (!S->have_list) orc_build_now(S);
     const orc_pot *p = &S->pot;
     double kin = 0.0, pair = 0.0, ex = 0.0, zee = 0.0, an = 0.0;
+    const int eam = eam_active(S);
+    if (eam) eam_density(S);
     for (int i = 0; i < S->N; ++i) {
         const double *vi = S->v + 3 * i;
         kin += 0.5 * S->m[i] * dot3(vi, vi) * ORC_MVV2E;
+        if (eam) {
+            double dF;
+            pair += eam_embed(p, S->rho[i], &dF);
+        }
         for (int k = S->off[i]; k < S->off[i + 1]; ++k) {
             int j = S->idx[k];
             if (j <= i) continue;     /* each unordered pair once */
@@ -1115,6 +1184,10 @@ void orc_energy(orc_sys *S, double e[6])
             double J, dJ, V, dV;
             pair_terms(S, r, &J, &dJ, &V, &dV);
             if (!S->frozen) pair += V;
+            if (eam) {
+                double dphi;
+                pair += eam_phi(p, r, &dphi);
+            }
             ex -= J * dot3(S->s + 3 * i, S->s + 3 * j);
             if (soc_on(p) && k < S->off[i] + S->nspin[i]) {
                 double en, ed;

@@ -45,6 +45,12 @@ typedef struct {
      * of Bethe-Slater form and e_ij = (r_j - r_i)/r_ij */
     double dmi_alpha, dmi_gamma, dmi_delta, dmi_rc;
     double dmi_n[3];
+    /* embedded-atom mechanical potential of the Finnis-Sinclair form:
+     * E = sum_i F(rho_i) + sum_{i<j} phi(r_ij), rho_i = sum_j f(r_ij),
+     * F(rho) = -A sqrt(rho), f(r) = (r-d)^2 + beta (r-d)^3/d (r < d),
+     * phi(r) = (r-c)^2 (c0 + c1 r + c2 r^2) (r < c) */
+    int eam_on;
+    double eam_A, eam_d, eam_beta, eam_c, eam_c0, eam_c1, eam_c2;
 } orc_pot;
 
 /* Key tag of the lattice-noise Philox stream: key = seed XOR this value. */

@@ -93,6 +93,11 @@ def thermal_displacements(N: int, sigma: float, seed: int):
 EXCHANGE_BJ = dict(ex_alpha=0.1, ex_gamma=0.2, ex_delta=1.2, ex_rc=3.5)
 MORSE_BJ = dict(morse_on=1, morse_D=0.4174, morse_alpha=1.3885, morse_r0=2.845,
                 morse_rc=5.0, morse_shift=1)
+# Embedded-atom stand-in for the paper's tabulated EAM (Sec. 2): the
+# Finnis-Sinclair potential for bcc iron (Finnis and Sinclair, Phil. Mag. A
+# 50, 45 (1984)), fitted to a = 2.8665 A and a cohesive energy of 4.28 eV.
+FS_FE = dict(eam_on=1, eam_A=1.828905, eam_d=3.569745, eam_beta=1.8, eam_c=3.40,
+             eam_c0=1.2371147, eam_c1=-0.3592185, eam_c2=-0.0385607)
 # Spin-orbit pair terms (appendix A; the paper's Co parameters are not
 # available): Neel g1(r) and the DMI magnitude in the Bethe-Slater form,
 # a tenth and a twentieth of the exchange scale, DMI vector n x e_ij, n = z.
@@ -131,7 +136,8 @@ def _pot(**kw):
                 temperature=0.0, lat_gamma=0.0, lat_temperature=0.0,
                 neel_alpha=0.0, neel_gamma=0.0, neel_delta=1.0, neel_rc=0.0,
                 dmi_alpha=0.0, dmi_gamma=0.0, dmi_delta=1.0, dmi_rc=0.0,
-                dmi_n=(0.0, 0.0, 1.0))
+                dmi_n=(0.0, 0.0, 1.0), eam_on=0, eam_A=0.0, eam_d=0.0,
+                eam_beta=0.0, eam_c=0.0, eam_c0=0.0, eam_c1=0.0, eam_c2=0.0)
     base.update(kw)
     return base
 
@@ -220,6 +226,20 @@ def soc_coupled(n: int = 8, T: float = 300.0, frozen: bool = False,
     return Workload("soc_frozen" if frozen else "soc_coupled", n, r, v,
                     random_unit_spins(N, spin_seed), m, box, pot, frozen, 1e-4,
                     1000, 0.0 if frozen else 0.3, key)
+
+
+def eam_coupled(n: int = 20, T: float = 300.0, spin_seed: int = 9001,
+                vel_seed: int = 9002, key: int = 9003, lam: float = 0.0) -> Workload:
+    """Coupled run with the embedded-atom (Finnis-Sinclair iron) mechanical
+    potential in place of Morse, Bethe-Slater exchange, Maxwell velocities
+    at T and random spins."""
+    r, box = bcc_lattice(n)
+    N = r.shape[0]
+    m = np.full(N, FE_MASS)
+    pot = _pot(**EXCHANGE_BJ, **FS_FE, lam=lam, temperature=T if lam > 0 else 0.0)
+    return Workload("eam_coupled", n, r, maxwell_velocities(m, T, vel_seed),
+                    random_unit_spins(N, spin_seed), m, box, pot, False, 1e-4,
+                    1000, 0.3, key)
 
 
 def batched_replicas(R: int = 64, seed: int = 4004, n_lo: int = 8,
