@@ -48,7 +48,7 @@ STEP_BYTES = {sl.SL_FP64: 4 * SPIN_BYTES[sl.SL_FP64] + FORCE_BYTES[sl.SL_FP64],
               sl.SL_FP32: 4 * SPIN_BYTES[sl.SL_FP32] + FORCE_BYTES[sl.SL_FP32]}
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_10233_amd", "csrc", f)
-                  for f in ("sl_dyn.hip", "sl_device.h")]
+                  for f in ("sl_step.h", "sl_dyn.hip", "sl_force.hip", "sl_device.h")]
 
 
 def kernel_sources_sha256():

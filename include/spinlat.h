@@ -101,7 +101,16 @@ typedef struct {
  *        D_ij = d(r) (dmi_n x e_ij), e_ij = (r_j - r_i)/r_ij, |dmi_n| = 1.
  *    Available with the analytic exchange only (not with a learned pair
  *    potential); their field on s_i depends on s_j only, so the colour
- *    sweeps keep their exact properties. */
+ *    sweeps keep their exact properties.
+ *  - Embedded-atom mechanical term (Sec. 2; the paper's tabulated EAM is
+ *    replaced by the analytic Finnis-Sinclair form), added to the Morse
+ *    term when both are on: sum_i F(rho_i) + sum_{i<j} phi(r_ij) with
+ *    rho_i = sum_j f(r_ij), F(rho) = -eam_A sqrt(rho),
+ *    f(r) = (r - eam_d)^2 + eam_beta (r - eam_d)^3 / eam_d for r < eam_d,
+ *    phi(r) = (r - eam_c)^2 (eam_c0 + eam_c1 r + eam_c2 r^2) for r < eam_c.
+ *    Forces take two passes (densities, then the gather with
+ *    F'(rho_i) + F'(rho_j)); the list radius covers eam_d and eam_c. Its
+ *    energy is reported in `pair`. Not with a learned pair potential. */
 typedef struct {
     int morse_on;
     double morse_D, morse_alpha, morse_r0, morse_rc;
@@ -118,6 +127,8 @@ typedef struct {
     double neel_alpha, neel_gamma, neel_delta, neel_rc;
     double dmi_alpha, dmi_gamma, dmi_delta, dmi_rc;
     double dmi_n[3];
+    int eam_on;
+    double eam_A, eam_d, eam_beta, eam_c, eam_c0, eam_c1, eam_c2;
 } sl_potential;
 
 /* Energies in eV: kinetic sum_i m v^2/2, pair, exchange (the magnetic pair

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspinlat.so")
-SOURCES = ["sl_api.hip", "sl_dyn.hip", "sl_nbr.hip", "sl_mlp.hip", "sl_mlp_api.hip"]
+SOURCES = ["sl_api.hip", "sl_dyn.hip", "sl_force.hip", "sl_batch.hip", "sl_nbr.hip", "sl_mlp.hip",
+           "sl_mlp_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -25,16 +26,42 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    """Compile each source to an object in parallel, then link the library."""
+    import shutil
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", CSRC, "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libspinlat.so")
-    os.replace(tmp, LIB)
+    tmpdir = tempfile.mkdtemp(prefix="spinlat_build_")
+    try:
+        cflags = [f for f in FLAGS if f != "-shared"]
+        objs = [os.path.join(tmpdir, os.path.basename(s) + ".o") for s in srcs]
+
+        def compile_one(pair):
+            src, obj = pair
+            cmd = [HIPCC, *cflags, "-I", CSRC, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            return subprocess.run(cmd, capture_output=True, text=True)
+
+        jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            results = list(ex.map(compile_one, zip(srcs, objs)))
+        for src, r in zip(srcs, results):
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError(f"hipcc failed on {os.path.basename(src)}")
+        tmp = LIB + ".tmp"
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed linking libspinlat.so")
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
 
 

@@ -114,6 +114,7 @@ struct sl_system {
   // exchange-coefficient cache per position buffer (analytic potential)
   int jcache = -1;  // set from the precision at creation (on for FP32)
   void *jc[2] = {nullptr, nullptr};
+  double *eam = nullptr;  // embedded-atom F'(rho), F(rho) per atom [2][ld]
   bool jc_ok[2] = {false, false};
 
   bool prof = false;
@@ -167,6 +168,7 @@ void dfree(void *p) {
 double list_radius(const sl_system *S) {
   double rc = S->pot.ex_rc;
   if (!S->prm.frozen && S->pot.morse_on && S->pot.morse_rc > rc) rc = S->pot.morse_rc;
+  if (!S->prm.frozen && S->pot.eam_on) rc = std::max(rc, std::max(S->pot.eam_d, S->pot.eam_c));
   return rc + (S->prm.frozen ? 0.0 : S->skin);
 }
 
@@ -235,6 +237,16 @@ void make_potconst(sl_system *S) {
     c.nRc2 = p.neel_rc * p.neel_rc;
     c.nA8InvD2 = 8.0 * p.neel_alpha / (p.neel_delta * p.neel_delta);
   }
+  c.eam_on = (p.eam_on && !S->prm.frozen) ? 1 : 0;
+  c.fA = p.eam_A;
+  c.fd = p.eam_d;
+  c.fbeta = p.eam_beta;
+  c.fc = p.eam_c;
+  c.fc0 = p.eam_c0;
+  c.fc1 = p.eam_c1;
+  c.fc2 = p.eam_c2;
+  c.fd2 = p.eam_d * p.eam_d;
+  c.fcc2 = p.eam_c * p.eam_c;
   if (dmi) {
     c.dA4 = 4.0 * p.dmi_alpha;
     c.dG = p.dmi_gamma;
@@ -270,6 +282,7 @@ SysView<real> view(sl_system *S, int posbuf) {
   v.spl = SplineView{};
   const bool jc_use = (!S->mlp || S->mlp_mode == SL_MLP_SPLINE) && S->jcache > 0 && !S->pc.soc_on;
   v.jc = (jc_use && S->jc_ok[posbuf]) ? (const real *)S->jc[posbuf] : nullptr;
+  v.eam = S->pc.eam_on ? S->eam : nullptr;
   if (S->mlp && S->mlp_mode == SL_MLP_SPLINE) v.spl = S->mlp->spline_view();
   else if (S->mlp) v.tab = S->tab[posbuf];
   return v;
@@ -860,7 +873,9 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   }
   {
     ProfScope ps(S, 1, (double)S->n);
-    launch_force<real>(view<real>(S, posbuf), S->pc, F, S->force_lanes, S->st);
+    const SysView<real> v = view<real>(S, posbuf);
+    launch_eam_density<real>(v, S->pc, S->st);
+    launch_force<real>(v, S->pc, F, S->force_lanes, S->st);
   }
   if (mode & (kModeFinal | kModeNext)) HIPCHK(S, hipEventRecord(S->ev[slot], S->st));
   return SL_OK;
@@ -1110,7 +1125,7 @@ int sl_destroy(sl_system *S) {
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
                   (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo,
                   (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
-                  (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1]})
+                  (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1], (void *)S->eam})
     dfree(p);
   if (S->ring) (void)hipHostFree(S->ring);
   if (S->own_stream && S->st) (void)hipStreamDestroy(S->st);
@@ -1145,6 +1160,16 @@ int sl_set_potential(sl_system *S, const sl_potential *pot) {
   }
   if ((neel || dmi) && S->mlp)
     return fail(S, SL_E_ARG, "Neel/DMI terms need the analytic exchange (a learned pair potential is set)");
+  if (pot->eam_on) {
+    const double ev[] = {pot->eam_A, pot->eam_d, pot->eam_beta, pot->eam_c, pot->eam_c0,
+                         pot->eam_c1, pot->eam_c2};
+    for (double v : ev)
+      if (!std::isfinite(v)) return fail(S, SL_E_ARG, "non-finite embedded-atom parameter");
+    if (pot->eam_A < 0.0 || pot->eam_d <= 0.0 || pot->eam_c <= 0.0)
+      return fail(S, SL_E_ARG, "embedded-atom terms need A >= 0, d > 0 and c > 0");
+    if (S->mlp) return fail(S, SL_E_ARG, "embedded-atom terms cannot be combined with a learned pair potential");
+  }
+  if (pot->eam_on && !S->eam) HIPCHK(S, dalloc(&S->eam, 2 * (size_t)S->ld));
   S->pot = *pot;
   S->have_pot = true;
   make_potconst(S);
@@ -1512,6 +1537,7 @@ int sl_set_mlp(sl_system *S, sl_mlp *m) {
     if (S->prec != SL_FP32) return fail(S, SL_E_ARG, "the learned potential runs in the FP32 form");
     if (!m->have_weights) return fail(S, SL_E_STATE, "the MLP has no weights");
     if (S->pc.soc_on) return fail(S, SL_E_ARG, "the Neel/DMI terms need the analytic exchange");
+    if (S->pc.eam_on) return fail(S, SL_E_ARG, "embedded-atom terms cannot be combined with a learned pair potential");
     (void)hipStreamSynchronize(m->st);
     for (int b = 0; b < 2; ++b)
       if (!S->tab[b]) HIPCHK(S, dalloc(&S->tab[b], (size_t)S->ld * S->max_nbr));
@@ -1609,6 +1635,7 @@ int fields_now(sl_system *S, double *F, double *hw, int where) {
   std::memset(&A, 0, sizeof(A));
   A.F = dF;
   A.hw = dW;
+  launch_eam_density<real>(view<real>(S, S->pos), S->pc, S->st);
   launch_fields<real>(view<real>(S, S->pos), S->pc, A, S->st);
   Atoms &At = S->a[S->cur];
   for (int q = 0; q < 2; ++q) {
@@ -1642,6 +1669,7 @@ int temps_now(sl_system *S, double *TL, double *TS) {
     FieldArgs A;
     std::memset(&A, 0, sizeof(A));
     A.ts = ts;
+    launch_eam_density<real>(view<real>(S, S->pos), S->pc, S->st);
     launch_fields<real>(view<real>(S, S->pos), S->pc, A, S->st);
     launch_sum_d(ts, n, ts + 2 * (size_t)n, S->st);
     launch_sum_d(ts + n, n, ts + 2 * (size_t)n + 1, S->st);
@@ -2099,6 +2127,15 @@ bool batch_soc(const sl_batch *B) {
   return false;
 }
 
+// Force variant of the batch kernels: 4 with spin-orbit terms, 8 with
+// embedded-atom terms (in any replica).
+int batch_variant(const sl_batch *B) {
+  int v = batch_soc(B) ? 4 : 0;
+  for (const sl_system *S : B->sys)
+    if (S->pc.eam_on) v |= 8;
+  return v;
+}
+
 // Descriptor of replica r for the batched kernels (current buffers, class
 // offsets, step, predictor state of the last two boundaries).
 template <typename real>
@@ -2152,7 +2189,7 @@ int batch_launch(sl_batch *B) {
     B->exec = nullptr;
     B->graph = nullptr;
     BCHK(B, hipStreamBeginCapture(B->st, hipStreamCaptureModeThreadLocal));
-    launch_batch_run<real>((RepDesc<real> *)B->d_desc, B->R, B->lanes, batch_soc(B), B->st);
+    launch_batch_run<real>((RepDesc<real> *)B->d_desc, B->R, B->lanes, batch_variant(B), B->st);
     BCHK(B, hipStreamEndCapture(B->st, &B->graph));
     BCHK(B, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     B->graph_lanes = B->lanes;
@@ -2289,7 +2326,7 @@ int batch_step_phased(sl_batch *B, int64_t n, double dt) {
   BatchPhase bp{};
   bp.kk = 0;
   bp.after = 0;
-  launch_batch_force<real>(D, R, max_n, kModeNext, bp, B->lanes, batch_soc(B), B->st);
+  launch_batch_force<real>(D, R, max_n, kModeNext, bp, B->lanes, batch_variant(B), B->st);
   BCHK(B, hipEventRecord(B->ev[0], B->st));
   for (int64_t kk = 0; kk < n; ++kk) {
     if (kk > 0) {
@@ -2350,7 +2387,7 @@ int batch_step_phased(sl_batch *B, int64_t n, double dt) {
       S->step = b;
     }
     bp.after = 1;
-    launch_batch_force<real>(D, R, max_n, mode, bp, B->lanes, batch_soc(B), B->st);
+    launch_batch_force<real>(D, R, max_n, mode, bp, B->lanes, batch_variant(B), B->st);
     bp.after = 0;
     BCHK(B, hipEventRecord(B->ev[(kk + 1) & 3], B->st));
     B->launches += 2 * (2 * Kmax - 1) + 1;

@@ -58,6 +58,11 @@ struct PotConst {
   double nA4, nG, nInvD2, nRc2, nA8InvD2;
   double dA4, dG, dInvD2, dRc2, dA8InvD2;
   double dn[3];
+  // embedded-atom terms (Finnis-Sinclair form): F(rho) = -A sqrt(rho),
+  // f(r) = (r-d)^2 + beta (r-d)^3/d for r < d, phi(r) = (r-c)^2 (c0 + c1 r +
+  // c2 r^2) for r < c
+  int eam_on;
+  double fA, fd, fbeta, fc, fc0, fc1, fc2, fd2, fcc2;  // fd2 = d^2, fcc2 = c^2
 };
 
 // Key tag of the lattice-noise Philox stream (key = seed ^ tag).
@@ -120,6 +125,8 @@ struct SysView {
   SplineView spl;              // learned potential as a spline (spl.t null: unused)
   const real *jc;              // exchange coefficients J(r_ij) per spin-segment
                                // entry at these positions, or null
+  double *eam;                 // embedded-atom terms of these positions:
+                               // F'(rho_i) at [i], F(rho_i) at [ld + i]
 };
 
 struct SpinPhaseArgs {

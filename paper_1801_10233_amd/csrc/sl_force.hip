@@ -1,0 +1,145 @@
+// sl_force.hip -- force kernels of the spin-lattice step on gfx950:
+//   * k_eam_density: first pass of the embedded-atom terms;
+//   * k_force:       pair + magneto-mechanical force (Eq. p_advance), fused
+//                    with the velocity-Verlet half kicks and the drift into
+//                    the other position buffer, energies on sampled steps
+//                    and the rebuild predictor.
+#include "sl_step.h"
+
+namespace sl {
+
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_eam_density(SysView<real> S, PotConst P) {
+  const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i < S.n) eam_density_atom<real>(S, P, i);
+}
+
+template <typename real>
+void launch_eam_density(const SysView<real> &S, const PotConst &P, hipStream_t st) {
+  if (S.n > 0 && P.eam_on && S.eam)
+    hipLaunchKernelGGL((k_eam_density<real>), dim3((S.n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       st, S, P);
+}
+template void launch_eam_density<double>(const SysView<double> &, const PotConst &, hipStream_t);
+template void launch_eam_density<float>(const SysView<float> &, const PotConst &, hipStream_t);
+
+
+template <typename real, int MODE, int LANES, int MLP>
+__global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
+  __shared__ double red[kBlock / 64][8];
+  __shared__ double redm[kBlock / 64][3];
+  __shared__ int last;
+  // Tiles are taken from the end of the atom order first: the last colour
+  // classes may hold a few atoms scattered over the whole box (repairs),
+  // whose gathers miss the caches; starting them first hides their latency
+  // behind the bulk instead of leaving them as the tail of the launch.
+  const int tile = gridDim.x - 1 - xcd_tile(blockIdx.x, gridDim.x);
+  const int t = tile * kBlock + threadIdx.x;
+  const int l = t & (LANES - 1);
+  const int i = t / LANES;
+  double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double dm = 0.0, vm = 0.0, wm = kInf;
+  force_atom<real, MODE, LANES, MLP>(S, P, A, i, i < S.n, l, e, dm, vm, wm);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (MODE & kModeEnergy) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double x = wave_sum(e[c]);
+      if (lane == 0) red[wv][c] = x;
+    }
+  }
+  if (MODE & (kModeFinal | kModeNext)) {
+    const double a = wave_max(dm), b = wave_max(vm), c = wave_min(wm);
+    if (lane == 0) { redm[wv][0] = a; redm[wv][1] = b; redm[wv][2] = c; }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (MODE & kModeEnergy) {
+      for (int c = 0; c < 8; ++c) {
+        double x = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) x += red[w][c];
+        A.partial[(size_t)tile * 8 + c] = x;
+      }
+    }
+    last = 0;
+    if (MODE & (kModeFinal | kModeNext)) {
+      double a = 0.0, b = 0.0, c = kInf;
+      for (int w = 0; w < kBlock / 64; ++w) {
+        a = fmax(a, redm[w][0]);
+        b = fmax(b, redm[w][1]);
+        c = fmin(c, redm[w][2]);
+      }
+      // non-negative doubles order like their bit patterns
+      atomicMax(&A.dslot[0], (unsigned long long)__double_as_longlong(a));
+      atomicMax(&A.dslot[1], (unsigned long long)__double_as_longlong(b));
+      atomicMin(&A.dslot[2], (unsigned long long)__double_as_longlong(c));
+      __threadfence();
+      const unsigned prev = atomicAdd(A.done, 1u);
+      last = (prev == gridDim.x - 1);
+    }
+  }
+  __syncthreads();
+  if ((MODE & (kModeFinal | kModeNext)) && last && threadIdx.x == 0) {
+    __threadfence();
+    const unsigned long long a = atomicExch(&A.dslot[0], 0ull);
+    const unsigned long long b = atomicExch(&A.dslot[1], 0ull);
+    const unsigned long long c = atomicExch(&A.dslot[2], (unsigned long long)__double_as_longlong(kInf));
+    atomicExch(A.done, 0u);
+    const int err = atomicOr(A.err, 0);
+    A.host_out[0] = __longlong_as_double((long long)a);
+    A.host_out[1] = __longlong_as_double((long long)b);
+    A.host_out[2] = (double)err;
+    A.host_out[4] = __longlong_as_double((long long)c);
+    A.host_out[3] = 1.0;  // written marker
+  }
+}
+
+
+template <typename real, int LANES, int MLP>
+static void force_lanes2(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
+                         hipStream_t st) {
+  const long threads = (long)S.n * LANES;
+  const int nb = (int)((threads + kBlock - 1) / kBlock);
+  switch (A.mode) {
+#define SL_FORCE_CASE(m) \
+  case m: hipLaunchKernelGGL((k_force<real, m, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A); break;
+    SL_FORCE_CASE(1) SL_FORCE_CASE(2) SL_FORCE_CASE(3) SL_FORCE_CASE(4)
+    SL_FORCE_CASE(5) SL_FORCE_CASE(6) SL_FORCE_CASE(7)
+#undef SL_FORCE_CASE
+    default: break;
+  }
+}
+
+template <typename real, int LANES>
+static void force_lanes(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
+                        hipStream_t st) {
+  if (P.soc_on && P.eam_on) force_lanes2<real, LANES, 12>(S, P, A, st);
+  else if (P.eam_on) force_lanes2<real, LANES, 8>(S, P, A, st);
+  else if (P.soc_on) force_lanes2<real, LANES, 4>(S, P, A, st);
+  else if (sizeof(real) == 4 && S.spl.t) force_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
+  else if (sizeof(real) == 4 && S.tab) force_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, st);
+  else force_lanes2<real, LANES, 0>(S, P, A, st);
+}
+
+// Blocks needed by a force launch (rows of the partial-sum buffer).
+int force_blocks(int n, int lanes) { return (int)(((long)n * lanes + kBlock - 1) / kBlock); }
+
+template <typename real>
+void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
+                  hipStream_t st) {
+  if (S.n <= 0) return;
+  switch (lanes) {
+    case 1: force_lanes<real, 1>(S, P, A, st); break;
+    case 2: force_lanes<real, 2>(S, P, A, st); break;
+    case 8: force_lanes<real, 8>(S, P, A, st); break;
+    default: force_lanes<real, 4>(S, P, A, st); break;
+  }
+}
+
+
+template void launch_force<double>(const SysView<double> &, const PotConst &, const ForceArgs &,
+                                   int, hipStream_t);
+template void launch_force<float>(const SysView<float> &, const PotConst &, const ForceArgs &, int,
+                                  hipStream_t);
+
+}  // namespace sl

@@ -18,7 +18,11 @@ void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
                   hipStream_t st);
 int force_blocks(int n, int lanes);
 template <typename real>
-void launch_batch_run(RepDesc<real> *D, int R, int lanes, bool soc, hipStream_t st);
+void launch_batch_run(RepDesc<real> *D, int R, int lanes, int variant, hipStream_t st);
+// Embedded-atom first pass (F'(rho), F(rho) of every atom) at the positions
+// of a view, before the force launch that reads them.
+template <typename real>
+void launch_eam_density(const SysView<real> &S, const PotConst &P, hipStream_t st);
 // Exchange-coefficient cache: J(r_ij) per spin-segment entry (ELL layout).
 template <typename real>
 void launch_jcache(const SysView<real> &S, const PotConst &P, real *out, double rs2,
@@ -26,14 +30,16 @@ void launch_jcache(const SysView<real> &S, const PotConst &P, real *out, double 
 // Phase-batched mode: one colour phase of every replica (max_class = the
 // largest class of any replica) and one force pass of every replica (max_n =
 // the largest replica; mode kModeNext at the call start, kModeFinal with or
-// without kModeNext after a step). soc selects the variants with the
-// spin-orbit pair terms (needed when any replica has them).
+// without kModeNext after a step). soc selects the spin variant with the
+// spin-orbit pair terms (needed when any replica has them); variant is the
+// force variant (4: spin-orbit terms, 8: embedded-atom terms, 12: both), the
+// embedded-atom densities being computed first.
 template <typename real>
 void launch_batch_spin(const RepDesc<real> *D, int R, int max_class, const BatchPhase &bp,
                        int lanes, bool soc, hipStream_t st);
 template <typename real>
 void launch_batch_force(const RepDesc<real> *D, int R, int max_n, int mode, const BatchPhase &bp,
-                        int lanes, bool soc, hipStream_t st);
+                        int lanes, int variant, hipStream_t st);
 void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st);
 
 // --- rebuild kernels (sl_nbr.hip) ---

@@ -655,6 +655,21 @@ __global__ void k_fields(SysView<real> S, PotConst P, FieldArgs A) {
     f[0] += c * dx; f[1] += c * dy; f[2] += c * dz;
     hw[0] += J * sjx; hw[1] += J * sjy; hw[2] += J * sjz;
     e += 0.5 * (V - J * sij);
+    if (!MLP && P.eam_on) {
+      // embedded-atom terms (densities from the first pass)
+      if (r2 < P.fd2) {
+        const double x = r - P.fd;
+        const double df = 2.0 * x + 3.0 * P.fbeta * x * x / P.fd;
+        const double cf = -(S.eam[i] + S.eam[j]) * df / r;
+        f[0] += cf * dx; f[1] += cf * dy; f[2] += cf * dz;
+      }
+      if (r2 < P.fcc2) {
+        const double x = r - P.fc, q = P.fc0 + P.fc1 * r + P.fc2 * r * r;
+        const double dphi = 2.0 * x * q + x * x * (P.fc1 + 2.0 * P.fc2 * r);
+        f[0] -= dphi * dx / r; f[1] -= dphi * dy / r; f[2] -= dphi * dz / r;
+        e += 0.5 * x * x * q;
+      }
+    }
     if (!MLP && P.soc_on) {
       // Neel and DMI pair terms (appendix A)
       soc_field<double>(P, dx, dy, dz, r2, sjx, sjy, sjz, hw[0], hw[1], hw[2]);
@@ -662,6 +677,7 @@ __global__ void k_fields(SysView<real> S, PotConst P, FieldArgs A) {
     }
   }
   const size_t n = S.n;
+  if (!MLP && P.eam_on) e += S.eam[(size_t)S.ld + i];
   if (A.ts) {
     // conservative field hbar omega_i: exchange, Zeeman and anisotropy
     const double sn = P.an[0] * six + P.an[1] * siy + P.an[2] * siz;

@@ -76,7 +76,10 @@ class sl_potential(C.Structure):
                 ("neel_delta", C.c_double), ("neel_rc", C.c_double),
                 ("dmi_alpha", C.c_double), ("dmi_gamma", C.c_double),
                 ("dmi_delta", C.c_double), ("dmi_rc", C.c_double),
-                ("dmi_n", C.c_double * 3)]
+                ("dmi_n", C.c_double * 3), ("eam_on", C.c_int),
+                ("eam_A", C.c_double), ("eam_d", C.c_double), ("eam_beta", C.c_double),
+                ("eam_c", C.c_double), ("eam_c0", C.c_double), ("eam_c1", C.c_double),
+                ("eam_c2", C.c_double)]
 
 
 class sl_energy(C.Structure):
