@@ -215,6 +215,26 @@ int sl_set_step(sl_system *sys, int64_t step);
 /* Advance n >= 0 steps of length dt (dt < 0 runs backwards). */
 int sl_step(sl_system *sys, int64_t n, double dt);
 
+/* Spin update order of the spin half-steps.
+ *  - SL_ORDER_COLOUR (default): colour classes of the spin graph, every
+ *    class updated in parallel (the GPU form of the sectors of Sec. 5.1).
+ *  - SL_ORDER_SECTORS: the paper's own order (Sec. 5.1, Eq.
+ *    spin_ST_sectoring). The box is split into grid[0] x grid[1] x grid[2]
+ *    subdomains (the processors of the paper), each bisected once per
+ *    dimension into 8 sectors, from the wrapped positions at the start of
+ *    every step. Class k is sector k of every subdomain: subdomains run in
+ *    parallel, and the atoms of one subdomain's sector are updated one after
+ *    another in id order (reversed on backward sweeps). A sector must be at
+ *    least the spin radius (ex_rc + skin) wide, else SL_E_ARG. Slow on a GPU
+ *    by nature (the sequential chains are a sector's atom count long); meant
+ *    for ordering studies.
+ *  - SL_ORDER_SERIAL: the serial order of Eq. spin_ST_decomposition (every
+ *    spin in id order, one thread); small systems only.
+ * The rebuild rule's watched-pair term applies to the colour ordering only.
+ * grid is read for SL_ORDER_SECTORS only. Batches always use colours. */
+enum { SL_ORDER_COLOUR = 0, SL_ORDER_SECTORS = 1, SL_ORDER_SERIAL = 2 };
+int sl_set_ordering(sl_system *sys, int ordering, const int grid[3]);
+
 /* Energy of the current state (computed now). Synchronises. */
 int sl_get_energy(sl_system *sys, sl_energy *out);
 

@@ -113,6 +113,15 @@ struct sl_system {
   bool tab_ok[2] = {false, false};
   // exchange-coefficient cache per position buffer (analytic potential)
   int jcache = -1;  // set from the precision at creation (on for FP32)
+  // spin ordering: colour classes, or the paper's sectors / serial order
+  int ordering = SL_ORDER_COLOUR;
+  int sgrid[3] = {1, 1, 1};
+  unsigned long long *skeys[2] = {nullptr, nullptr};
+  int *svals[2] = {nullptr, nullptr};
+  int *scount = nullptr, *soff = nullptr;
+  int s_nbins_cap = 0;
+  void *cub_tmp = nullptr;
+  size_t cub_bytes = 0;
   void *jc[2] = {nullptr, nullptr};
   double *eam = nullptr;  // embedded-atom F'(rho), F(rho) per atom [2][ld]
   bool jc_ok[2] = {false, false};
@@ -771,6 +780,82 @@ double noise_amp(const sl_system *S, double h) {
   return std::sqrt(2.0 * DS / std::fabs(h));
 }
 
+// Sectored / serial ordering (Sec. 5.1, Eq. spin_ST_sectoring): classes and
+// subdomains of the atoms at the positions of buffer posbuf, sorted by
+// (class, subdomain, id).
+int sect_classes(const sl_system *S) { return S->ordering == SL_ORDER_SECTORS ? 8 : 1; }
+int sect_nproc(const sl_system *S) {
+  return S->ordering == SL_ORDER_SECTORS ? S->sgrid[0] * S->sgrid[1] * S->sgrid[2] : 1;
+}
+
+int sect_prepare(sl_system *S, int posbuf) {
+  const int n = S->n, np = sect_nproc(S), nb = sect_classes(S) * np;
+  if (!S->skeys[0]) {
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK(S, dalloc(&S->skeys[b], (size_t)n));
+      HIPCHK(S, dalloc(&S->svals[b], (size_t)n));
+    }
+  }
+  if (nb + 1 > S->s_nbins_cap) {
+    dfree(S->scount);
+    dfree(S->soff);
+    S->scount = S->soff = nullptr;
+    S->s_nbins_cap = 0;
+    HIPCHK(S, dalloc(&S->scount, (size_t)nb + 1));
+    HIPCHK(S, dalloc(&S->soff, (size_t)nb + 1));
+    S->s_nbins_cap = nb + 1;
+  }
+  Atoms &A = S->a[S->cur];
+  SectKeyArgs K;
+  std::memset(&K, 0, sizeof(K));
+  K.n = n;
+  K.rx = A.rx[posbuf];
+  K.ry = A.ry[posbuf];
+  K.rz = A.rz[posbuf];
+  for (int d = 0; d < 3; ++d) {
+    K.L[d] = S->L[d];
+    K.g[d] = S->sgrid[d];
+  }
+  K.nproc = np;
+  K.serial = S->ordering == SL_ORDER_SERIAL ? 1 : 0;
+  K.id = A.id;
+  K.keys = S->skeys[0];
+  K.vals = S->svals[0];
+  K.count = S->scount;
+  launch_zero_i(nb + 1, S->scount, S->st);
+  launch_sect_keys(K, S->st);
+  if (sect_sort(K, nb, S->skeys[1], S->svals[1], S->soff, &S->cub_tmp, &S->cub_bytes, S->st))
+    return fail(S, SL_E_HIP, "sector sort failed");
+  return SL_OK;
+}
+
+// One spin half-step in the sectored / serial order: classes forward with
+// sub-update sub_fwd, then backward with sub_fwd + 1.
+template <typename real>
+void sect_half(sl_system *S, int posbuf, int64_t step, int sub_fwd, double h) {
+  (void)ensure_jcache<real>(S, posbuf);
+  const int nc = sect_classes(S);
+  SectPhaseArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.nproc = sect_nproc(S);
+  A.off = S->soff;
+  A.order = S->svals[1];
+  A.h = h;
+  A.amp = noise_amp(S, h);
+  A.rs2 = S->pot.ex_rc * S->pot.ex_rc;
+  A.step = step;
+  A.seed = S->prm.seed;
+  A.replica = S->prm.replica;
+  const SysView<real> v = view<real>(S, posbuf);
+  for (int q = 0; q < 2 * nc; ++q) {
+    A.backward = q >= nc ? 1 : 0;
+    A.cls = q < nc ? q : 2 * nc - 1 - q;
+    A.sub = sub_fwd + A.backward;
+    ProfScope ps(S, 0, (double)S->n / nc);
+    launch_sect_phase<real>(v, S->pc, A, S->st);
+  }
+}
+
 template <typename real>
 void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) {
   (void)ensure_table(S, posbuf);
@@ -921,7 +1006,8 @@ int wait_predictor(sl_system *S, int64_t boundary, bool *due) {
   const double adt = std::fabs(S->meta[slot].dt);
   const double D = (rb ? 0.0 : o[0]) + 2.0 * adt * o[1];
   const double W = (rb ? colour_radius(S) : std::sqrt(o[4])) - 4.0 * adt * o[1];
-  *due = D >= S->skin / 2.0 - 0.01 || W < S->pot.ex_rc + 0.01;
+  *due = D >= S->skin / 2.0 - 0.01 ||
+         (S->ordering == SL_ORDER_COLOUR && W < S->pot.ex_rc + 0.01);
   return SL_OK;
 }
 
@@ -938,12 +1024,20 @@ int step_frozen(sl_system *S, int64_t n, double dt) {
       chunk = std::min(chunk, to_sample);
     }
     chunk = std::min<int64_t>(chunk, 64);
-    std::vector<Upd> u;
-    for (int64_t q = 0; q < chunk; ++q) {
-      half_step_updates(S, S->step + q, 0, u);
-      half_step_updates(S, S->step + q, 2, u);
+    if (S->ordering != SL_ORDER_COLOUR) {
+      CHK(sect_prepare(S, S->pos));
+      for (int64_t q = 0; q < chunk; ++q) {
+        sect_half<real>(S, S->pos, S->step + q, 0, h);
+        sect_half<real>(S, S->pos, S->step + q, 2, h);
+      }
+    } else {
+      std::vector<Upd> u;
+      for (int64_t q = 0; q < chunk; ++q) {
+        half_step_updates(S, S->step + q, 0, u);
+        half_step_updates(S, S->step + q, 2, u);
+      }
+      run_updates<real>(S, S->pos, u, h);
     }
-    run_updates<real>(S, S->pos, u, h);
     S->step += chunk;
     k += chunk;
     if (te > 0 && S->step % te == 0) {
@@ -982,12 +1076,19 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
       }
     }
     S->prof_now = S->prof && (k % S->prof_every == 0);
-    std::vector<Upd> u;
-    half_step_updates(S, k, 0, u);
-    run_updates<real>(S, S->pos, u, h);
-    u.clear();
-    half_step_updates(S, k, 2, u);
-    run_updates<real>(S, 1 - S->pos, u, h);
+    if (S->ordering != SL_ORDER_COLOUR) {
+      // classes from the positions at the start of the step
+      CHK(sect_prepare(S, S->pos));
+      sect_half<real>(S, S->pos, k, 0, h);
+      sect_half<real>(S, 1 - S->pos, k, 2, h);
+    } else {
+      std::vector<Upd> u;
+      half_step_updates(S, k, 0, u);
+      run_updates<real>(S, S->pos, u, h);
+      u.clear();
+      half_step_updates(S, k, 2, u);
+      run_updates<real>(S, 1 - S->pos, u, h);
+    }
     const int64_t b = k + 1;
     int mode = kModeFinal;
     if (k + 1 < k0 + n) mode |= kModeNext;
@@ -1125,7 +1226,9 @@ int sl_destroy(sl_system *S) {
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
                   (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo,
                   (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
-                  (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1], (void *)S->eam})
+                  (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1], (void *)S->eam,
+                  (void *)S->skeys[0], (void *)S->skeys[1], (void *)S->svals[0],
+                  (void *)S->svals[1], (void *)S->scount, (void *)S->soff, S->cub_tmp})
     dfree(p);
   if (S->ring) (void)hipHostFree(S->ring);
   if (S->own_stream && S->st) (void)hipStreamDestroy(S->st);
@@ -1730,6 +1833,34 @@ int mfail_str(sl_mlp *m, int code, const std::string &msg) {
 }
 
 extern "C" {
+
+int sl_set_ordering(sl_system *S, int ordering, const int grid[3]) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  if (ordering != SL_ORDER_COLOUR && ordering != SL_ORDER_SECTORS && ordering != SL_ORDER_SERIAL)
+    return fail(S, SL_E_ARG, "unknown ordering");
+  int g[3] = {1, 1, 1};
+  if (ordering == SL_ORDER_SECTORS) {
+    if (!grid) return fail(S, SL_E_ARG, "the sectored ordering needs a subdomain grid");
+    long np = 1;
+    for (int d = 0; d < 3; ++d) {
+      if (grid[d] < 1) return fail(S, SL_E_ARG, "subdomain grid entries must be >= 1");
+      g[d] = grid[d];
+      np *= grid[d];
+    }
+    if (np > (1 << 20)) return fail(S, SL_E_ARG, "too many subdomains");
+    // a sector must be at least the spin radius wide, so that atoms in the
+    // same sector of different subdomains never interact
+    const double rs = spin_radius(S);
+    for (int d = 0; d < 3; ++d)
+      if (S->L[d] / (2.0 * g[d]) < rs)
+        return fail(S, SL_E_ARG, "sector width " + std::to_string(S->L[d] / (2.0 * g[d])) +
+                                     " A is below the spin radius " + std::to_string(rs));
+  }
+  CHK(sl_synchronize(S));
+  S->ordering = ordering;
+  for (int d = 0; d < 3; ++d) S->sgrid[d] = g[d];
+  return SL_OK;
+}
 
 int sl_get_temperatures(sl_system *S, double *T_lattice, double *T_spin) {
   if (!S) return fail(S, SL_E_ARG, "NULL system");

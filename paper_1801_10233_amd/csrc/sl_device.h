@@ -141,6 +141,31 @@ struct SpinPhaseArgs {
   double rs2;                 // exchange cutoff squared
 };
 
+// Sectored (or serial) ordering: keys of the per-step sort and one class of a
+// sectored sweep.
+struct SectKeyArgs {
+  int n;
+  const double *rx, *ry, *rz;
+  double L[3];
+  int g[3], nproc;
+  int serial;                 // 1: one class, one subdomain (id order)
+  const int *id;
+  unsigned long long *keys;   // out: (bin << 32) | id
+  int *vals;                  // out: internal index
+  int *count;                 // [nbins + 1], zeroed before the launch
+};
+
+struct SectPhaseArgs {
+  int cls, nproc, backward;
+  const int *off;             // [nbins + 1] bin offsets into order
+  const int *order;           // internal indices sorted by (bin, id)
+  double h, amp, rs2;
+  int64_t step;
+  int sub;
+  uint64_t seed;
+  uint32_t replica;
+};
+
 // Fused run of small colour classes (one workgroup).
 constexpr int kMaxTail = 16;
 constexpr int kTailBlock = 512;   // 2 waves per SIMD: room for 256 VGPRs, no spills

@@ -42,6 +42,14 @@ void launch_batch_force(const RepDesc<real> *D, int R, int max_n, int mode, cons
                         int lanes, int variant, hipStream_t st);
 void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st);
 
+// --- sectored ordering (sl_sect.hip) ---
+void launch_sect_keys(const SectKeyArgs &A, hipStream_t st);
+int sect_sort(const SectKeyArgs &A, int nbins, unsigned long long *keys_out, int *vals_out,
+              int *off, void **tmp, size_t *tmp_bytes, hipStream_t st);
+template <typename real>
+void launch_sect_phase(const SysView<real> &S, const PotConst &P, const SectPhaseArgs &A,
+                       hipStream_t st);
+
 // --- rebuild kernels (sl_nbr.hip) ---
 struct CellGrid {
   int nc[3];

@@ -32,6 +32,7 @@ SL_MLP_PAIRWISE = 0
 SL_MLP_SPLINE = 1
 SL_BATCH_PERSISTENT = 0
 SL_BATCH_PHASED = 1
+SL_ORDER_COLOUR, SL_ORDER_SECTORS, SL_ORDER_SERIAL = 0, 1, 2
 
 PROF_SPIN, PROF_FORCE, PROF_REBUILD, PROF_TABLE = 0, 1, 2, 3  # kernel kinds of sl_get_profile
 PROF_REDUCE = PROF_TABLE
@@ -44,7 +45,7 @@ EXPORTS = [
     "sl_get_energy", "sl_get_magnetization", "sl_get_temperatures", "sl_get_thermo",
     "sl_get_stats",
     "sl_synchronize", "sl_set_tuning", "sl_get_tuning", "sl_autotune", "sl_set_profiling",
-    "sl_set_mlp_mode",
+    "sl_set_mlp_mode", "sl_set_ordering",
     "sl_get_profile", "sl_last_error",
     "sl_mlp_create", "sl_mlp_destroy", "sl_mlp_set_weights", "sl_mlp_get_weights",
     "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
@@ -163,6 +164,7 @@ def lib():
         "sl_get_tuning": ([vp, C.POINTER(sl_tuning)], C.c_int),
         "sl_autotune": ([vp, C.c_int, C.c_double, C.POINTER(sl_tuning)], C.c_int),
         "sl_set_mlp_mode": ([vp, C.c_int], C.c_int),
+        "sl_set_ordering": ([vp, C.c_int, ip], C.c_int),
         "sl_set_profiling": ([vp, C.c_int], C.c_int),
         "sl_get_profile": ([vp, C.c_int, C.POINTER(C.c_int64), dp, dp], C.c_int),
         "sl_last_error": ([vp], C.c_char_p),
@@ -388,6 +390,12 @@ class System:
         self._check(lib().sl_autotune(self.h, int(steps), float(dt), C.byref(t)))
         return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
                     small_class=t.small_class, jcache=t.jcache)
+
+    def set_ordering(self, ordering, grid=(1, 1, 1)):
+        """SL_ORDER_COLOUR, SL_ORDER_SECTORS (with the subdomain grid) or
+        SL_ORDER_SERIAL."""
+        g = (C.c_int * 3)(*[int(x) for x in grid])
+        self._check(lib().sl_set_ordering(self.h, int(ordering), g))
 
     def set_mlp_mode(self, mode):
         self._check(lib().sl_set_mlp_mode(self.h, int(mode)))

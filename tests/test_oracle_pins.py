@@ -184,6 +184,50 @@ def test_reversibility_coupled():
 
 
 # --------------------------------------------------------------------------
+# P7: the ordering of the spin updates (Sec. 5.1, E4). Colour classes, the
+# paper's sectors and the serial order of Eq. spin_ST_decomposition are all
+# products of exact single-spin rotations, so each keeps the energy of a
+# frozen lattice exactly (a concurrent Jacobi update does not) and each is
+# time reversible; coupled, their energy and |M| statistics agree while the
+# trajectories separate only slowly.
+@pytest.mark.parametrize("ordering", [O.SEQ, O.SECT])
+def test_orderings_exact_on_frozen_lattice_and_reversible(ordering):
+    w = W.spin_frozen(6)
+    o = O.Oracle(w.r, w.v, w.s, w.mass, w.box, w.pot, frozen=True, ordering=ordering,
+                 sect_grid=(1, 1, 1))
+    e0 = o.energy()["total"]
+    o.step(100, 1e-4)
+    o.step(10, 2e-2)
+    assert abs(o.energy()["total"] / e0 - 1) < 1e-12
+    o.step(10, -2e-2)
+    o.step(100, -1e-4)
+    assert np.abs(o.get_state()[2] - w.s).max() < 1e-10
+
+
+def test_orderings_statistically_equivalent_coupled():
+    w = W.coupled_nve(n=6)
+    res = {}
+    for name, ordering in (("colour", O.COLOUR), ("sect", O.SECT), ("seq", O.SEQ)):
+        o = O.Oracle(w.r, w.v, w.s, w.mass, w.box, w.pot, frozen=False, skin=w.skin,
+                     ordering=ordering, sect_grid=(2, 2, 2))
+        es, ms = [], []
+        for _ in range(20):
+            o.step(10, 2e-4)
+            es.append(o.energy()["total"])
+            ms.append(np.linalg.norm(o.magnetization()) / w.N)
+        res[name] = (np.array(es), np.array(ms), o.get_state()[2])
+    e_c, m_c, s_c = res["colour"]
+    dev_c = np.abs(e_c - e_c[0]).max()
+    for name in ("sect", "seq"):
+        e, m, s = res[name]
+        dev = np.abs(e - e[0]).max()
+        assert 0.2 < dev / dev_c < 5.0, (name, dev, dev_c)
+        assert np.abs(m - m_c).max() < 0.01
+        # different orders, different trajectories, yet close after 200 steps
+        assert 1e-12 < np.abs(s - s_c).max() < 0.05
+
+
+# --------------------------------------------------------------------------
 # P6: mean relative absolute deviations (Eq. relative_deviation) of E and |M|
 # scale as dt^2 over a fixed time (Sec. 3).
 def rel_dev(x):
