@@ -247,6 +247,44 @@ def drift_per_10ps(w, precision, steps, every=10, settle=2000, mlp=None):
     return float(slope * 10.0), float(np.std(E / w.N))
 
 
+def next_rows(w, steps, warmup, tune, base_value):
+    """Throughput of the widened step on the same 432k-atom workload: with
+    the lattice bath, with the Neel and DMI pair terms, with the
+    embedded-atom potential in place of Morse, and in the paper's sectored
+    order (16^3 subdomains, 5.4 A sectors); plus the cost of one T_L, T_S
+    evaluation."""
+    out = {}
+    cases = [
+        ("lattice_bath", dict(lat_gamma=50.0, lat_temperature=300.0), None, steps),
+        ("spin_orbit", dict(W.NEEL_BJ, **W.DMI_BJ), None, steps),
+        ("eam", dict(W.FS_FE, morse_on=0), None, steps),
+        ("sectors", {}, (16, 16, 16), max(10, steps // 20)),
+    ]
+    for name, extra, grid, nst in cases:
+        wk = W.large_langevin(n=w.n)
+        wk.pot = dict(wk.pot, **extra)
+        S = sl.system_from_workload(wk, precision=sl.SL_FP64, thermo_every=100)
+        if grid is not None:
+            S.set_ordering(sl.SL_ORDER_SECTORS, grid)
+        S.step(0, wk.dt)
+        if tune and grid is None:
+            S.autotune(20, wk.dt)
+        S.step(warmup if grid is None else 2, wk.dt)
+        el, _ = timed_run(S, nst, wk.dt)
+        v = wk.N * nst / el
+        out[name] = dict(value=round(v, 1), ms_per_step=round(el / nst * 1e3, 4), steps=nst,
+                         vs_plain_fp64=round(v / base_value, 3))
+        if name == "lattice_bath":
+            S.temperatures()
+            t0 = time.perf_counter()
+            tl, ts = S.temperatures()
+            out["temperatures"] = dict(ms_per_call=round((time.perf_counter() - t0) * 1e3, 3),
+                                       T_L=round(tl, 2), T_S=round(ts, 2))
+        S.close()
+    out["sectors"]["grid"] = [16, 16, 16]
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle as it stands on this host, single thread, on the same
     workload: setup (list, colouring) excluded, then whole steps."""
@@ -413,6 +451,8 @@ def main():
         log("forms:", json.dumps(out["forms"]))
         out["batched"] = batched_throughput(args.batch_steps, tune=not args.no_tune)
         log("batched:", json.dumps(out["batched"]))
+        out["next_rows"] = next_rows(w, min(args.steps, 300), args.warmup, not args.no_tune, value)
+        log("next rows:", json.dumps(out["next_rows"]))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
