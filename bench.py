@@ -39,6 +39,11 @@ FP64_PEAK_TFLOPS = 78.6
 #   force (fused with kicks and drift): r, s, 58 indices, v read + write,
 #   mass, reference position, next position write
 SPIN_BYTES = {sl.SL_FP64: 24 + 24 + 24 + 14 * 4, sl.SL_FP32: 12 + 12 + 24 + 14 * 4}
+# with the exchange-coefficient cache the spin phase reads 14 cached J(r_ij)
+# instead of its own position; the cache is rebuilt once per drift (own r,
+# 14 indices, 14 coefficients written)
+SPIN_BYTES_JC = {sl.SL_FP64: 24 + 24 + 14 * 4 + 14 * 8, sl.SL_FP32: 12 + 12 + 14 * 4 + 14 * 4}
+JCACHE_BYTES = {sl.SL_FP64: 24 + 14 * 4 + 14 * 8, sl.SL_FP32: 24 + 14 * 4 + 14 * 4}
 FORCE_BYTES = {sl.SL_FP64: 24 + 24 + 58 * 4 + 48 + 8 + 24 + 24,
                sl.SL_FP32: 24 + 12 + 58 * 4 + 48 + 8 + 24 + 24}
 KIND_NAME = {sl.PROF_SPIN: "k_spin_phase", sl.PROF_FORCE: "k_force"}
@@ -46,6 +51,8 @@ KIND_NAME = {sl.PROF_SPIN: "k_spin_phase", sl.PROF_FORCE: "k_force"}
 # one force pass with kicks and drift), same counting as above
 STEP_BYTES = {sl.SL_FP64: 4 * SPIN_BYTES[sl.SL_FP64] + FORCE_BYTES[sl.SL_FP64],
               sl.SL_FP32: 4 * SPIN_BYTES[sl.SL_FP32] + FORCE_BYTES[sl.SL_FP32]}
+STEP_BYTES_JC = {p: 4 * SPIN_BYTES_JC[p] + FORCE_BYTES[p] + JCACHE_BYTES[p]
+                 for p in (sl.SL_FP64, sl.SL_FP32)}
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_10233_amd", "csrc", f)
                   for f in ("sl_step.h", "sl_dyn.hip", "sl_force.hip", "sl_device.h")]
@@ -59,10 +66,10 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def counter_traffic(kernel, precision):
+def counter_traffic(kernel, precision, shape=None):
     """HBM bytes per launch of `kernel` from the committed memory-counter
-    summary, or None when there is none or the kernel sources changed since
-    the counters were taken."""
+    summary, or None when there is none, the kernel sources changed since
+    the counters were taken, or the summary is of another launch shape."""
     tag = "fp64" if precision == sl.SL_FP64 else "fp32"
     path = os.path.join(PROFILES, f"{kernel}_432k_{tag}_memory_counters.txt")
     if not os.path.exists(path):
@@ -74,6 +81,8 @@ def counter_traffic(kernel, precision):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip().split()[0] if v.strip() else ""
     if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    if shape is not None and vals.get("launch_shape") != shape:
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -379,7 +388,13 @@ def main():
     kinds = {k: v for k, v in prof.items() if k in KIND_NAME}
     dom = max(kinds, key=lambda k: kinds[k][1])
     launches, ms, work = kinds[dom]
-    per_atom = SPIN_BYTES[prec] if dom == sl.PROF_SPIN else FORCE_BYTES[prec]
+    tun = S.tuning()
+    jc_on = tun["jcache"] > 0
+    per_atom = ((SPIN_BYTES_JC if jc_on else SPIN_BYTES)[prec] if dom == sl.PROF_SPIN
+                else FORCE_BYTES[prec])
+    shape = (f"lanes={tun['spin_lanes']},jcache={int(jc_on)}" if dom == sl.PROF_SPIN
+             else f"lanes={tun['force_lanes']}")
+    step_bytes = (STEP_BYTES_JC if jc_on else STEP_BYTES)[prec]
     avg_ms = ms / launches
     bytes_per_launch = per_atom * work / launches
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
@@ -388,20 +403,20 @@ def main():
                                 atoms_per_launch=round(v[2] / max(v[0], 1), 1))
              for k, v in kinds.items()}
     log("kernels:", json.dumps(other))
-    traffic = counter_traffic(KIND_NAME[dom], prec)
+    traffic = counter_traffic(KIND_NAME[dom], prec, shape)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic, 1),
                     traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                    kernel=KIND_NAME[dom], avg_launch_us=round(avg_ms * 1e3, 3),
+                    kernel=KIND_NAME[dom], launch_shape=shape, avg_launch_us=round(avg_ms * 1e3, 3),
                     timing=f"HIP events on the library stream around every launch of every "
                            f"{PROFILE_EVERY}th timed step",
                     algorithmic_bytes_per_atom=per_atom,
                     algorithmic_bytes_per_launch=round(bytes_per_launch, 1),
                     atoms_per_launch=round(work / launches, 1), kernels=other,
-                    whole_step=dict(algorithmic_bytes_per_atom_step=STEP_BYTES[prec],
-                                    achieved_GBs=round(STEP_BYTES[prec] * value / 1e9, 1),
-                                    frac=round(STEP_BYTES[prec] * value / 1e9 / HBM_PEAK_GBS, 4)))
+                    whole_step=dict(algorithmic_bytes_per_atom_step=step_bytes,
+                                    achieved_GBs=round(step_bytes * value / 1e9, 1),
+                                    frac=round(step_bytes * value / 1e9 / HBM_PEAK_GBS, 4)))
 
     out = dict(metric="atom-steps/s, 432k-atom bcc spin-lattice, plain FP64 vs FP32/MLP form @ drift",
                value=round(value, 1), unit="atom-steps/s", n_gpus=1, steps=args.steps,
