@@ -125,6 +125,7 @@ def sync():
 
 
 PROFILE_EVERY = 10   # HIP events bracket the launches of every 10th timed step
+TUNE_STEPS = 50      # steps per autotuner window (8 launch shapes x 3 rounds)
 
 
 def timed_run(S, steps, dt, profile=False):
@@ -182,7 +183,7 @@ def mlp_form(w, steps, warmup, tune):
     S.set_mlp(m)
     S.step(0, w.dt)
     if tune:
-        S.autotune(20, w.dt)
+        S.autotune(TUNE_STEPS, w.dt)
     S.step(warmup, w.dt)
     el, prof = timed_run(S, steps, w.dt, profile=True)
     kinds = {name: dict(launches=k[0], avg_us=round(k[1] / max(k[0], 1) * 1e3, 3))
@@ -277,7 +278,7 @@ def next_rows(w, steps, warmup, tune, base_value):
             S.set_ordering(sl.SL_ORDER_SECTORS, grid)
         S.step(0, wk.dt)
         if tune and grid is None:
-            S.autotune(20, wk.dt)
+            S.autotune(TUNE_STEPS, wk.dt)
         S.step(warmup if grid is None else 2, wk.dt)
         el, _ = timed_run(S, nst, wk.dt)
         v = wk.N * nst / el
@@ -369,7 +370,7 @@ def main():
     t_setup = time.perf_counter()
     S = sl.system_from_workload(w, precision=prec, thermo_every=100)
     S.step(0, w.dt)                     # first list build and colouring
-    tuned = None if args.no_tune else S.autotune(20, w.dt)
+    tuned = None if args.no_tune else S.autotune(TUNE_STEPS, w.dt)
     S.step(args.warmup, w.dt)
     S.synchronize()
     log(f"setup + warmup {time.perf_counter() - t_setup:.2f} s; stats {S.stats()}")
@@ -438,7 +439,7 @@ def main():
         S32 = sl.system_from_workload(w, precision=sl.SL_FP32)
         S32.step(0, w.dt)
         if not args.no_tune:
-            S32.autotune(20, w.dt)
+            S32.autotune(TUNE_STEPS, w.dt)
         S32.step(args.warmup, w.dt)
         el32, _ = timed_run(S32, args.steps, w.dt)
         S32.close()

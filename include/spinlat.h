@@ -281,12 +281,14 @@ typedef struct {
 int sl_set_tuning(sl_system *sys, const sl_tuning *t);
 int sl_get_tuning(sl_system *sys, sl_tuning *t);
 
-/* Autotuner. Runs `steps` steps of length dt under each candidate launch
- * shape (spin lanes 1, 2, 4; force lanes 1, 2) on a scratch copy of the
- * system (same parameters, interactions, learned potential, user list,
- * state and step counter; its own stream and memory, freed before
- * returning), times the spin-phase and force kernels with HIP events, and
- * sets the fastest shape on sys (returned in *chosen if not NULL). sys is
+/* Autotuner. Runs windows of `steps` steps of length dt under each
+ * candidate launch shape (spin lanes 1, 2, 4; force lanes 1, 2; the
+ * exchange-coefficient cache on or off) on a scratch copy of the system
+ * (same parameters, interactions, learned potential, user list, state and
+ * step counter; its own stream and memory, freed before returning), times
+ * each whole window with HIP events on the copy's stream (a window with a
+ * list rebuild in it is run again; three rounds, best window per shape),
+ * and sets the fastest shape on sys (returned in *chosen if not NULL). sys is
  * not advanced, and its later results change at most by summation-order
  * roundoff (the shape only splits neighbour sums across lanes); colouring,
  * skin and rebuild rule are never touched. When the environment variable

@@ -2153,41 +2153,51 @@ int sl_autotune(sl_system *S, int steps, double dt, sl_tuning *chosen) {
   if (!cache_lookup(key, v)) {
     sl_system *C = nullptr;
     CHK(clone_system(S, &C));
-    // (spin lanes, force lanes, J cache) trials, each run twice in turn
-    // (the better run counts). Spin lanes and the J cache are judged by the
-    // spin-phase time per step including the cache's own kernel, force
-    // lanes by the force kernel time.
-    const int trial[4][3] = {{1, 1, 1}, {2, 2, 1}, {4, 1, 1}, {2, 1, -1}};
-    double spin_ms[4] = {1e300, 1e300, 1e300, 1e300}, force_us[4] = {1e300, 1e300, 1e300, 1e300};
+    // Every candidate (spin lanes, force lanes, J cache) runs a window of
+    // `steps` steps on the clone, timed with events on its stream: the whole
+    // step counts, so the cache's own kernel and its effect on the other
+    // kernels (it shares the caches with them) are part of the comparison.
+    // A window with a list rebuild in it is run again; three rounds over
+    // all candidates, the best window of each counts.
+    const int trial[8][3] = {{2, 1, -1}, {1, 1, 1}, {2, 1, 1}, {1, 1, -1},
+                             {4, 1, 1}, {4, 1, -1}, {2, 2, -1}, {1, 2, 1}};
+    double best[8];
+    for (double &b : best) b = 1e300;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SL_OK;
-    for (int pass = 0; pass < 2 && rc == SL_OK; ++pass)
-      for (int t = 0; t < 4 && rc == SL_OK; ++t) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = SL_E_HIP;
+    for (int pass = 0; pass < 3 && rc == SL_OK; ++pass)
+      for (int t = 0; t < 8 && rc == SL_OK; ++t) {
         sl_tuning tt{trial[t][0], trial[t][1], S->small_class, trial[t][2]};
         if ((rc = sl_set_tuning(C, &tt))) break;
         if ((rc = sl_step(C, 3, dt))) break;
-        if ((rc = sl_set_profiling(C, 1))) break;
-        if ((rc = sl_step(C, steps, dt))) break;
-        if ((rc = sl_synchronize(C))) break;
-        int64_t l0 = 0, l1 = 0, l3 = 0;
-        double m0 = 0, m1 = 0, m3 = 0, w = 0;
-        sl_get_profile(C, 0, &l0, &m0, &w);
-        sl_get_profile(C, 1, &l1, &m1, &w);
-        sl_get_profile(C, 3, &l3, &m3, &w);
-        spin_ms[t] = std::min(spin_ms[t], (m0 + m3) / steps);
-        if (l1) force_us[t] = std::min(force_us[t], 1e3 * m1 / l1);
-        rc = sl_set_profiling(C, 0);
+        for (int attempt = 0; attempt < 3 && rc == SL_OK; ++attempt) {
+          const int64_t rb0 = C->rebuilds;
+          if (hipEventRecord(e0, C->st) != hipSuccess) { rc = SL_E_HIP; break; }
+          if ((rc = sl_step(C, steps, dt))) break;
+          if (hipEventRecord(e1, C->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = SL_E_HIP;
+            break;
+          }
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = SL_E_HIP; break; }
+          if (C->rebuilds != rb0) continue;  // a rebuild in the window: run it again
+          best[t] = std::min(best[t], (double)ms / steps);
+          break;
+        }
       }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     const std::string err = rc ? C->last_err : std::string();
     sl_destroy(C);
     if (rc) return fail(S, rc, "autotune trial: " + err);
-    int bs = 0;
-    for (int t = 1; t < 4; ++t)
-      if (spin_ms[t] < spin_ms[bs]) bs = t;
-    const double f1 = std::min(force_us[0], std::min(force_us[2], force_us[3])), f2 = force_us[1];
-    v[0] = trial[bs][0];
-    v[1] = (S->prm.frozen || f1 <= f2) ? 1 : 2;
+    int bt = 0;
+    for (int t = 1; t < 8; ++t)
+      if (best[t] < best[bt]) bt = t;
+    v[0] = trial[bt][0];
+    v[1] = S->prm.frozen ? 1 : trial[bt][1];
     v[2] = S->small_class;
-    v[3] = trial[bs][2];
+    v[3] = trial[bt][2];
     cache_store(key, v);
   }
   sl_tuning t{v[0], v[1], v[2], v[3]};

@@ -222,6 +222,9 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
     // and spins, the rest [ns, na) lies beyond the exchange cutoff (its
     // build-time distance exceeds ex_rc + skin, and no atom has moved more
     // than skin/2) and needs positions only.
+    // (the two segments are unrolled: each copy knows whether it needs the
+    // neighbour spins, and schedules all of a chunk's loads together)
+#pragma unroll
     for (int seg = 0; seg < 2; ++seg) {
       const int beg = seg == 0 ? 0 : ns, end = seg == 0 ? ns : na;
       for (int base = beg + l; base < end; base += LANES * kForceChunk) {
@@ -233,28 +236,18 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
         }
         double px[kForceChunk], py[kForceChunk], pz[kForceChunk];
         real sij[kForceChunk];
-        real qx[kForceChunk], qy[kForceChunk], qz[kForceChunk];  // kV == 4
+        real qx[kForceChunk], qy[kForceChunk], qz[kForceChunk];  // spin segment
         real fpj[kForceChunk];                                   // kEam
         float4 tt[kForceChunk];
 #pragma unroll
         for (int c = 0; c < kForceChunk; ++c) {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
           if (kEam) fpj[c] = eam ? (real)S.eam[jj[c]] : (real)0;
+          if (seg == 0) { qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]]; }
         }
-        if (seg == 0 && kV == 4) {
 #pragma unroll
-          for (int c = 0; c < kForceChunk; ++c) {
-            qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
-            sij[c] = six * qx[c] + siy * qy[c] + siz * qz[c];
-          }
-        } else if (seg == 0) {
-#pragma unroll
-          for (int c = 0; c < kForceChunk; ++c)
-            sij[c] = six * S.sx[jj[c]] + siy * S.sy[jj[c]] + siz * S.sz[jj[c]];
-        } else {
-#pragma unroll
-          for (int c = 0; c < kForceChunk; ++c) sij[c] = 0;
-        }
+        for (int c = 0; c < kForceChunk; ++c)
+          sij[c] = seg == 0 ? six * qx[c] + siy * qy[c] + siz * qz[c] : (real)0;
         if (kV == 1) {
 #pragma unroll
           for (int c = 0; c < kForceChunk; ++c) {
