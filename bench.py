@@ -71,7 +71,8 @@ def counter_traffic(kernel, precision, shape=None):
     summary, or None when there is none, the kernel sources changed since
     the counters were taken, or the summary is of another launch shape."""
     tag = "fp64" if precision == sl.SL_FP64 else "fp32"
-    path = os.path.join(PROFILES, f"{kernel}_432k_{tag}_memory_counters.txt")
+    stag = "" if shape is None else "_" + shape.replace("=", "").replace(",", "_")
+    path = os.path.join(PROFILES, f"{kernel}_432k_{tag}{stag}_memory_counters.txt")
     if not os.path.exists(path):
         return None
     vals = {}

@@ -82,6 +82,7 @@ struct sl_system {
   double *kx = nullptr, *ky = nullptr, *kz = nullptr;
   double *stage = nullptr;  // 3n doubles
   int *err = nullptr, *seen = nullptr, *jpcnt = nullptr, *maxc = nullptr;
+  int *jplist[2] = {nullptr, nullptr};  // Jones-Plassmann work lists
   unsigned long long *dslot = nullptr;
   unsigned int *done = nullptr;
   double *partial = nullptr, *red_out = nullptr;
@@ -489,13 +490,18 @@ ColourArgs colour_args(sl_system *S) {
   return C;
 }
 
+// Jones-Plassmann rounds until every atom has a colour. Round r reads list
+// r % 2 with count r % 3 and writes list (r + 1) % 2 with count (r + 1) % 3.
 int jp_rounds(sl_system *S, const ColourArgs &C) {
-  HIPCHK(S, hipMemsetAsync(S->jpcnt, 0, 2 * sizeof(int), S->st));
+  HIPCHK(S, hipMemsetAsync(S->jpcnt, 0, 3 * sizeof(int), S->st));
+  launch_colour_list_init(C, S->jplist[0], &S->jpcnt[0], S->st);
   int r = 0;
   for (;;) {
-    for (int b = 0; b < kJpBatch; ++b, ++r) launch_colour_round(C, &S->jpcnt[r & 1], &S->jpcnt[(r + 1) & 1], S->st);
+    for (int b = 0; b < kJpBatch; ++b, ++r)
+      launch_colour_round(C, S->jplist[r & 1], &S->jpcnt[r % 3], S->jplist[(r + 1) & 1],
+                          &S->jpcnt[(r + 1) % 3], &S->jpcnt[(r + 2) % 3], S->st);
     int rem = 0;
-    HIPCHK(S, hipMemcpyAsync(&rem, &S->jpcnt[(r - 1) & 1], sizeof(int), hipMemcpyDeviceToHost, S->st));
+    HIPCHK(S, hipMemcpyAsync(&rem, &S->jpcnt[r % 3], sizeof(int), hipMemcpyDeviceToHost, S->st));
     HIPCHK(S, hipStreamSynchronize(S->st));
     if (rem == 0) break;
     if (r > S->n + 2 * kJpBatch) return fail(S, SL_E_COLOR, "colouring rounds made no progress");
@@ -1177,7 +1183,9 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(dalloc(&S->stage, 3 * (size_t)n));
   A_(dalloc(&S->err, 1));
   A_(dalloc(&S->seen, 2));
-  A_(dalloc(&S->jpcnt, 2));
+  A_(dalloc(&S->jpcnt, 3));
+  A_(dalloc(&S->jplist[0], (size_t)n));
+  A_(dalloc(&S->jplist[1], (size_t)n));
   A_(dalloc(&S->maxc, 1));
   A_(dalloc(&S->dslot, 3));
   A_(dalloc(&S->done, 1));
@@ -1224,6 +1232,7 @@ int sl_destroy(sl_system *S) {
                   (void *)S->perm, (void *)S->inv, (void *)S->uinv, (void *)S->ctmp,
                   (void *)S->kx, (void *)S->ky, (void *)S->kz, (void *)S->stage, (void *)S->err,
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
+                  (void *)S->jplist[0], (void *)S->jplist[1],
                   (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo,
                   (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
                   (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1], (void *)S->eam,
@@ -2093,6 +2102,8 @@ int clone_system(sl_system *S, sl_system **out) {
     if ((rc = sl_set_neighbor_list(C, off.data(), idx.data(), SL_HOST))) return bail(rc);
   }
   if (S->mlp && (rc = sl_set_mlp(C, S->mlp))) return bail(rc);
+  if (S->mlp && (rc = sl_set_mlp_mode(C, S->mlp_mode))) return bail(rc);
+  if ((rc = sl_set_ordering(C, S->ordering, S->sgrid))) return bail(rc);
   if ((rc = sl_set_step(C, S->step))) return bail(rc);
   *out = C;
   return SL_OK;

@@ -214,12 +214,11 @@ __global__ void k_colour_mark(ColourArgs A, int *out) {
 // either seen with its final colour or seen uncoloured (then this atom waits
 // a round); both give the sequential greedy result, only the round count
 // can differ.
-__global__ void k_colour_round(ColourArgs A, int *remaining, int *reset_next) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *reset_next = 0;
-  if (i >= A.n) return;
+// Colour atom i if every conflicting neighbour of earlier key has its
+// colour (first free colour among all coloured conflicting neighbours);
+// returns false when it has to wait for a later round.
+__device__ __forceinline__ bool colour_try(const ColourArgs &A, int i) {
   volatile int *col = A.colour;
-  if (col[i] >= 0) return;
   unsigned long long used = 0ull;
   for (int k = 0; k < A.nspin[i]; ++k) {
     const int j = A.nbr[(size_t)k * A.ld + i];
@@ -228,11 +227,32 @@ __global__ void k_colour_round(ColourArgs A, int *remaining, int *reset_next) {
     if (cj >= 0) {
       used |= 1ull << (cj & 63);
     } else if (key_less(A, j, i)) {
-      atomicAdd(remaining, 1);
-      return;
+      return false;
     }
   }
   col[i] = __ffsll((long long)~used) - 1;
+  return true;
+}
+
+// The uncoloured atoms form the first work list.
+__global__ void k_colour_list_init(ColourArgs A, int *list, int *count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < A.n && A.colour[i] < 0) list[atomicAdd(count, 1)] = i;
+}
+
+// One Jones-Plassmann round over the work list: the atoms that must wait go
+// to the next list. The result does not depend on the list order (an
+// atom's colour is fixed by its earlier-key neighbours' colours alone), so
+// the lists need no ordering. The counter of the round after next is
+// cleared here (nothing reads or writes it in this round).
+__global__ void k_colour_round(ColourArgs A, const int *in, const int *in_count, int *out,
+                               int *out_count, int *clear_next) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *clear_next = 0;
+  const int m = *in_count;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+    const int i = in[t];
+    if (!colour_try(A, i)) out[atomicAdd(out_count, 1)] = i;
+  }
 }
 
 __global__ void k_colour_stats(ColourArgs A, int *maxc, int *err) {
@@ -420,8 +440,14 @@ void launch_colour_fill(int n, int *colour, int value, hipStream_t st) {
 void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st) {
   if (A.n > 0) hipLaunchKernelGGL(k_colour_mark, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, colour_out);
 }
-void launch_colour_round(const ColourArgs &A, int *remaining, int *reset_next, hipStream_t st) {
-  hipLaunchKernelGGL(k_colour_round, dim3(nblocks(A.n > 0 ? A.n : 1)), dim3(kBlock), 0, st, A, remaining, reset_next);
+void launch_colour_list_init(const ColourArgs &A, int *list, int *count, hipStream_t st) {
+  if (A.n > 0) hipLaunchKernelGGL(k_colour_list_init, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, list, count);
+}
+void launch_colour_round(const ColourArgs &A, const int *in, const int *in_count, int *out,
+                         int *out_count, int *clear_next, hipStream_t st) {
+  const int nb = nblocks(A.n > 0 ? A.n : 1);
+  hipLaunchKernelGGL(k_colour_round, dim3(nb < 1024 ? nb : 1024), dim3(kBlock), 0, st, A, in,
+                     in_count, out, out_count, clear_next);
 }
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st) {
   if (A.n > 0) hipLaunchKernelGGL(k_colour_stats, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, maxc, err);

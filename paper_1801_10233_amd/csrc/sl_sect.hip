@@ -28,6 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_sect_keys(SectKeyArgs A) {
       const double f = x / A.L[a] * A.g[a];
       int q = (int)floor(f);
       if (q >= A.g[a]) q = A.g[a] - 1;
+      if (!(q >= 0)) q = 0;  // never outside the grid, whatever the input
       p[a] = q;
       b[a] = (f - q) >= 0.5;
     }

@@ -1,0 +1,53 @@
+"""Host-side logic of the benchmark (no GPU): the single-GPU guard, the
+rocprofv3 summaries, and the byte accounting of the roofline."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_summaries_of_trace_and_counter_files(tmp_path, capsys):
+    B = _bench()
+    kt = tmp_path / "kt_kernel_trace.csv"
+    kt.write_text("Kernel_Name,Start_Timestamp,End_Timestamp\n"
+                  "k_a,100,1100\nk_a,2000,5000\nk_b,0,500\n")
+    pc = tmp_path / "pc_counter_collection.csv"
+    pc.write_text("Kernel_Name,Counter_Name,Counter_Value\n"
+                  "k_a,FETCH_SIZE,10\nk_a,FETCH_SIZE,30\nk_b,WRITE_SIZE,7\n")
+    B.summarize([str(kt), str(pc)])
+    out = capsys.readouterr().out
+    # k_a: two launches of 1 us and 3 us
+    line = [l for l in out.splitlines() if l.endswith("k_a") and "calls" in l][0]
+    assert "calls=     2" in line and "mean_us=     2.000" in line
+    line = [l for l in out.splitlines() if "FETCH_SIZE" in l][0]
+    assert "dispatches=     2" in line and "mean=          20.0" in line
+
+
+def test_algorithmic_bytes_and_profile_lookup():
+    B = _bench()
+    sl = B.sl
+    # plain spin update: s r/w, own r, 14 indices; cached: 14 J instead of r
+    assert B.SPIN_BYTES[sl.SL_FP64] == 128 and B.SPIN_BYTES_JC[sl.SL_FP64] == 216
+    assert B.FORCE_BYTES[sl.SL_FP64] == 384
+    assert B.STEP_BYTES_JC[sl.SL_FP64] == 4 * 216 + 384 + 192
+    # a summary of another launch shape or of older sources is never used
+    assert B.counter_traffic("k_spin_phase", sl.SL_FP64, "lanes=3,jcache=0") is None
+    assert B.counter_traffic("no_such_kernel", sl.SL_FP64, "lanes=1") is None
