@@ -126,7 +126,7 @@ def sync():
 
 
 PROFILE_EVERY = 10   # HIP events bracket the launches of every 10th timed step
-TUNE_STEPS = 50      # steps per autotuner window (8 launch shapes x 3 rounds)
+TUNE_STEPS = 50      # steps per autotuner window (8 launch shapes x 4 rounds)
 
 
 def timed_run(S, steps, dt, profile=False):
@@ -346,6 +346,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shapes (no autotune before timing)")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--tune-steps", type=int, default=TUNE_STEPS,
+                    help="steps per autotuner window")
+    ap.add_argument("--shape", metavar="SPIN,FORCE,JCACHE",
+                    help="fixed launch shape for the timed FP64/FP32 run instead of autotuning "
+                         "(spin lanes, force lanes, exchange cache 1/-1)")
     ap.add_argument("--summarize", nargs="+", metavar="CSV",
                     help="print per-kernel averages of rocprofv3 CSV files and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -371,7 +376,12 @@ def main():
     t_setup = time.perf_counter()
     S = sl.system_from_workload(w, precision=prec, thermo_every=100)
     S.step(0, w.dt)                     # first list build and colouring
-    tuned = None if args.no_tune else S.autotune(TUNE_STEPS, w.dt)
+    if args.shape:
+        sp, fo, jc = (int(x) for x in args.shape.split(","))
+        S.set_tuning(sp, fo, 0, jc)
+        tuned = S.tuning()
+    else:
+        tuned = None if args.no_tune else S.autotune(args.tune_steps, w.dt)
     S.step(args.warmup, w.dt)
     S.synchronize()
     log(f"setup + warmup {time.perf_counter() - t_setup:.2f} s; stats {S.stats()}")

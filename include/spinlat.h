@@ -287,7 +287,8 @@ int sl_get_tuning(sl_system *sys, sl_tuning *t);
  * (same parameters, interactions, learned potential, user list, state and
  * step counter; its own stream and memory, freed before returning), times
  * each whole window with HIP events on the copy's stream (a window with a
- * list rebuild in it is run again; three rounds, best window per shape),
+ * list rebuild in it is run again; four rounds in rotating order, best
+ * window per shape),
  * and sets the fastest shape on sys (returned in *chosen if not NULL). sys is
  * not advanced, and its later results change at most by summation-order
  * roundoff (the shape only splits neighbour sums across lanes); colouring,

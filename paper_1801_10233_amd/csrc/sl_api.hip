@@ -2168,7 +2168,7 @@ int sl_autotune(sl_system *S, int steps, double dt, sl_tuning *chosen) {
     // `steps` steps on the clone, timed with events on its stream: the whole
     // step counts, so the cache's own kernel and its effect on the other
     // kernels (it shares the caches with them) are part of the comparison.
-    // A window with a list rebuild in it is run again; three rounds over
+    // A window with a list rebuild in it is run again; four rounds over
     // all candidates, the best window of each counts.
     const int trial[8][3] = {{2, 1, -1}, {1, 1, 1}, {2, 1, 1}, {1, 1, -1},
                              {4, 1, 1}, {4, 1, -1}, {2, 2, -1}, {1, 2, 1}};
@@ -2177,8 +2177,11 @@ int sl_autotune(sl_system *S, int steps, double dt, sl_tuning *chosen) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SL_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = SL_E_HIP;
-    for (int pass = 0; pass < 3 && rc == SL_OK; ++pass)
-      for (int t = 0; t < 8 && rc == SL_OK; ++t) {
+    // the order of the candidates rotates from round to round, so no shape
+    // always follows the same other one
+    for (int pass = 0; pass < 4 && rc == SL_OK; ++pass)
+      for (int q = 0; q < 8 && rc == SL_OK; ++q) {
+        const int t = (q + 3 * pass) % 8;
         sl_tuning tt{trial[t][0], trial[t][1], S->small_class, trial[t][2]};
         if ((rc = sl_set_tuning(C, &tt))) break;
         if ((rc = sl_step(C, 3, dt))) break;
