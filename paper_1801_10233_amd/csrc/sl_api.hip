@@ -2177,6 +2177,9 @@ int sl_autotune(sl_system *S, int steps, double dt, sl_tuning *chosen) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SL_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = SL_E_HIP;
+    // sustained load first: the device's clocks and caches then are those of
+    // a long run, not of a device that has just been idle
+    if (rc == SL_OK) rc = sl_step(C, 6 * steps, dt);
     // the order of the candidates rotates from round to round, so no shape
     // always follows the same other one
     for (int pass = 0; pass < 4 && rc == SL_OK; ++pass)
