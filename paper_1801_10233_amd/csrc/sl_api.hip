@@ -490,15 +490,15 @@ ColourArgs colour_args(sl_system *S) {
   return C;
 }
 
-// Jones-Plassmann rounds until every atom has a colour. Round r reads list
+// Colouring rounds until every atom has a colour. Round r reads ready list
 // r % 2 with count r % 3 and writes list (r + 1) % 2 with count (r + 1) % 3.
 int jp_rounds(sl_system *S, const ColourArgs &C) {
   HIPCHK(S, hipMemsetAsync(S->jpcnt, 0, 3 * sizeof(int), S->st));
-  launch_colour_list_init(C, S->jplist[0], &S->jpcnt[0], S->st);
+  launch_colour_indeg(C, S->ctmp, S->jplist[0], &S->jpcnt[0], S->st);
   int r = 0;
   for (;;) {
     for (int b = 0; b < kJpBatch; ++b, ++r)
-      launch_colour_round(C, S->jplist[r & 1], &S->jpcnt[r % 3], S->jplist[(r + 1) & 1],
+      launch_colour_round(C, S->ctmp, S->jplist[r & 1], &S->jpcnt[r % 3], S->jplist[(r + 1) & 1],
                           &S->jpcnt[(r + 1) % 3], &S->jpcnt[(r + 2) % 3], S->st);
     int rem = 0;
     HIPCHK(S, hipMemcpyAsync(&rem, &S->jpcnt[r % 3], sizeof(int), hipMemcpyDeviceToHost, S->st));

@@ -100,12 +100,13 @@ void launch_colour_fill(int n, int *colour, int value, hipStream_t st);
 // Uncolour every atom that shares its colour with an earlier-key neighbour,
 // and every atom whose colour lies outside the base palette.
 void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st);
-// Jones-Plassmann rounds with key priority and first-fit colour choice over
-// a work list of the uncoloured atoms: the first list, then one round
-// (atoms that wait go to *out; *clear_next is zeroed for the round after).
-void launch_colour_list_init(const ColourArgs &A, int *list, int *count, hipStream_t st);
-void launch_colour_round(const ColourArgs &A, const int *in, const int *in_count, int *out,
-                         int *out_count, int *clear_next, hipStream_t st);
+// Key-priority first-fit colouring by readiness: counts of uncoloured
+// earlier-key conflicting neighbours and the first ready list, then one
+// round (colour the ready list; newly ready atoms go to *out; *clear_next is
+// zeroed for the round after).
+void launch_colour_indeg(const ColourArgs &A, int *indeg, int *list, int *count, hipStream_t st);
+void launch_colour_round(const ColourArgs &A, int *indeg, const int *in, const int *in_count,
+                         int *out, int *out_count, int *clear_next, hipStream_t st);
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st);
 
 // Per atom, the spin-segment slots (< 64) whose entry has the atom's colour.

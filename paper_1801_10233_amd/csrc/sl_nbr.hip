@@ -234,24 +234,50 @@ __device__ __forceinline__ bool colour_try(const ColourArgs &A, int i) {
   return true;
 }
 
-// The uncoloured atoms form the first work list.
-__global__ void k_colour_list_init(ColourArgs A, int *list, int *count) {
+// Key-priority first-fit colouring driven by readiness: every uncoloured
+// atom counts its uncoloured conflicting neighbours of earlier key; atoms at
+// zero are ready. Ready atoms never conflict with each other (of two
+// conflicting uncoloured atoms the later one still waits for the earlier),
+// so a round colours all of them at once; each then releases its later-key
+// uncoloured neighbours, and an atom whose count reaches zero joins the next
+// ready list. Every atom is coloured once all its earlier-key neighbours
+// are, from the colours around it then -- the sequential greedy's choice --
+// and each round touches only the atoms that became ready.
+__global__ void k_colour_indeg(ColourArgs A, int *indeg, int *list, int *count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < A.n && A.colour[i] < 0) list[atomicAdd(count, 1)] = i;
+  if (i >= A.n || A.colour[i] >= 0) return;
+  int c = 0;
+  for (int k = 0; k < A.nspin[i]; ++k) {
+    const int j = A.nbr[(size_t)k * A.ld + i];
+    if (conflict(A, i, j) && A.colour[j] < 0 && key_less(A, j, i)) ++c;
+  }
+  indeg[i] = c;
+  if (c == 0) list[atomicAdd(count, 1)] = i;
 }
 
-// One Jones-Plassmann round over the work list: the atoms that must wait go
-// to the next list. The result does not depend on the list order (an
-// atom's colour is fixed by its earlier-key neighbours' colours alone), so
-// the lists need no ordering. The counter of the round after next is
-// cleared here (nothing reads or writes it in this round).
-__global__ void k_colour_round(ColourArgs A, const int *in, const int *in_count, int *out,
-                               int *out_count, int *clear_next) {
+// One round: colour the ready atoms, release their later neighbours. The
+// counter of the round after next is cleared here (nothing else touches it
+// in this round).
+__global__ void k_colour_round(ColourArgs A, int *indeg, const int *in, const int *in_count,
+                               int *out, int *out_count, int *clear_next) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *clear_next = 0;
   const int m = *in_count;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
     const int i = in[t];
-    if (!colour_try(A, i)) out[atomicAdd(out_count, 1)] = i;
+    unsigned long long used = 0ull;
+    for (int k = 0; k < A.nspin[i]; ++k) {
+      const int j = A.nbr[(size_t)k * A.ld + i];
+      if (!conflict(A, i, j)) continue;
+      const int cj = A.colour[j];
+      if (cj >= 0) used |= 1ull << (cj & 63);
+    }
+    A.colour[i] = __ffsll((long long)~used) - 1;
+    for (int k = 0; k < A.nspin[i]; ++k) {
+      const int j = A.nbr[(size_t)k * A.ld + i];
+      if (conflict(A, i, j) && key_less(A, i, j) && A.colour[j] < 0 &&
+          atomicSub(&indeg[j], 1) == 1)
+        out[atomicAdd(out_count, 1)] = j;
+    }
   }
 }
 
@@ -440,14 +466,13 @@ void launch_colour_fill(int n, int *colour, int value, hipStream_t st) {
 void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st) {
   if (A.n > 0) hipLaunchKernelGGL(k_colour_mark, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, colour_out);
 }
-void launch_colour_list_init(const ColourArgs &A, int *list, int *count, hipStream_t st) {
-  if (A.n > 0) hipLaunchKernelGGL(k_colour_list_init, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, list, count);
+void launch_colour_indeg(const ColourArgs &A, int *indeg, int *list, int *count, hipStream_t st) {
+  if (A.n > 0) hipLaunchKernelGGL(k_colour_indeg, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, indeg, list, count);
 }
-void launch_colour_round(const ColourArgs &A, const int *in, const int *in_count, int *out,
-                         int *out_count, int *clear_next, hipStream_t st) {
-  const int nb = nblocks(A.n > 0 ? A.n : 1);
-  hipLaunchKernelGGL(k_colour_round, dim3(nb < 1024 ? nb : 1024), dim3(kBlock), 0, st, A, in,
-                     in_count, out, out_count, clear_next);
+void launch_colour_round(const ColourArgs &A, int *indeg, const int *in, const int *in_count,
+                         int *out, int *out_count, int *clear_next, hipStream_t st) {
+  hipLaunchKernelGGL(k_colour_round, dim3(64), dim3(kBlock), 0, st, A, indeg, in, in_count, out,
+                     out_count, clear_next);
 }
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st) {
   if (A.n > 0) hipLaunchKernelGGL(k_colour_stats, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, maxc, err);
