@@ -82,7 +82,8 @@ struct sl_system {
   double *kx = nullptr, *ky = nullptr, *kz = nullptr;
   double *stage = nullptr;  // 3n doubles
   int *err = nullptr, *seen = nullptr, *jpcnt = nullptr, *maxc = nullptr;
-  int *jplist[2] = {nullptr, nullptr};  // Jones-Plassmann work lists
+  int *jplist[2] = {nullptr, nullptr};  // ready lists of the colouring rounds
+  unsigned long long *jpmask[2] = {nullptr, nullptr};  // conflict / earlier-key slot masks
   unsigned long long *dslot = nullptr;
   unsigned int *done = nullptr;
   double *partial = nullptr, *red_out = nullptr;
@@ -494,12 +495,13 @@ ColourArgs colour_args(sl_system *S) {
 // r % 2 with count r % 3 and writes list (r + 1) % 2 with count (r + 1) % 3.
 int jp_rounds(sl_system *S, const ColourArgs &C) {
   HIPCHK(S, hipMemsetAsync(S->jpcnt, 0, 3 * sizeof(int), S->st));
-  launch_colour_indeg(C, S->ctmp, S->jplist[0], &S->jpcnt[0], S->st);
+  launch_colour_indeg(C, S->ctmp, S->jpmask[0], S->jpmask[1], S->jplist[0], &S->jpcnt[0], S->st);
   int r = 0;
   for (;;) {
     for (int b = 0; b < kJpBatch; ++b, ++r)
-      launch_colour_round(C, S->ctmp, S->jplist[r & 1], &S->jpcnt[r % 3], S->jplist[(r + 1) & 1],
-                          &S->jpcnt[(r + 1) % 3], &S->jpcnt[(r + 2) % 3], S->st);
+      launch_colour_round(C, S->ctmp, S->jpmask[0], S->jpmask[1], S->jplist[r & 1],
+                          &S->jpcnt[r % 3], S->jplist[(r + 1) & 1], &S->jpcnt[(r + 1) % 3],
+                          &S->jpcnt[(r + 2) % 3], S->st);
     int rem = 0;
     HIPCHK(S, hipMemcpyAsync(&rem, &S->jpcnt[r % 3], sizeof(int), hipMemcpyDeviceToHost, S->st));
     HIPCHK(S, hipStreamSynchronize(S->st));
@@ -1186,6 +1188,8 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(dalloc(&S->jpcnt, 3));
   A_(dalloc(&S->jplist[0], (size_t)n));
   A_(dalloc(&S->jplist[1], (size_t)n));
+  A_(dalloc(&S->jpmask[0], (size_t)n));
+  A_(dalloc(&S->jpmask[1], (size_t)n));
   A_(dalloc(&S->maxc, 1));
   A_(dalloc(&S->dslot, 3));
   A_(dalloc(&S->done, 1));
@@ -1232,7 +1236,8 @@ int sl_destroy(sl_system *S) {
                   (void *)S->perm, (void *)S->inv, (void *)S->uinv, (void *)S->ctmp,
                   (void *)S->kx, (void *)S->ky, (void *)S->kz, (void *)S->stage, (void *)S->err,
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
-                  (void *)S->jplist[0], (void *)S->jplist[1],
+                  (void *)S->jplist[0], (void *)S->jplist[1], (void *)S->jpmask[0],
+                  (void *)S->jpmask[1],
                   (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo,
                   (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
                   (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1], (void *)S->eam,

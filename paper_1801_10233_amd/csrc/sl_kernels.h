@@ -104,8 +104,12 @@ void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st);
 // earlier-key conflicting neighbours and the first ready list, then one
 // round (colour the ready list; newly ready atoms go to *out; *clear_next is
 // zeroed for the round after).
-void launch_colour_indeg(const ColourArgs &A, int *indeg, int *list, int *count, hipStream_t st);
-void launch_colour_round(const ColourArgs &A, int *indeg, const int *in, const int *in_count,
+// The conflict and earlier-key slot masks (cmask, emask) are computed once
+// by the first pass and read by every round.
+void launch_colour_indeg(const ColourArgs &A, int *indeg, unsigned long long *cmask,
+                         unsigned long long *emask, int *list, int *count, hipStream_t st);
+void launch_colour_round(const ColourArgs &A, int *indeg, const unsigned long long *cmask,
+                         const unsigned long long *emask, const int *in, const int *in_count,
                          int *out, int *out_count, int *clear_next, hipStream_t st);
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st);
 

@@ -243,40 +243,74 @@ __device__ __forceinline__ bool colour_try(const ColourArgs &A, int i) {
 // ready list. Every atom is coloured once all its earlier-key neighbours
 // are, from the colours around it then -- the sequential greedy's choice --
 // and each round touches only the atoms that became ready.
-__global__ void k_colour_indeg(ColourArgs A, int *indeg, int *list, int *count) {
+__global__ void k_colour_indeg(ColourArgs A, int *indeg, unsigned long long *cmask,
+                               unsigned long long *emask, int *list, int *count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n || A.colour[i] >= 0) return;
+  // spin-segment slots that are edges of the colouring graph, and those of
+  // them whose atom comes earlier in key order (the segment has < 64 slots)
+  unsigned long long cm = 0ull, em = 0ull;
   int c = 0;
-  for (int k = 0; k < A.nspin[i]; ++k) {
+  const int ns = A.nspin[i] < 64 ? A.nspin[i] : 64;
+  for (int k = 0; k < ns; ++k) {
     const int j = A.nbr[(size_t)k * A.ld + i];
-    if (conflict(A, i, j) && A.colour[j] < 0 && key_less(A, j, i)) ++c;
+    if (!conflict(A, i, j)) continue;
+    cm |= 1ull << k;
+    if (key_less(A, j, i)) {
+      em |= 1ull << k;
+      if (A.colour[j] < 0) ++c;
+    }
   }
+  cmask[i] = cm;
+  emask[i] = em;
   indeg[i] = c;
   if (c == 0) list[atomicAdd(count, 1)] = i;
 }
 
 // One round: colour the ready atoms, release their later neighbours. The
 // counter of the round after next is cleared here (nothing else touches it
-// in this round).
-__global__ void k_colour_round(ColourArgs A, int *indeg, const int *in, const int *in_count,
-                               int *out, int *out_count, int *clear_next) {
+// in this round). The slot loads of a chunk go out together, then the
+// colour loads: each ready atom costs a few memory round trips.
+constexpr int kColourChunk = 16;
+__global__ void k_colour_round(ColourArgs A, int *indeg, const unsigned long long *cmask,
+                               const unsigned long long *emask, const int *in,
+                               const int *in_count, int *out, int *out_count, int *clear_next) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *clear_next = 0;
   const int m = *in_count;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
     const int i = in[t];
+    const unsigned long long cm = cmask[i], em = emask[i];
+    const int ns = A.nspin[i] < 64 ? A.nspin[i] : 64;
     unsigned long long used = 0ull;
-    for (int k = 0; k < A.nspin[i]; ++k) {
-      const int j = A.nbr[(size_t)k * A.ld + i];
-      if (!conflict(A, i, j)) continue;
-      const int cj = A.colour[j];
-      if (cj >= 0) used |= 1ull << (cj & 63);
+    for (int k0 = 0; k0 < ns; k0 += kColourChunk) {
+      int jj[kColourChunk];
+#pragma unroll
+      for (int q = 0; q < kColourChunk; ++q) {
+        const int k = k0 + q;
+        jj[q] = (k < ns && ((cm >> k) & 1ull)) ? A.nbr[(size_t)k * A.ld + i] : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < kColourChunk; ++q) {
+        const int cj = jj[q] >= 0 ? A.colour[jj[q]] : -1;
+        if (cj >= 0) used |= 1ull << (cj & 63);
+      }
     }
     A.colour[i] = __ffsll((long long)~used) - 1;
-    for (int k = 0; k < A.nspin[i]; ++k) {
-      const int j = A.nbr[(size_t)k * A.ld + i];
-      if (conflict(A, i, j) && key_less(A, i, j) && A.colour[j] < 0 &&
-          atomicSub(&indeg[j], 1) == 1)
-        out[atomicAdd(out_count, 1)] = j;
+    // later-key uncoloured neighbours lose one wait; the last one queues them
+    const unsigned long long later = cm & ~em;
+    for (int k0 = 0; k0 < ns; k0 += kColourChunk) {
+      int jj[kColourChunk];
+#pragma unroll
+      for (int q = 0; q < kColourChunk; ++q) {
+        const int k = k0 + q;
+        jj[q] = (k < ns && ((later >> k) & 1ull)) ? A.nbr[(size_t)k * A.ld + i] : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < kColourChunk; ++q) {
+        const int j = jj[q];
+        if (j >= 0 && A.colour[j] < 0 && atomicSub(&indeg[j], 1) == 1)
+          out[atomicAdd(out_count, 1)] = j;
+      }
     }
   }
 }
@@ -466,13 +500,17 @@ void launch_colour_fill(int n, int *colour, int value, hipStream_t st) {
 void launch_colour_mark(const ColourArgs &A, int *colour_out, hipStream_t st) {
   if (A.n > 0) hipLaunchKernelGGL(k_colour_mark, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, colour_out);
 }
-void launch_colour_indeg(const ColourArgs &A, int *indeg, int *list, int *count, hipStream_t st) {
-  if (A.n > 0) hipLaunchKernelGGL(k_colour_indeg, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, indeg, list, count);
+void launch_colour_indeg(const ColourArgs &A, int *indeg, unsigned long long *cmask,
+                         unsigned long long *emask, int *list, int *count, hipStream_t st) {
+  if (A.n > 0)
+    hipLaunchKernelGGL(k_colour_indeg, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, indeg, cmask,
+                       emask, list, count);
 }
-void launch_colour_round(const ColourArgs &A, int *indeg, const int *in, const int *in_count,
+void launch_colour_round(const ColourArgs &A, int *indeg, const unsigned long long *cmask,
+                         const unsigned long long *emask, const int *in, const int *in_count,
                          int *out, int *out_count, int *clear_next, hipStream_t st) {
-  hipLaunchKernelGGL(k_colour_round, dim3(64), dim3(kBlock), 0, st, A, indeg, in, in_count, out,
-                     out_count, clear_next);
+  hipLaunchKernelGGL(k_colour_round, dim3(64), dim3(kBlock), 0, st, A, indeg, cmask, emask, in,
+                     in_count, out, out_count, clear_next);
 }
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st) {
   if (A.n > 0) hipLaunchKernelGGL(k_colour_stats, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, maxc, err);
