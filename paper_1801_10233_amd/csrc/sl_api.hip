@@ -743,9 +743,12 @@ int ensure_ready(sl_system *S) {
 // --- launches ---------------------------------------------------------------
 double noise_amp(const sl_system *S, double h);
 
+// One launch of class c: nrep successive updates at buffer posbuf, or with
+// dual set the two updates across the drift (the first at posbuf, the
+// second at the other buffer).
 template <typename real>
 void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps, const int *subs,
-                 double h) {
+                 double h, bool dual = false) {
   SpinPhaseArgs A;
   std::memset(&A, 0, sizeof(A));
   A.begin = S->class_off[c];
@@ -760,8 +763,13 @@ void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps
   A.seed = S->prm.seed;
   A.replica = S->prm.replica;
   A.rs2 = S->pot.ex_rc * S->pot.ex_rc;
-  ProfScope ps(S, 0, (double)(A.end - A.begin));
-  launch_spin_phase<real>(view<real>(S, posbuf), S->pc, A, S->spin_lanes, S->st);
+  ProfScope ps(S, 0, (double)(A.end - A.begin));  // atoms (a dual launch counts them once)
+  if (dual) {
+    const SysView<real> v2 = view<real>(S, 1 - posbuf);
+    launch_spin_phase<real>(view<real>(S, posbuf), S->pc, A, S->spin_lanes, S->st, &v2);
+  } else {
+    launch_spin_phase<real>(view<real>(S, posbuf), S->pc, A, S->spin_lanes, S->st);
+  }
 }
 
 // A run of dt/4 updates (class, step, sub) applied in order. Consecutive
@@ -1090,12 +1098,29 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
       sect_half<real>(S, S->pos, k, 0, h);
       sect_half<real>(S, 1 - S->pos, k, 2, h);
     } else {
-      std::vector<Upd> u;
+      std::vector<Upd> u, w;
       half_step_updates(S, k, 0, u);
-      run_updates<real>(S, S->pos, u, h);
-      u.clear();
-      half_step_updates(S, k, 2, u);
-      run_updates<real>(S, 1 - S->pos, u, h);
+      half_step_updates(S, k, 2, w);
+      // the first class closes one half-step and opens the next: its two
+      // updates around the drift go in one dual launch when it is large
+      // enough for its own launch anyway
+      const int c0 = u.back().c;
+      const bool dual = S->K >= 2 && w.front().c == c0 &&
+                        S->class_off[c0 + 1] - S->class_off[c0] > S->small_class;
+      if (dual) {
+        u.pop_back();
+        w.erase(w.begin());
+        run_updates<real>(S, S->pos, u, h);
+        (void)ensure_table(S, 1 - S->pos);
+        (void)ensure_jcache<real>(S, 1 - S->pos);
+        const int64_t st2[2] = {k, k};
+        const int sb2[2] = {1, 2};
+        spin_launch<real>(S, S->pos, c0, 2, st2, sb2, h, true);
+        run_updates<real>(S, 1 - S->pos, w, h);
+      } else {
+        run_updates<real>(S, S->pos, u, h);
+        run_updates<real>(S, 1 - S->pos, w, h);
+      }
     }
     const int64_t b = k + 1;
     int mode = kModeFinal;

@@ -7,17 +7,18 @@
 
 namespace sl {
 
-template <typename real, bool LANGEVIN, bool ANISO, int LANES, int MLP>
+template <typename real, bool LANGEVIN, bool ANISO, int LANES, int MLP, bool DUAL>
 __global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst P,
-                                                       SpinPhaseArgs A) {
+                                                       SpinPhaseArgs A, SysView<real> S2) {
   // LANES consecutive lanes share one atom: each gathers every LANES-th
   // neighbour, the partial sums are combined with cross-lane shuffles and
   // the first lane rotates and stores the spin.
   const int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int l = t & (LANES - 1);
   const int i = A.begin + t / LANES;
-  spin_update<real, LANGEVIN, ANISO, LANES, MLP>(S, P, i, i < A.end, l, A.nrep, A.step, A.sub,
-                                                 A.h, A.amp, A.seed, A.replica, A.rs2);
+  spin_update<real, LANGEVIN, ANISO, LANES, MLP, DUAL>(S, P, i, i < A.end, l, A.nrep, A.step,
+                                                       A.sub, A.h, A.amp, A.seed, A.replica,
+                                                       A.rs2, &S2);
 }
 
 // A run of small classes (a few atoms each, e.g. the extra colours a repair
@@ -127,37 +128,44 @@ __global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, 
 // Host launchers. The learned-potential variants (table lookups instead of
 // the analytic J and V) exist in the FP32 form only; variant 4 is the
 // analytic potential with the spin-orbit pair terms.
-template <typename real, int LANES, int MLP>
-static void spin_phase_lanes2(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
-                              hipStream_t st) {
+template <typename real, int LANES, int MLP, bool DUAL>
+static void spin_phase_lanes3(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
+                              const SysView<real> &S2, hipStream_t st) {
   const long threads = (long)(A.end - A.begin) * LANES;
   const int nb = (int)((threads + kBlock - 1) / kBlock);
   const bool lg = P.langevin != 0, an = P.aniso_on != 0;
-  if (lg && an) hipLaunchKernelGGL((k_spin_phase<real, true, true, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
-  else if (lg) hipLaunchKernelGGL((k_spin_phase<real, true, false, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
-  else if (an) hipLaunchKernelGGL((k_spin_phase<real, false, true, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
-  else hipLaunchKernelGGL((k_spin_phase<real, false, false, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  if (lg && an) hipLaunchKernelGGL((k_spin_phase<real, true, true, LANES, MLP, DUAL>), dim3(nb), dim3(kBlock), 0, st, S, P, A, S2);
+  else if (lg) hipLaunchKernelGGL((k_spin_phase<real, true, false, LANES, MLP, DUAL>), dim3(nb), dim3(kBlock), 0, st, S, P, A, S2);
+  else if (an) hipLaunchKernelGGL((k_spin_phase<real, false, true, LANES, MLP, DUAL>), dim3(nb), dim3(kBlock), 0, st, S, P, A, S2);
+  else hipLaunchKernelGGL((k_spin_phase<real, false, false, LANES, MLP, DUAL>), dim3(nb), dim3(kBlock), 0, st, S, P, A, S2);
+}
+
+template <typename real, int LANES, int MLP>
+static void spin_phase_lanes2(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
+                              const SysView<real> *S2, hipStream_t st) {
+  if (S2) spin_phase_lanes3<real, LANES, MLP, true>(S, P, A, *S2, st);
+  else spin_phase_lanes3<real, LANES, MLP, false>(S, P, A, S, st);
 }
 
 template <typename real, int LANES>
 static void spin_phase_lanes(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
-                             hipStream_t st) {
-  if (P.soc_on) spin_phase_lanes2<real, LANES, 4>(S, P, A, st);
-  else if (S.jc) spin_phase_lanes2<real, LANES, 3>(S, P, A, st);
-  else if (sizeof(real) == 4 && S.spl.t) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, st);
-  else if (sizeof(real) == 4 && S.tab) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, st);
-  else spin_phase_lanes2<real, LANES, 0>(S, P, A, st);
+                             const SysView<real> *S2, hipStream_t st) {
+  if (P.soc_on) spin_phase_lanes2<real, LANES, 4>(S, P, A, S2, st);
+  else if (S.jc) spin_phase_lanes2<real, LANES, 3>(S, P, A, S2, st);
+  else if (sizeof(real) == 4 && S.spl.t) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 2 : 0)>(S, P, A, S2, st);
+  else if (sizeof(real) == 4 && S.tab) spin_phase_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, S2, st);
+  else spin_phase_lanes2<real, LANES, 0>(S, P, A, S2, st);
 }
 
 template <typename real>
 void launch_spin_phase(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
-                       int lanes, hipStream_t st) {
+                       int lanes, hipStream_t st, const SysView<real> *S2) {
   if (A.end - A.begin <= 0) return;
   switch (lanes) {
-    case 1: spin_phase_lanes<real, 1>(S, P, A, st); break;
-    case 2: spin_phase_lanes<real, 2>(S, P, A, st); break;
-    case 8: spin_phase_lanes<real, 8>(S, P, A, st); break;
-    default: spin_phase_lanes<real, 4>(S, P, A, st); break;
+    case 1: spin_phase_lanes<real, 1>(S, P, A, S2, st); break;
+    case 2: spin_phase_lanes<real, 2>(S, P, A, S2, st); break;
+    case 8: spin_phase_lanes<real, 8>(S, P, A, S2, st); break;
+    default: spin_phase_lanes<real, 4>(S, P, A, S2, st); break;
   }
 }
 
@@ -200,9 +208,11 @@ void launch_reduce8(const double *partial, int nb, double *out, hipStream_t st) 
 
 
 template void launch_spin_phase<double>(const SysView<double> &, const PotConst &,
-                                        const SpinPhaseArgs &, int, hipStream_t);
+                                        const SpinPhaseArgs &, int, hipStream_t,
+                                        const SysView<double> *);
 template void launch_spin_phase<float>(const SysView<float> &, const PotConst &,
-                                       const SpinPhaseArgs &, int, hipStream_t);
+                                       const SpinPhaseArgs &, int, hipStream_t,
+                                       const SysView<float> *);
 template void launch_spin_tail<double>(const SysView<double> &, const PotConst &,
                                        const TailArgs &, int, hipStream_t);
 template void launch_spin_tail<float>(const SysView<float> &, const PotConst &, const TailArgs &,

@@ -7,9 +7,11 @@ namespace sl {
 
 // --- per-step kernels (sl_dyn.hip) ---
 // `lanes` (1, 2, 4 or 8) consecutive lanes cooperate on one atom.
+// With S2 (the same system at its other position buffer) the launch is the
+// dual update: A.nrep == 2, the first update's field at S, the second's at S2.
 template <typename real>
 void launch_spin_phase(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
-                       int lanes, hipStream_t st);
+                       int lanes, hipStream_t st, const SysView<real> *S2 = nullptr);
 template <typename real>
 void launch_spin_tail(const SysView<real> &S, const PotConst &P, const TailArgs &T, int lanes,
                       hipStream_t st);

@@ -34,11 +34,18 @@ struct SpinChunk {
   static constexpr int value = LANES >= 8 ? 2 : (LANES >= 4 ? 4 : 8);
 };
 
-template <typename real, bool LANGEVIN, bool ANISO, int LANES, int MLP>
+// DUAL: two successive updates of one class at two sets of positions (the
+// last update of a spin half-step and the first of the next, with the drift
+// in between): the neighbour spins are the same for both (no other class
+// moves in between), so they are gathered once and the exchange field is
+// summed at the positions of S for the first update and of S2 (same atoms,
+// same list, the other position buffer) for the second; nrep must be 2.
+template <typename real, bool LANGEVIN, bool ANISO, int LANES, int MLP, bool DUAL = false>
 __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotConst &P, int i,
                                             bool valid, int l, int nrep, const int64_t *step,
                                             const int *sub, double hd, double ampd,
-                                            uint64_t seed, uint32_t replica, double rs2) {
+                                            uint64_t seed, uint32_t replica, double rs2,
+                                            const SysView<real> *S2 = nullptr) {
   // Latency is what bounds this update, so every load that does not depend
   // on another is issued at once: the row length, the own position, spin
   // and id, and the list entries of the first round (taken unconditionally
@@ -48,6 +55,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
   // noise of the first update is computed while they are in flight.
   constexpr int CH = SpinChunk<LANES>::value;
   real ax = 0, ay = 0, az = 0;
+  real bx = 0, by = 0, bz = 0;  // DUAL: field at the positions of S2
   real sx = 0, sy = 0, sz = 0;
   real g0[3] = {0, 0, 0};
   uint32_t aid = 0;
@@ -55,6 +63,8 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
     const int ld = S.ld;
     const int ns = S.nspin[i];
     const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
+    double rix2 = 0, riy2 = 0, riz2 = 0;
+    if (DUAL) { rix2 = S2->rx[i]; riy2 = S2->ry[i]; riz2 = S2->rz[i]; }
     sx = S.sx[i]; sy = S.sy[i]; sz = S.sz[i];
     if (LANGEVIN) aid = (uint32_t)S.id[i];
     for (int base = l, round = 0; round == 0 || base < ns; base += LANES * CH, ++round) {
@@ -70,16 +80,23 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
       double px[CH], py[CH], pz[CH];
       float jt[CH];
       real jr[CH];
+      // DUAL: the same at the second positions
+      real J2[CH], hx2[CH], hy2[CH], hz2[CH];
+      double px2[CH], py2[CH], pz2[CH];
+      float jt2[CH];
+      real jr2[CH];
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
+        const int k = base + LANES * c;
         if (MLP == 1) {
-          const int k = base + LANES * c;
           jt[c] = k < S.kcap ? S.tab[(size_t)k * ld + i].x : 0.f;
+          if (DUAL) jt2[c] = k < S.kcap ? S2->tab[(size_t)k * ld + i].x : 0.f;
         } else if (MLP == 3) {
-          const int k = base + LANES * c;
           jr[c] = k < S.kcap ? S.jc[(size_t)k * ld + i] : (real)0;
+          if (DUAL) jr2[c] = k < S.kcap ? S2->jc[(size_t)k * ld + i] : (real)0;
         } else {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
+          if (DUAL) { px2[c] = S2->rx[jj[c]]; py2[c] = S2->ry[jj[c]]; pz2[c] = S2->rz[jj[c]]; }
         }
         qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
       }
@@ -112,6 +129,35 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
           }
         }
       }
+      if (DUAL) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const bool in = base + LANES * c < ns;
+          if (MLP == 1) {
+            J2[c] = in ? (real)jt2[c] : (real)0;
+          } else if (MLP == 3) {
+            J2[c] = in ? jr2[c] : (real)0;
+          } else if (MLP == 2) {
+            const double dx = min_image(rix2 - px2[c], S.L[0], S.invL[0]);
+            const double dy = min_image(riy2 - py2[c], S.L[1], S.invL[1]);
+            const double dz = min_image(riz2 - pz2[c], S.L[2], S.invL[2]);
+            const float r = (float)sqrt(dx * dx + dy * dy + dz * dz);
+            J2[c] = in ? (real)spline_phys(S.spl, r).x : (real)0;
+          } else {
+            const double dx = min_image(rix2 - px2[c], S.L[0], S.invL[0]);
+            const double dy = min_image(riy2 - py2[c], S.L[1], S.invL[1]);
+            const double dz = min_image(riz2 - pz2[c], S.L[2], S.invL[2]);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const real u = (real)(r2 * P.eInvD2);
+            const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+            J2[c] = (in && r2 < rs2) ? Jc : (real)0;
+            if (MLP == 4) {
+              hx2[c] = hy2[c] = hz2[c] = (real)0;
+              if (in) soc_field<real>(P, dx, dy, dz, r2, qx[c], qy[c], qz[c], hx2[c], hy2[c], hz2[c]);
+            }
+          }
+        }
+      }
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         ax += J[c] * qx[c];
@@ -122,6 +168,16 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
           ay += hy[c];
           az += hz[c];
         }
+        if (DUAL) {
+          bx += J2[c] * qx[c];
+          by += J2[c] * qy[c];
+          bz += J2[c] * qz[c];
+          if (MLP == 4) {
+            bx += hx2[c];
+            by += hy2[c];
+            bz += hz2[c];
+          }
+        }
       }
     }
   }
@@ -130,12 +186,19 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
     ax += __shfl_xor(ax, o, 64);
     ay += __shfl_xor(ay, o, 64);
     az += __shfl_xor(az, o, 64);
+    if (DUAL) {
+      bx += __shfl_xor(bx, o, 64);
+      by += __shfl_xor(by, o, 64);
+      bz += __shfl_xor(bz, o, 64);
+    }
   }
   if (!valid || l != 0) return;
   const real h = (real)hd;
   const real ih = (real)(1.0 / kHbar);
   for (int rep = 0; rep < nrep; ++rep) {
-    real ex = ax + (real)P.zB[0], ey = ay + (real)P.zB[1], ez = az + (real)P.zB[2];
+    const bool second = DUAL && rep == 1;
+    real ex = (second ? bx : ax) + (real)P.zB[0], ey = (second ? by : ay) + (real)P.zB[1],
+         ez = (second ? bz : az) + (real)P.zB[2];
     if (ANISO) {
       const real sn2 = (real)2 * (real)P.aK * (sx * (real)P.an[0] + sy * (real)P.an[1] + sz * (real)P.an[2]);
       ex += sn2 * (real)P.an[0];
