@@ -270,11 +270,15 @@ def test_fp32_form_error_vs_oracle():
     assert abs(eg - eo) / w.N < 1e-5
 
 
-def test_full_size_large_system_sampled_parity():
-    # the 432000-atom workload in the launch configuration of the benchmark:
-    # two FP64 steps on the GPU and in the oracle, every atom compared
+@pytest.mark.parametrize("shape", [(4, 1, 0, -1), (2, 1, 0, -1), (1, 1, 0, 1)])
+def test_full_size_large_system_sampled_parity(shape):
+    # the 432000-atom workload in the launch shapes the benchmark's autotuner
+    # chooses between (4 spin lanes without the exchange cache is its pick on
+    # MI355X): two FP64 steps (a dual spin launch in each) on the GPU and in
+    # the oracle, every atom compared
     w = W.large_langevin(n=60)
     g = make_gpu(w)
+    g.set_tuning(*shape)
     g.step(2, w.dt)
     o = make_oracle(w)
     o.step(2, w.dt)
@@ -282,3 +286,19 @@ def test_full_size_large_system_sampled_parity():
     _print("432k parity", p)
     assert p["ok"], p
     assert g.coloring()[1] == o.coloring()[1] == 4
+
+
+def test_full_size_widened_step_parity():
+    # every widened term at once on the 432000-atom lattice: embedded-atom
+    # mechanics, Neel and DMI pair terms, lattice and spin baths
+    w = W.large_langevin(n=60)
+    w.pot = dict(w.pot, morse_on=0, **W.FS_FE, **W.NEEL_BJ, **W.DMI_BJ, lat_gamma=100.0,
+                 lat_temperature=300.0)
+    g = make_gpu(w)
+    g.set_tuning(4, 1, 0, -1)
+    g.step(2, w.dt)
+    o = make_oracle(w)
+    o.step(2, w.dt)
+    p = parity(w, o, g)
+    _print("432k widened parity", p)
+    assert p["ok"], p
