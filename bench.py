@@ -362,7 +362,8 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this "
-              "build (see DESIGN.md for how the path would shard).", file=sys.stderr)
+              "library: a large system would shard spatially into bricks with halo exchange, "
+              "replicas shard trivially.", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "no GPU visible"
