@@ -54,8 +54,10 @@ STEP_BYTES = {sl.SL_FP64: 4 * SPIN_BYTES[sl.SL_FP64] + FORCE_BYTES[sl.SL_FP64],
 STEP_BYTES_JC = {p: 4 * SPIN_BYTES_JC[p] + FORCE_BYTES[p] + JCACHE_BYTES[p]
                  for p in (sl.SL_FP64, sl.SL_FP32)}
 PROFILES = os.path.join(ROOT, "profiles")
+# the kernels and the list build, whose row order sets the gathers' memory pattern
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_10233_amd", "csrc", f)
-                  for f in ("sl_step.h", "sl_dyn.hip", "sl_force.hip", "sl_device.h")]
+                  for f in ("sl_step.h", "sl_dyn.hip", "sl_force.hip", "sl_device.h",
+                            "sl_nbr.hip", "sl_kernels.h")]
 
 
 def kernel_sources_sha256():

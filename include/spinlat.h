@@ -188,6 +188,20 @@ int sl_set_potential(sl_system *sys, const sl_potential *pot);
  * first-fit in key order. */
 int sl_set_neighbor(sl_system *sys, double skin, int max_nbr);
 
+/* Order of the entries inside each of the two segments of a list row
+ * (a memory-layout choice: the physics is unchanged up to summation-order
+ * roundoff). quantum = 0 (default): cell-loop order. quantum > 0 (A): each
+ * segment sorted by the neighbour's displacement r_j - r_i rounded to a grid
+ * of that step, (z, y, x) lexicographic, ties by internal index. In a
+ * crystal whose neighbour displacements are multiples of the grid step (half
+ * the cubic lattice constant for bcc and fcc) slot k of every row then holds
+ * the neighbour at the same lattice offset, so a wavefront of spatially
+ * sorted atoms gathers slot k from a short contiguous range of memory.
+ * Applies from the next automatic list build (the list is invalidated);
+ * user-supplied lists keep their order. SL_E_ARG if quantum < 0 or not
+ * finite. */
+int sl_set_row_order(sl_system *sys, double quantum);
+
 /* User-supplied full list in CSR form over user ids: offsets[N+1], idx[].
  * Each row is split (stably) into entries closer than ex_rc + skin first.
  * Disables automatic rebuilds. */

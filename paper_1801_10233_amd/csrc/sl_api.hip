@@ -117,6 +117,7 @@ struct sl_system {
   int jcache = -1;  // set from the precision at creation (on for FP32)
   // spin ordering: colour classes, or the paper's sectors / serial order
   int ordering = SL_ORDER_COLOUR;
+  double row_q = 0.0;  // list row order: 0 cell loop, > 0 displacement grid (A)
   int sgrid[3] = {1, 1, 1};
   unsigned long long *skeys[2] = {nullptr, nullptr};
   int *svals[2] = {nullptr, nullptr};
@@ -715,6 +716,7 @@ int rebuild(sl_system *S) {
     B.bz = A.bz;
     B.err = S->err;
     B.seen = S->seen;
+    B.row_q = S->row_q;
     HIPCHK(S, hipMemsetAsync(S->seen, 0, 2 * sizeof(int), S->st));
     launch_nbr_build(B, S->st);
     int seen[2] = {0, 0};
@@ -1901,6 +1903,18 @@ int sl_set_ordering(sl_system *S, int ordering, const int grid[3]) {
   return SL_OK;
 }
 
+int sl_set_row_order(sl_system *S, double quantum) {
+  if (!S) return fail(S, SL_E_ARG, "NULL system");
+  if (!(quantum >= 0.0) || !std::isfinite(quantum)) return fail(S, SL_E_ARG, "row-order grid step must be finite and >= 0");
+  CHK(sl_synchronize(S));
+  S->row_q = quantum;
+  if (!S->user_list) {
+    S->have_list = false;
+    S->have_D = false;
+  }
+  return SL_OK;
+}
+
 int sl_get_temperatures(sl_system *S, double *T_lattice, double *T_spin) {
   if (!S) return fail(S, SL_E_ARG, "NULL system");
   CHK(sl_synchronize(S));
@@ -2134,6 +2148,7 @@ int clone_system(sl_system *S, sl_system **out) {
   if (S->mlp && (rc = sl_set_mlp(C, S->mlp))) return bail(rc);
   if (S->mlp && (rc = sl_set_mlp_mode(C, S->mlp_mode))) return bail(rc);
   if ((rc = sl_set_ordering(C, S->ordering, S->sgrid))) return bail(rc);
+  if ((rc = sl_set_row_order(C, S->row_q))) return bail(rc);
   if ((rc = sl_set_step(C, S->step))) return bail(rc);
   *out = C;
   return SL_OK;

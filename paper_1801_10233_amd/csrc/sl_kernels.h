@@ -79,6 +79,8 @@ struct NbrBuildArgs {
   double *bx, *by, *bz;   // reference positions written at build time
   int *err;
   int *seen;              // [2]: largest spin segment and row
+  double row_q;           // > 0: sort each row segment by the displacement
+                          // rounded to this grid step (A); 0: cell-loop order
 };
 void launch_nbr_build(const NbrBuildArgs &A, hipStream_t st);
 

@@ -165,6 +165,50 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(NbrBuildArgs A) {
   A.bz[i] = riz;
 }
 
+// Row order by displacement: each segment of a freshly built row is sorted
+// by the key (z, y, x of r_j - r_i rounded to the grid 1/invq, 10 bits each,
+// then j). With the atoms sorted spatially, slot k of neighbouring rows then
+// holds neighbours at the same lattice offset, which lie next to each other
+// in memory: the gathers of one slot across a wavefront touch few cache
+// lines. One thread per atom; the keys of a segment sit in LDS, one column
+// per thread (slot-major, so a wavefront's reads hit distinct banks), and
+// every entry goes straight to its rank (keys are unique: they end in j).
+// Segments longer than kOrderMax keep the cell-loop order.
+constexpr int kOrderBlock = 64, kOrderMax = 64;
+__global__ __launch_bounds__(kOrderBlock) void k_row_order(NbrBuildArgs A, double invq) {
+  __shared__ unsigned long long key[kOrderMax * kOrderBlock];
+  const int t = threadIdx.x;
+  const int i = blockIdx.x * kOrderBlock + t;
+  if (i >= A.n) return;
+  const double Lx = A.G.L[0], Ly = A.G.L[1], Lz = A.G.L[2];
+  const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
+  const double rix = A.rx[i], riy = A.ry[i], riz = A.rz[i];
+  const int ns = A.nspin[i], na = A.nall[i];
+  auto q10 = [&](double d) -> unsigned long long {
+    const double q = fmin(fmax(rint(d * invq), -511.0), 511.0);
+    return (unsigned long long)((int)q + 512);
+  };
+  for (int seg = 0; seg < 2; ++seg) {
+    const int beg = seg == 0 ? 0 : ns, end = seg == 0 ? ns : na;
+    const int m = end - beg;
+    if (m < 2 || m > kOrderMax) continue;
+    for (int f = 0; f < m; ++f) {
+      const int j = A.nbr[(size_t)(beg + f) * A.ld + i];
+      const double dx = min_image(A.rx[j] - rix, Lx, iLx);
+      const double dy = min_image(A.ry[j] - riy, Ly, iLy);
+      const double dz = min_image(A.rz[j] - riz, Lz, iLz);
+      const unsigned long long q = (q10(dz) << 20) | (q10(dy) << 10) | q10(dx);
+      key[f * kOrderBlock + t] = (q << 32) | (unsigned)j;
+    }
+    for (int e = 0; e < m; ++e) {
+      const unsigned long long ke = key[e * kOrderBlock + t];
+      int rank = 0;
+      for (int f = 0; f < m; ++f) rank += key[f * kOrderBlock + t] < ke ? 1 : 0;
+      A.nbr[(size_t)(beg + rank) * A.ld + i] = (int)(unsigned)(ke & 0xffffffffull);
+    }
+  }
+}
+
 __global__ void k_keys(int n, const double *rx, const double *ry, const double *rz, double Lx,
                        double Ly, double Lz, double *kx, double *ky, double *kz) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -489,6 +533,9 @@ void launch_nbr_build(const NbrBuildArgs &A, hipStream_t st) {
     const long threads = (long)A.n * 16;
     hipLaunchKernelGGL(k_nbr_build<16>, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, A);
   }
+  if (A.row_q > 0.0)
+    hipLaunchKernelGGL(k_row_order, dim3((unsigned)((A.n + kOrderBlock - 1) / kOrderBlock)),
+                       dim3(kOrderBlock), 0, st, A, 1.0 / A.row_q);
 }
 void launch_keys(int n, const double *rx, const double *ry, const double *rz, const double L[3],
                  double *kx, double *ky, double *kz, hipStream_t st) {

@@ -45,7 +45,7 @@ EXPORTS = [
     "sl_get_energy", "sl_get_magnetization", "sl_get_temperatures", "sl_get_thermo",
     "sl_get_stats",
     "sl_synchronize", "sl_set_tuning", "sl_get_tuning", "sl_autotune", "sl_set_profiling",
-    "sl_set_mlp_mode", "sl_set_ordering",
+    "sl_set_mlp_mode", "sl_set_ordering", "sl_set_row_order",
     "sl_get_profile", "sl_last_error",
     "sl_mlp_create", "sl_mlp_destroy", "sl_mlp_set_weights", "sl_mlp_get_weights",
     "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
@@ -165,6 +165,7 @@ def lib():
         "sl_autotune": ([vp, C.c_int, C.c_double, C.POINTER(sl_tuning)], C.c_int),
         "sl_set_mlp_mode": ([vp, C.c_int], C.c_int),
         "sl_set_ordering": ([vp, C.c_int, ip], C.c_int),
+        "sl_set_row_order": ([vp, C.c_double], C.c_int),
         "sl_set_profiling": ([vp, C.c_int], C.c_int),
         "sl_get_profile": ([vp, C.c_int, C.POINTER(C.c_int64), dp, dp], C.c_int),
         "sl_last_error": ([vp], C.c_char_p),
@@ -397,6 +398,11 @@ class System:
         g = (C.c_int * 3)(*[int(x) for x in grid])
         self._check(lib().sl_set_ordering(self.h, int(ordering), g))
 
+    def set_row_order(self, quantum):
+        """Sort each list-row segment by the neighbour displacement rounded
+        to a grid of `quantum` A (0: cell-loop order); from the next build."""
+        self._check(lib().sl_set_row_order(self.h, float(quantum)))
+
     def set_mlp_mode(self, mode):
         self._check(lib().sl_set_mlp_mode(self.h, int(mode)))
 
@@ -594,4 +600,6 @@ def system_from_workload(w, precision=SL_FP64, thermo_every=0, **kw):
                replica=w.replica, thermo_every=thermo_every, **kw)
     S.set_potential(w.pot)
     S.set_state(w.r, w.v, w.s, w.mass)
+    if getattr(w, "row_quantum", 0.0) > 0.0:
+        S.set_row_order(w.row_quantum)
     return S

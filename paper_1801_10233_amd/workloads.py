@@ -122,6 +122,9 @@ class Workload:
     skin: float
     seed: int          # Philox key for the Langevin noise
     replica: int = 0
+    # list-row order grid (A): neighbour displacements in bcc are multiples
+    # of a/2, so rounding to that grid gives every row the same slot order
+    row_quantum: float = BCC_A / 2
 
     @property
     def N(self):

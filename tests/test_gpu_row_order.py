@@ -1,0 +1,80 @@
+"""List-row order by displacement (a memory layout of the neighbour list):
+each segment of a row sorted by r_j - r_i rounded to a grid, same entries
+as the cell-loop order, and the same trajectories up to summation-order
+roundoff (oracle parity at 1e-10 over 100 steps either way)."""
+import numpy as np
+import pytest
+
+from paper_1801_10233_amd import workloads as W
+from tests.common import make_gpu, make_oracle, parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _keys(r, box, i, row, q):
+    d = r[row] - r[i]
+    d = d - box * np.rint(d / box)
+    k = np.clip(np.rint(d / q), -511, 511).astype(np.int64)
+    return [tuple(x) for x in k[:, ::-1]]          # (z, y, x)
+
+
+def test_rows_sorted_same_entries():
+    w = W.coupled_nve(n=9)
+    w.r = w.r + W.thermal_displacements(w.N, 0.2, 91)
+    q = W.BCC_A / 2
+    a = make_gpu(w)                                   # workload default: ordered
+    b = make_gpu(w)
+    b.set_row_order(0.0)
+    a.step(0, w.dt)
+    b.step(0, w.dt)
+    nsa, naa, ra = a.neighbor_list()
+    nsb, nab, rb = b.neighbor_list()
+    assert np.array_equal(nsa, nsb) and np.array_equal(naa, nab)
+    reordered = 0
+    for i in range(w.N):
+        for lo, hi in ((0, nsa[i]), (nsa[i], naa[i])):
+            assert sorted(ra[i][lo:hi]) == sorted(rb[i][lo:hi])
+            k = _keys(w.r, w.box, i, ra[i][lo:hi], q)
+            assert all(k[m] <= k[m + 1] for m in range(len(k) - 1)), (i, lo)
+            reordered += int(not np.array_equal(ra[i][lo:hi], rb[i][lo:hi]))
+    assert reordered > 0
+
+
+def test_crystal_rows_share_one_slot_order():
+    # thermal displacements well inside half a grid cell: slot k of every
+    # row holds the neighbour at the same lattice offset
+    w = W.coupled_nve(n=8)
+    w.r = w.r + W.thermal_displacements(w.N, 0.02, 5)
+    g = make_gpu(w)
+    g.step(0, w.dt)
+    ns, na, rows = g.neighbor_list()
+    assert len(set(ns.tolist())) == 1 and len(set(na.tolist())) == 1
+    q = W.BCC_A / 2
+    ref = _keys(w.r, w.box, 0, rows[0], q)
+    for i in range(1, w.N):
+        assert _keys(w.r, w.box, i, rows[i], q) == ref, i
+
+
+@pytest.mark.parametrize("quantum", [0.0, W.BCC_A / 2, W.BCC_A / 4])
+def test_row_order_keeps_parity_through_rebuilds(quantum):
+    w = W.coupled_nve(n=8)
+    w.v = w.v * 6.0                                   # several rebuilds in 100 steps
+    o = make_oracle(w)
+    g = make_gpu(w)
+    g.set_row_order(quantum)
+    o.step(100, w.dt)
+    g.step(100, w.dt)
+    p = parity(w, o, g)
+    print("row order", quantum, p, g.stats(), flush=True)
+    assert g.stats()["rebuilds"] >= 2
+    assert p["ok"], p
+
+
+def test_row_order_rejects_bad_grid():
+    from paper_1801_10233_amd import spinlat as sl
+    g = make_gpu(W.coupled_nve(n=5))
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(sl.SpinLatError) as e:
+            g.set_row_order(bad)
+        assert e.value.code == sl.SL_E_ARG
+    g.step(2, 1e-4)
