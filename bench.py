@@ -46,7 +46,7 @@ SPIN_BYTES_JC = {sl.SL_FP64: 24 + 24 + 14 * 4 + 14 * 8, sl.SL_FP32: 12 + 12 + 14
 JCACHE_BYTES = {sl.SL_FP64: 24 + 14 * 4 + 14 * 8, sl.SL_FP32: 24 + 14 * 4 + 14 * 4}
 FORCE_BYTES = {sl.SL_FP64: 24 + 24 + 58 * 4 + 48 + 8 + 24 + 24,
                sl.SL_FP32: 24 + 12 + 58 * 4 + 48 + 8 + 24 + 24}
-KIND_NAME = {sl.PROF_SPIN: "k_spin_phase", sl.PROF_FORCE: "k_force"}
+KIND_NAME = {sl.PROF_SPIN: "k_spin_phase", sl.PROF_FORCE: "k_force", sl.PROF_PAIR: "k_pair"}
 # algorithmic bytes of one whole FP64 / FP32 atom-step (four spin updates,
 # one force pass with kicks and drift), same counting as above
 STEP_BYTES = {sl.SL_FP64: 4 * SPIN_BYTES[sl.SL_FP64] + FORCE_BYTES[sl.SL_FP64],
@@ -144,7 +144,7 @@ def timed_run(S, steps, dt, profile=False):
     prof = None
     if profile:
         prof = {k: S.profile(k) for k in (sl.PROF_SPIN, sl.PROF_FORCE, sl.PROF_REBUILD,
-                                          sl.PROF_TABLE)}
+                                          sl.PROF_TABLE, sl.PROF_PAIR)}
         S.set_profiling(False)
     return t1 - t0, prof
 
@@ -350,9 +350,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--tune-steps", type=int, default=TUNE_STEPS,
                     help="steps per autotuner window")
-    ap.add_argument("--shape", metavar="SPIN,FORCE,JCACHE",
+    ap.add_argument("--shape", metavar="SPIN,FORCE,JCACHE[,OVERLAP]",
                     help="fixed launch shape for the timed FP64/FP32 run instead of autotuning "
-                         "(spin lanes, force lanes, exchange cache 1/-1)")
+                         "(spin lanes, force lanes, exchange cache 1/-1, split force 1/-1)")
     ap.add_argument("--summarize", nargs="+", metavar="CSV",
                     help="print per-kernel averages of rocprofv3 CSV files and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -380,8 +380,9 @@ def main():
     S = sl.system_from_workload(w, precision=prec, thermo_every=100)
     S.step(0, w.dt)                     # first list build and colouring
     if args.shape:
-        sp, fo, jc = (int(x) for x in args.shape.split(","))
-        S.set_tuning(sp, fo, 0, jc)
+        vals = [int(x) for x in args.shape.split(",")]
+        sp, fo, jc = vals[:3]
+        S.set_tuning(sp, fo, 0, jc, vals[3] if len(vals) > 3 else 0)
         tuned = S.tuning()
     else:
         tuned = None if args.no_tune else S.autotune(args.tune_steps, w.dt)
@@ -400,8 +401,8 @@ def main():
     st = S.stats()
 
     # dominant kernel = largest summed event time in the timed region
-    kinds = {k: v for k, v in prof.items() if k in KIND_NAME}
-    dom = max(kinds, key=lambda k: kinds[k][1])
+    kinds = {k: v for k, v in prof.items() if k in KIND_NAME and v[0] > 0}
+    dom = max((k for k in kinds if k in (sl.PROF_SPIN, sl.PROF_FORCE)), key=lambda k: kinds[k][1])
     launches, ms, work = kinds[dom]
     tun = S.tuning()
     jc_on = tun["jcache"] > 0

@@ -290,6 +290,12 @@ typedef struct {
                          read by the spin phases; 0 = default (on for the
                          FP32 form, off for FP64, as measured on MI355X),
                          1 on, -1 off */
+    int overlap;      /* split force (analytic potentials, 1 or 2 force
+                         lanes): the spin-independent pair terms of a step's
+                         closing force run on a second stream of the library
+                         while the spins update, and the closing force launch
+                         adds the spin-dependent terms; 0 = default (off),
+                         1 on, -1 off. Not changed by the autotuner. */
 } sl_tuning;
 
 int sl_set_tuning(sl_system *sys, const sl_tuning *t);
@@ -320,7 +326,8 @@ int sl_autotune(sl_system *sys, int steps, double dt, sl_tuning *chosen);
  * and the summed event time in ms since profiling was last switched on
  * (switching it off keeps the totals readable). Kinds: 0 spin phase,
  * 1 force, 2 neighbour rebuild, 3 pair-coefficient table (exchange cache
- * or per-pair learned potential). */
+ * or per-pair learned potential), 4 pair pass of the split force (its
+ * events are on the library's second stream). */
 int sl_set_profiling(sl_system *sys, int on);
 int sl_get_profile(sl_system *sys, int kind, int64_t *launches, double *ms,
                    double *work_items);

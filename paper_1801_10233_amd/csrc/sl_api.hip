@@ -85,6 +85,7 @@ struct sl_system {
   int *jplist[2] = {nullptr, nullptr};  // ready lists of the colouring rounds
   unsigned long long *jpmask[2] = {nullptr, nullptr};  // conflict / earlier-key slot masks
   unsigned long long *dslot = nullptr;
+  double *pred = nullptr;  // [force blocks][3] predictor terms of one launch
   unsigned int *done = nullptr;
   double *partial = nullptr, *red_out = nullptr;
   double *thermo = nullptr;
@@ -118,6 +119,11 @@ struct sl_system {
   // spin ordering: colour classes, or the paper's sectors / serial order
   int ordering = SL_ORDER_COLOUR;
   double row_q = 0.0;  // list row order: 0 cell loop, > 0 displacement grid (A)
+  // split force (tuning): the pair pass runs on st2 while the spins update
+  int overlap = -1;
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  double *fp = nullptr;  // [4][ld] pair force and pair energy
   int sgrid[3] = {1, 1, 1};
   unsigned long long *skeys[2] = {nullptr, nullptr};
   int *svals[2] = {nullptr, nullptr};
@@ -134,9 +140,9 @@ struct sl_system {
   bool prof_now = false;  // the current step is timed
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
-  int64_t prof_launch[4] = {0, 0, 0, 0};
-  double prof_ms[4] = {0, 0, 0, 0};
-  double prof_work[4] = {0, 0, 0, 0};
+  int64_t prof_launch[5] = {0, 0, 0, 0, 0};
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  double prof_work[5] = {0, 0, 0, 0, 0};
 
   std::string last_err;
 };
@@ -317,16 +323,18 @@ struct ProfScope {
   int kind;
   double work;
   hipEvent_t a = nullptr;
-  ProfScope(sl_system *S_, int kind_, double work_) : S(S_), kind(kind_), work(work_) {
+  hipStream_t st;
+  ProfScope(sl_system *S_, int kind_, double work_, hipStream_t st_ = nullptr)
+      : S(S_), kind(kind_), work(work_), st(st_ ? st_ : S_->st) {
     if (S->prof_now) {
       a = get_event(S);
-      (void)hipEventRecord(a, S->st);
+      (void)hipEventRecord(a, st);
     }
   }
   ~ProfScope() {
     if (a) {
       hipEvent_t b = get_event(S);
-      (void)hipEventRecord(b, S->st);
+      (void)hipEventRecord(b, st);
       S->prof_recs.push_back({kind, a, b, work});
     }
   }
@@ -937,8 +945,11 @@ void half_step_updates(const sl_system *S, int64_t step, int sub_fwd, std::vecto
   for (int c = S->K - 1; c >= 0; --c) u.push_back({c, step, sub_fwd + 1});
 }
 
+// With split set, the pair pass of this boundary (pair_launch) has filled
+// S->fp and the launch is the spin pass.
 template <typename real>
-int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary) {
+int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary,
+                 bool split = false) {
   Atoms &A = S->a[S->cur];
   ForceArgs F;
   std::memset(&F, 0, sizeof(F));
@@ -958,12 +969,14 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   F.partial = S->partial;
   F.dslot = S->dslot;
   F.done = S->done;
+  F.pred = S->pred;
   F.err = S->err;
   F.wmask = A.wmask;
   F.frozen = S->prm.frozen;
   F.seed = S->prm.seed;
   F.replica = S->prm.replica;
   F.step = boundary;
+  F.fp = split ? S->fp : nullptr;
   CHK(ensure_table(S, posbuf));
   if (mode & kModeNext) S->tab_ok[1 - posbuf] = S->jc_ok[1 - posbuf] = false;
   const int slot = (int)(boundary & 3);
@@ -977,11 +990,44 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   {
     ProfScope ps(S, 1, (double)S->n);
     const SysView<real> v = view<real>(S, posbuf);
-    launch_eam_density<real>(v, S->pc, S->st);
-    launch_force<real>(v, S->pc, F, S->force_lanes, S->st);
+    if (split) {
+      launch_force_spin<real>(v, S->pc, F, S->force_lanes, S->st);
+    } else {
+      launch_eam_density<real>(v, S->pc, S->st);
+      launch_force<real>(v, S->pc, F, S->force_lanes, S->st);
+    }
   }
+  if (mode & (kModeFinal | kModeNext))
+    launch_pred_reduce(S->pred, force_blocks(S->n, S->force_lanes), S->err, F.host_out, S->st);
   if (mode & (kModeFinal | kModeNext)) HIPCHK(S, hipEventRecord(S->ev[slot], S->st));
   return SL_OK;
+}
+
+// Split force: whether this system takes it, the second stream, its two
+// events and the pair buffer (made on first use), and the pair pass of a
+// boundary on the second stream (the embedded-atom density pass first).
+bool split_ok(const sl_system *S) {
+  return S->overlap > 0 && !S->mlp && (S->force_lanes == 1 || S->force_lanes == 2);
+}
+
+int ensure_split(sl_system *S) {
+  if (!S->st2) HIPCHK(S, hipStreamCreateWithFlags(&S->st2, hipStreamNonBlocking));
+  if (!S->ev_fork) HIPCHK(S, hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
+  if (!S->ev_join) HIPCHK(S, hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
+  if (!S->fp) HIPCHK(S, dalloc(&S->fp, (size_t)4 * S->ld));
+  return SL_OK;
+}
+
+template <typename real>
+void pair_launch(sl_system *S, int posbuf, bool energy) {
+  ForceArgs F;
+  std::memset(&F, 0, sizeof(F));
+  F.fp = S->fp;
+  F.err = S->err;
+  ProfScope ps(S, 4, (double)S->n, S->st2);
+  const SysView<real> v = view<real>(S, posbuf);
+  launch_eam_density<real>(v, S->pc, S->st2);
+  launch_pair<real>(v, S->pc, F, S->force_lanes, energy, S->st2);
 }
 
 int record_thermo(sl_system *S, int64_t boundary) {
@@ -1094,6 +1140,22 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
       }
     }
     S->prof_now = S->prof && (k % S->prof_every == 0);
+    const int64_t b = k + 1;
+    int mode = kModeFinal;
+    if (k + 1 < k0 + n) mode |= kModeNext;
+    const bool sample = te > 0 && b % te == 0;
+    if (sample) mode |= kModeEnergy;
+    // split force: the pair pass of boundary b needs only the positions of
+    // b (already drifted into the other buffer), so it runs on the second
+    // stream while the spins of this step update
+    const bool split = split_ok(S);
+    if (split) {
+      CHK(ensure_split(S));
+      HIPCHK(S, hipEventRecord(S->ev_fork, S->st));
+      HIPCHK(S, hipStreamWaitEvent(S->st2, S->ev_fork, 0));
+      pair_launch<real>(S, 1 - S->pos, sample);
+      HIPCHK(S, hipEventRecord(S->ev_join, S->st2));
+    }
     if (S->ordering != SL_ORDER_COLOUR) {
       // classes from the positions at the start of the step
       CHK(sect_prepare(S, S->pos));
@@ -1124,12 +1186,8 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
         run_updates<real>(S, 1 - S->pos, w, h);
       }
     }
-    const int64_t b = k + 1;
-    int mode = kModeFinal;
-    if (k + 1 < k0 + n) mode |= kModeNext;
-    const bool sample = te > 0 && b % te == 0;
-    if (sample) mode |= kModeEnergy;
-    CHK(force_launch<real>(S, 1 - S->pos, mode, dt, b));
+    if (split) HIPCHK(S, hipStreamWaitEvent(S->st, S->ev_join, 0));
+    CHK(force_launch<real>(S, 1 - S->pos, mode, dt, b, split));
     if (sample) CHK(record_thermo(S, b));
     S->pos = 1 - S->pos;
     S->step = b;
@@ -1221,6 +1279,7 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(dalloc(&S->dslot, 3));
   A_(dalloc(&S->done, 1));
   A_(dalloc(&S->partial, (size_t)nb * 8));
+  A_(dalloc(&S->pred, (size_t)nb * 3));
   A_(dalloc(&S->red_out, 8));
   A_(dalloc(&S->thermo, (size_t)kThermoCap * 8));
   A_(hipHostMalloc((void **)&S->ring, 32 * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
@@ -1249,6 +1308,7 @@ int sl_create(const sl_params *p, sl_system **out) {
 int sl_destroy(sl_system *S) {
   if (!S) return SL_OK;
   if (S->st) (void)hipStreamSynchronize(S->st);
+  if (S->st2) (void)hipStreamSynchronize(S->st2);
   for (auto &r : S->prof_recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -1265,12 +1325,16 @@ int sl_destroy(sl_system *S) {
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
                   (void *)S->jplist[0], (void *)S->jplist[1], (void *)S->jpmask[0],
                   (void *)S->jpmask[1],
-                  (void *)S->done, (void *)S->partial, (void *)S->red_out, (void *)S->thermo,
+                  (void *)S->done, (void *)S->partial, (void *)S->pred, (void *)S->red_out, (void *)S->thermo,
                   (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
                   (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1], (void *)S->eam,
                   (void *)S->skeys[0], (void *)S->skeys[1], (void *)S->svals[0],
-                  (void *)S->svals[1], (void *)S->scount, (void *)S->soff, S->cub_tmp})
+                  (void *)S->svals[1], (void *)S->scount, (void *)S->soff, S->cub_tmp,
+                  (void *)S->fp})
     dfree(p);
+  if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+  if (S->ev_join) (void)hipEventDestroy(S->ev_join);
+  if (S->st2) (void)hipStreamDestroy(S->st2);
   if (S->ring) (void)hipHostFree(S->ring);
   if (S->own_stream && S->st) (void)hipStreamDestroy(S->st);
   delete S;
@@ -1713,11 +1777,13 @@ int sl_set_tuning(sl_system *S, const sl_tuning *t) {
   if (!ok(t->spin_lanes) || !ok(t->force_lanes)) return fail(S, SL_E_ARG, "lanes must be 1, 2, 4 or 8");
   if (t->small_class < -1) return fail(S, SL_E_ARG, "small_class must be >= -1");
   if (t->jcache < -1 || t->jcache > 1) return fail(S, SL_E_ARG, "jcache must be -1, 0 or 1");
+  if (t->overlap < -1 || t->overlap > 1) return fail(S, SL_E_ARG, "overlap must be -1, 0 or 1");
   CHK(sl_synchronize(S));
   S->spin_lanes = t->spin_lanes ? t->spin_lanes : 2;
   S->force_lanes = t->force_lanes ? t->force_lanes : 1;
   S->small_class = t->small_class == 0 ? 512 : t->small_class;
   S->jcache = t->jcache == 0 ? (S->prec == SL_FP32 ? 1 : -1) : t->jcache;
+  S->overlap = t->overlap == 0 ? -1 : t->overlap;
   return SL_OK;
 }
 
@@ -1727,6 +1793,7 @@ int sl_get_tuning(sl_system *S, sl_tuning *t) {
   t->force_lanes = S->force_lanes;
   t->small_class = S->small_class;
   t->jcache = S->jcache;
+  t->overlap = S->overlap;
   return SL_OK;
 }
 
@@ -1735,7 +1802,7 @@ int sl_set_profiling(sl_system *S, int on) {
   if (S->prof && !on) prof_collect(S);  // totals stay readable after stopping
   if (on < 0) return fail(S, SL_E_ARG, "profiling period must be >= 0");
   if (on && !S->prof)
-    for (int k = 0; k < 4; ++k) {        // a new measurement starts from zero
+    for (int k = 0; k < 5; ++k) {        // a new measurement starts from zero
       S->prof_launch[k] = 0;
       S->prof_ms[k] = 0.0;
       S->prof_work[k] = 0.0;
@@ -1747,7 +1814,7 @@ int sl_set_profiling(sl_system *S, int on) {
 }
 
 int sl_get_profile(sl_system *S, int kind, int64_t *launches, double *ms, double *work_items) {
-  if (!S || kind < 0 || kind > 3) return fail(S, SL_E_ARG, "bad argument");
+  if (!S || kind < 0 || kind > 4) return fail(S, SL_E_ARG, "bad argument");
   prof_collect(S);
   if (launches) *launches = S->prof_launch[kind];
   if (ms) *ms = S->prof_ms[kind];
@@ -2230,7 +2297,7 @@ int sl_autotune(sl_system *S, int steps, double dt, sl_tuning *chosen) {
     for (int pass = 0; pass < 4 && rc == SL_OK; ++pass)
       for (int q = 0; q < 8 && rc == SL_OK; ++q) {
         const int t = (q + 3 * pass) % 8;
-        sl_tuning tt{trial[t][0], trial[t][1], S->small_class, trial[t][2]};
+        sl_tuning tt{trial[t][0], trial[t][1], S->small_class, trial[t][2], S->overlap};
         if ((rc = sl_set_tuning(C, &tt))) break;
         if ((rc = sl_step(C, 3, dt))) break;
         for (int attempt = 0; attempt < 3 && rc == SL_OK; ++attempt) {
@@ -2262,7 +2329,7 @@ int sl_autotune(sl_system *S, int steps, double dt, sl_tuning *chosen) {
     v[3] = trial[bt][2];
     cache_store(key, v);
   }
-  sl_tuning t{v[0], v[1], v[2], v[3]};
+  sl_tuning t{v[0], v[1], v[2], v[3], S->overlap};
   CHK(sl_set_tuning(S, &t));
   if (chosen) *chosen = t;
   return SL_OK;

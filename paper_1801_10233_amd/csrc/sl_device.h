@@ -203,6 +203,11 @@ struct ForceArgs {
   uint64_t seed;              // Philox seed and replica of the lattice noise
   uint32_t replica;
   int64_t step;               // step whose drift this launch computes
+  double *pred;               // [blocks][3] per-block rebuild predictor terms:
+                              // max |r - r_build|, max |v|, min watched r^2
+  double *fp;                 // [4][ld] split force: pair force x, y, z and the
+                              // pair energy of each atom, written by the pair
+                              // pass and added by the spin pass
 };
 
 enum : int { kModeFinal = 1, kModeNext = 2, kModeEnergy = 4 };

@@ -3,7 +3,9 @@
 //   * k_force:       pair + magneto-mechanical force (Eq. p_advance), fused
 //                    with the velocity-Verlet half kicks and the drift into
 //                    the other position buffer, energies on sampled steps
-//                    and the rebuild predictor.
+//                    and the per-block terms of the rebuild predictor;
+//   * k_pred_reduce: one block joining those terms and handing them to the
+//                    host.
 #include "sl_step.h"
 
 namespace sl {
@@ -28,7 +30,6 @@ template <typename real, int MODE, int LANES, int MLP>
 __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
   __shared__ double red[kBlock / 64][8];
   __shared__ double redm[kBlock / 64][3];
-  __shared__ int last;
   // Tiles are taken from the end of the atom order first: the last colour
   // classes may hold a few atoms scattered over the whole box (repairs),
   // whose gathers miss the caches; starting them first hides their latency
@@ -61,7 +62,10 @@ __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, 
         A.partial[(size_t)tile * 8 + c] = x;
       }
     }
-    last = 0;
+    // Predictor terms go out as plain per-block stores; k_pred_reduce joins
+    // them. (Device-scope atomics on three shared words, plus a completion
+    // counter, cost ~50 us per launch at 1688 blocks: they serialise across
+    // the XCDs.)
     if (MODE & (kModeFinal | kModeNext)) {
       double a = 0.0, b = 0.0, c = kInf;
       for (int w = 0; w < kBlock / 64; ++w) {
@@ -69,29 +73,49 @@ __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, 
         b = fmax(b, redm[w][1]);
         c = fmin(c, redm[w][2]);
       }
-      // non-negative doubles order like their bit patterns
-      atomicMax(&A.dslot[0], (unsigned long long)__double_as_longlong(a));
-      atomicMax(&A.dslot[1], (unsigned long long)__double_as_longlong(b));
-      atomicMin(&A.dslot[2], (unsigned long long)__double_as_longlong(c));
-      __threadfence();
-      const unsigned prev = atomicAdd(A.done, 1u);
-      last = (prev == gridDim.x - 1);
+      A.pred[(size_t)tile * 3 + 0] = a;
+      A.pred[(size_t)tile * 3 + 1] = b;
+      A.pred[(size_t)tile * 3 + 2] = c;
     }
   }
-  __syncthreads();
-  if ((MODE & (kModeFinal | kModeNext)) && last && threadIdx.x == 0) {
-    __threadfence();
-    const unsigned long long a = atomicExch(&A.dslot[0], 0ull);
-    const unsigned long long b = atomicExch(&A.dslot[1], 0ull);
-    const unsigned long long c = atomicExch(&A.dslot[2], (unsigned long long)__double_as_longlong(kInf));
-    atomicExch(A.done, 0u);
-    const int err = atomicOr(A.err, 0);
-    A.host_out[0] = __longlong_as_double((long long)a);
-    A.host_out[1] = __longlong_as_double((long long)b);
-    A.host_out[2] = (double)err;
-    A.host_out[4] = __longlong_as_double((long long)c);
-    A.host_out[3] = 1.0;  // written marker
+}
+
+// Joins the per-block predictor terms of one force launch (max, max, min:
+// exact in any order) and writes them, with the sticky error word, to the
+// pinned host slot; the written marker goes last.
+__global__ __launch_bounds__(kBlock) void k_pred_reduce(const double *pred, int nb, int *err,
+                                                        double *host_out) {
+  __shared__ double s[3][kBlock / 64];
+  double a = 0.0, b = 0.0, c = kInf;
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    a = fmax(a, pred[(size_t)k * 3 + 0]);
+    b = fmax(b, pred[(size_t)k * 3 + 1]);
+    c = fmin(c, pred[(size_t)k * 3 + 2]);
   }
+  a = wave_max(a);
+  b = wave_max(b);
+  c = wave_min(c);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { s[0][wv] = a; s[1][wv] = b; s[2][wv] = c; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      a = fmax(a, s[0][w]);
+      b = fmax(b, s[1][w]);
+      c = fmin(c, s[2][w]);
+    }
+    const int e = atomicOr(err, 0);
+    host_out[0] = a;
+    host_out[1] = b;
+    host_out[2] = (double)e;
+    host_out[4] = c;
+    __threadfence_system();
+    host_out[3] = 1.0;  // written marker
+  }
+}
+
+void launch_pred_reduce(const double *pred, int nb, int *err, double *host_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pred_reduce, dim3(1), dim3(kBlock), 0, st, pred, nb, err, host_out);
 }
 
 
@@ -120,6 +144,65 @@ static void force_lanes(const SysView<real> &S, const PotConst &P, const ForceAr
   else if (sizeof(real) == 4 && S.tab) force_lanes2<real, LANES, (sizeof(real) == 4 ? 1 : 0)>(S, P, A, st);
   else force_lanes2<real, LANES, 0>(S, P, A, st);
 }
+
+// Pair pass of the split force: the spin-independent terms of every atom
+// into A.fp (MODE is 0 or kModeEnergy: with it the pair energy is stored
+// too). No reductions, kicks or predictor: the spin pass does those.
+template <typename real, int MODE, int LANES, int MLP>
+__global__ __launch_bounds__(kBlock, kForceWaves) void k_pair(SysView<real> S, PotConst P, ForceArgs A) {
+  const int tile = gridDim.x - 1 - xcd_tile(blockIdx.x, gridDim.x);
+  const int t = tile * kBlock + threadIdx.x;
+  const int l = t & (LANES - 1);
+  const int i = t / LANES;
+  double e[8];
+  double dm = 0.0, vm = 0.0, wm = kInf;
+  force_atom<real, MODE, LANES, MLP | 16>(S, P, A, i, i < S.n, l, e, dm, vm, wm);
+}
+
+template <typename real, int LANES, int MLP>
+static void pair_lanes2(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
+                        bool energy, hipStream_t st) {
+  const int nb = (int)(((long)S.n * LANES + kBlock - 1) / kBlock);
+  if (energy)
+    hipLaunchKernelGGL((k_pair<real, kModeEnergy, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+  else
+    hipLaunchKernelGGL((k_pair<real, 0, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A);
+}
+
+template <typename real>
+void launch_pair(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
+                 bool energy, hipStream_t st) {
+  if (S.n <= 0) return;
+  if (lanes == 2) {
+    if (P.eam_on) pair_lanes2<real, 2, 8>(S, P, A, energy, st);
+    else pair_lanes2<real, 2, 0>(S, P, A, energy, st);
+  } else {
+    if (P.eam_on) pair_lanes2<real, 1, 8>(S, P, A, energy, st);
+    else pair_lanes2<real, 1, 0>(S, P, A, energy, st);
+  }
+}
+template void launch_pair<double>(const SysView<double> &, const PotConst &, const ForceArgs &, int,
+                                  bool, hipStream_t);
+template void launch_pair<float>(const SysView<float> &, const PotConst &, const ForceArgs &, int,
+                                 bool, hipStream_t);
+
+// Spin pass of the split force (the pair pass must have filled A.fp).
+template <typename real>
+void launch_force_spin(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
+                       hipStream_t st) {
+  if (S.n <= 0) return;
+  if (lanes == 2) {
+    if (P.soc_on) force_lanes2<real, 2, 4 | 32>(S, P, A, st);
+    else force_lanes2<real, 2, 32>(S, P, A, st);
+  } else {
+    if (P.soc_on) force_lanes2<real, 1, 4 | 32>(S, P, A, st);
+    else force_lanes2<real, 1, 32>(S, P, A, st);
+  }
+}
+template void launch_force_spin<double>(const SysView<double> &, const PotConst &,
+                                        const ForceArgs &, int, hipStream_t);
+template void launch_force_spin<float>(const SysView<float> &, const PotConst &, const ForceArgs &,
+                                       int, hipStream_t);
 
 // Blocks needed by a force launch (rows of the partial-sum buffer).
 int force_blocks(int n, int lanes) { return (int)(((long)n * lanes + kBlock - 1) / kBlock); }

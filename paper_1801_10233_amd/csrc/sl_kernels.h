@@ -18,7 +18,20 @@ void launch_spin_tail(const SysView<real> &S, const PotConst &P, const TailArgs 
 template <typename real>
 void launch_force(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
                   hipStream_t st);
+// Split force of the analytic forms (1 or 2 lanes per atom): the pair pass
+// stores the spin-independent force (and, with energy, the pair energy) of
+// every atom in A.fp; the spin pass adds the spin-dependent terms of the
+// spin segment to it and does what the fused launch does after the gather.
+template <typename real>
+void launch_pair(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
+                 bool energy, hipStream_t st);
+template <typename real>
+void launch_force_spin(const SysView<real> &S, const PotConst &P, const ForceArgs &A, int lanes,
+                       hipStream_t st);
 int force_blocks(int n, int lanes);
+// Joins the per-block rebuild predictor terms (pred[nb][3]) of a force launch
+// into the pinned host slot host_out, with the error word and the marker.
+void launch_pred_reduce(const double *pred, int nb, int *err, double *host_out, hipStream_t st);
 template <typename real>
 void launch_batch_run(RepDesc<real> *D, int R, int lanes, int variant, hipStream_t st);
 // Embedded-atom first pass (F'(rho), F(rho) of every atom) at the positions

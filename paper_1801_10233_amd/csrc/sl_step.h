@@ -258,12 +258,23 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
 // 1 learned per-pair table, 2 learned spline, 4 analytic with the spin-orbit
 // pair terms); MLP & 8 adds the embedded-atom terms, whose F'(rho) of every
 // atom a first pass (k_eam_density) has stored.
+// Split force (analytic forms only): MLP & 16 is the pair pass, which sums
+// the spin-independent terms (Morse, embedded atom) over the whole row and
+// stores them in A.fp, and does nothing else; it depends on the positions
+// alone, so it can run while the spins are still being updated. MLP & 32 is
+// the spin pass: the spin-dependent terms over the spin segment only, plus
+// the stored pair part, then the kicks, drift, energies and predictor as in
+// the fused form.
 template <typename real, int MODE, int LANES, int MLP>
 __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotConst &P,
                                            const ForceArgs &A, int i, bool valid, int l,
                                            double e[8], double &dm, double &vm, double &wm) {
   constexpr int kV = MLP & 7;
   constexpr bool kEam = (MLP & 8) != 0;
+  constexpr bool kPairPass = (MLP & 16) != 0, kSpinPass = (MLP & 32) != 0;
+  static_assert(!(kPairPass || kSpinPass) || kV == 0 || kV == 4,
+                "the split force covers the analytic forms only");
+  static_assert(!(kPairPass && kSpinPass), "one pass at a time");
   real fx = 0, fy = 0, fz = 0;
   real ep = 0, ee = 0;
   double rix = 0, riy = 0, riz = 0;
@@ -274,12 +285,12 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
     const int ns = S.nspin[i], na = S.nall[i];
     const int ld = S.ld;
     // the variant may serve replicas without the embedded-atom terms
-    const bool eam = kEam && P.eam_on;
+    const bool eam = kEam && !kSpinPass && P.eam_on;
     const real fpi = eam ? (real)S.eam[i] : (real)0;
     if (eam && (MODE & kModeEnergy) && l == 0) ep += (real)S.eam[ld + i];
     // spin-segment slots holding a pair of one colour class are watched
     const unsigned long long wmk =
-        ((MODE & (kModeFinal | kModeNext)) && A.wmask) ? A.wmask[i] : 0ull;
+        (!kPairPass && (MODE & (kModeFinal | kModeNext)) && A.wmask) ? A.wmask[i] : 0ull;
     // Two segments of the row, each gathered in chunks (all loads of a
     // chunk in flight together): the spin segment [0, ns) needs positions
     // and spins, the rest [ns, na) lies beyond the exchange cutoff (its
@@ -289,6 +300,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
     // neighbour spins, and schedules all of a chunk's loads together)
 #pragma unroll
     for (int seg = 0; seg < 2; ++seg) {
+      if (kSpinPass && seg == 1) continue;
       const int beg = seg == 0 ? 0 : ns, end = seg == 0 ? ns : na;
       for (int base = beg + l; base < end; base += LANES * kForceChunk) {
         int jj[kForceChunk];
@@ -306,11 +318,11 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
         for (int c = 0; c < kForceChunk; ++c) {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
           if (kEam) fpj[c] = eam ? (real)S.eam[jj[c]] : (real)0;
-          if (seg == 0) { qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]]; }
+          if (seg == 0 && !kPairPass) { qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]]; }
         }
 #pragma unroll
         for (int c = 0; c < kForceChunk; ++c)
-          sij[c] = seg == 0 ? six * qx[c] + siy * qy[c] + siz * qz[c] : (real)0;
+          sij[c] = (seg == 0 && !kPairPass) ? six * qx[c] + siy * qy[c] + siz * qz[c] : (real)0;
         if (kV == 1) {
 #pragma unroll
           for (int c = 0; c < kForceChunk; ++c) {
@@ -325,7 +337,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           const double dyd = min_image(riy - py[c], S.L[1], S.invL[1]);
           const double dzd = min_image(riz - pz[c], S.L[2], S.invL[2]);
           const double r2d = use ? dxd * dxd + dyd * dyd + dzd * dzd : 1.0;
-          if (seg == 0 && use && ((wmk >> (base + LANES * c)) & 1ull)) wm = fmin(wm, r2d);
+          if (!kPairPass && seg == 0 && use && ((wmk >> (base + LANES * c)) & 1ull)) wm = fmin(wm, r2d);
           const real dx = (real)dxd, dy = (real)dyd, dz = (real)dzd;
           const double rinvd = rsqrt_nr(r2d);
           const real r = (real)(r2d * rinvd), rinv = (real)rinvd;
@@ -339,7 +351,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
               ee -= (real)0.5 * (real)tt[c].x * sij[c];
             }
           } else {
-            if (P.morse_on && r2d < P.mRc2) {
+            if (!kSpinPass && P.morse_on && r2d < P.mRc2) {
               const real ex = exp(-(real)P.mA * (r - (real)P.mR0));
               const real dM = -(real)2 * (real)P.mA * (real)P.mD * (ex * ex - ex);
               cc -= dM - (real)P.mdMc;
@@ -348,7 +360,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
                                          (r - (real)P.mRc) * (real)P.mdMc)
                           : (real)0;
             }
-            if (seg == 0 && P.ex_on && r2d < P.eRc2) {
+            if (!kPairPass && seg == 0 && P.ex_on && r2d < P.eRc2) {
               const real u = (real)(r2d * P.eInvD2);
               const real eu = exp(-u);
               const real dJ = (real)P.eA8InvD2 * r * eu *
@@ -376,7 +388,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           fx += cr * dx;
           fy += cr * dy;
           fz += cr * dz;
-          if (kV == 4 && seg == 0 && use) {
+          if (kV == 4 && !kPairPass && seg == 0 && use) {
             const real es = soc_force<real>(P, dxd, dyd, dzd, r2d, six, siy, siz, qx[c], qy[c],
                                             qz[c], fx, fy, fz);
             if (MODE & kModeEnergy) ee += (real)0.5 * es;
@@ -394,6 +406,23 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
       ep += __shfl_xor(ep, o, 64);
       ee += __shfl_xor(ee, o, 64);
     }
+  }
+  if (kPairPass) {
+    if (valid && l == 0) {
+      const int ld = S.ld;
+      A.fp[i] = (double)fx;
+      A.fp[ld + i] = (double)fy;
+      A.fp[2 * ld + i] = (double)fz;
+      if (MODE & kModeEnergy) A.fp[3 * ld + i] = (double)ep;
+    }
+    return;
+  }
+  if (kSpinPass && valid && l == 0) {
+    const int ld = S.ld;
+    fx += (real)A.fp[i];
+    fy += (real)A.fp[ld + i];
+    fz += (real)A.fp[2 * ld + i];
+    if (MODE & kModeEnergy) ep += (real)A.fp[3 * ld + i];
   }
   if (valid && l == 0) {
     if (!isfinite((double)fx) || !isfinite((double)fy) || !isfinite((double)fz))

@@ -34,7 +34,7 @@ SL_BATCH_PERSISTENT = 0
 SL_BATCH_PHASED = 1
 SL_ORDER_COLOUR, SL_ORDER_SECTORS, SL_ORDER_SERIAL = 0, 1, 2
 
-PROF_SPIN, PROF_FORCE, PROF_REBUILD, PROF_TABLE = 0, 1, 2, 3  # kernel kinds of sl_get_profile
+PROF_SPIN, PROF_FORCE, PROF_REBUILD, PROF_TABLE, PROF_PAIR = 0, 1, 2, 3, 4  # kinds of sl_get_profile
 PROF_REDUCE = PROF_TABLE
 
 # Every function the header declares (checked by the tests).
@@ -96,7 +96,7 @@ class sl_stats(C.Structure):
 
 class sl_tuning(C.Structure):
     _fields_ = [("spin_lanes", C.c_int), ("force_lanes", C.c_int), ("small_class", C.c_int),
-                ("jcache", C.c_int)]
+                ("jcache", C.c_int), ("overlap", C.c_int)]
 
 
 class sl_mlp_spec(C.Structure):
@@ -375,22 +375,23 @@ class System:
     def synchronize(self):
         self._check(lib().sl_synchronize(self.h))
 
-    def set_tuning(self, spin_lanes=0, force_lanes=0, small_class=0, jcache=0):
-        t = sl_tuning(int(spin_lanes), int(force_lanes), int(small_class), int(jcache))
+    def set_tuning(self, spin_lanes=0, force_lanes=0, small_class=0, jcache=0, overlap=0):
+        t = sl_tuning(int(spin_lanes), int(force_lanes), int(small_class), int(jcache),
+                      int(overlap))
         self._check(lib().sl_set_tuning(self.h, C.byref(t)))
 
     def tuning(self):
         t = sl_tuning()
         self._check(lib().sl_get_tuning(self.h, C.byref(t)))
         return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
-                    small_class=t.small_class, jcache=t.jcache)
+                    small_class=t.small_class, jcache=t.jcache, overlap=t.overlap)
 
     def autotune(self, steps, dt):
         """Time launch shapes on a scratch copy and keep the fastest."""
         t = sl_tuning()
         self._check(lib().sl_autotune(self.h, int(steps), float(dt), C.byref(t)))
         return dict(spin_lanes=t.spin_lanes, force_lanes=t.force_lanes,
-                    small_class=t.small_class, jcache=t.jcache)
+                    small_class=t.small_class, jcache=t.jcache, overlap=t.overlap)
 
     def set_ordering(self, ordering, grid=(1, 1, 1)):
         """SL_ORDER_COLOUR, SL_ORDER_SECTORS (with the subdomain grid) or

@@ -81,7 +81,7 @@ def test_launch_shapes_keep_parity(spin_lanes, force_lanes, small, jcache):
     g = make_gpu(w)
     g.set_tuning(spin_lanes, force_lanes, small, jcache)
     assert g.tuning() == dict(spin_lanes=spin_lanes, force_lanes=force_lanes, small_class=small,
-                              jcache=jcache)
+                              jcache=jcache, overlap=-1)
     o.step(50, w.dt)
     g.step(50, w.dt)
     p = parity(w, o, g)
