@@ -2424,6 +2424,7 @@ int fill_desc(sl_batch *B, int r, double dt, int64_t target, RepDesc<real> &d) {
   d.F.wmask = A.wmask;
   d.F.dslot = S->dslot;
   d.F.done = S->done;
+  d.F.pred = S->pred;
   d.F.seed = S->prm.seed;
   d.F.replica = S->prm.replica;
   if (S->K > kMaxClass) return bfail(B, SL_E_COLOR, "replica " + std::to_string(r) + " has too many colours");

@@ -177,7 +177,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_spin(const RepDesc<real> *D, B
 template <typename real, int MODE, int LANES, int MLP>
 __global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, BatchPhase bp) {
   __shared__ double redm[kBlock / 64][3];
-  __shared__ int last;
   const RepDesc<real> &d = D[blockIdx.y];
   const int n = d.V[0].n;
   const int per = kBlock / LANES;
@@ -207,25 +206,49 @@ __global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, 
       y = fmax(y, redm[w][1]);
       z = fmin(z, redm[w][2]);
     }
-    atomicMax(&F.dslot[0], (unsigned long long)__double_as_longlong(x));
-    atomicMax(&F.dslot[1], (unsigned long long)__double_as_longlong(y));
-    atomicMin(&F.dslot[2], (unsigned long long)__double_as_longlong(z));
-    __threadfence();
-    last = (atomicAdd(F.done, 1u) == (unsigned)nb - 1);
+    // per-block terms as plain stores, joined per replica by k_batch_pred_reduce
+    F.pred[(size_t)blockIdx.x * 3 + 0] = x;
+    F.pred[(size_t)blockIdx.x * 3 + 1] = y;
+    F.pred[(size_t)blockIdx.x * 3 + 2] = z;
   }
+}
+
+// One block per replica: joins the per-block predictor terms of the force
+// pass with the same BatchPhase into the replica's pinned slot (error word,
+// then the written marker last).
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_batch_pred_reduce(const RepDesc<real> *D, BatchPhase bp,
+                                                              int per) {
+  __shared__ double s[3][kBlock / 64];
+  const RepDesc<real> &d = D[blockIdx.x];
+  const int nb = (d.V[0].n + per - 1) / per;
+  const int64_t boundary = d.step + bp.kk + bp.after;
+  double *host_out = d.ring + 8 * (int)(boundary & 3);
+  double a = 0.0, b = 0.0, c = kInf;
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    a = fmax(a, d.F.pred[(size_t)k * 3 + 0]);
+    b = fmax(b, d.F.pred[(size_t)k * 3 + 1]);
+    c = fmin(c, d.F.pred[(size_t)k * 3 + 2]);
+  }
+  a = wave_max(a);
+  b = wave_max(b);
+  c = wave_min(c);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { s[0][wv] = a; s[1][wv] = b; s[2][wv] = c; }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    const unsigned long long x = atomicExch(&F.dslot[0], 0ull);
-    const unsigned long long y = atomicExch(&F.dslot[1], 0ull);
-    const unsigned long long z = atomicExch(&F.dslot[2], (unsigned long long)__double_as_longlong(kInf));
-    atomicExch(F.done, 0u);
-    const int err = atomicOr(F.err, 0);
-    F.host_out[0] = __longlong_as_double((long long)x);
-    F.host_out[1] = __longlong_as_double((long long)y);
-    F.host_out[2] = (double)err;
-    F.host_out[4] = __longlong_as_double((long long)z);
-    F.host_out[3] = 1.0;  // written marker
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      a = fmax(a, s[0][w]);
+      b = fmax(b, s[1][w]);
+      c = fmin(c, s[2][w]);
+    }
+    const int e = atomicOr(d.F.err, 0);
+    host_out[0] = a;
+    host_out[1] = b;
+    host_out[2] = (double)e;
+    host_out[4] = c;
+    __threadfence_system();
+    host_out[3] = 1.0;  // written marker
   }
 }
 
@@ -292,6 +315,10 @@ void launch_batch_force(const RepDesc<real> *D, int R, int max_n, int mode, cons
     case 12: batch_force_any<real, 12>(D, grid, mode, bp, lanes, st); break;
     default: batch_force_any<real, 0>(D, grid, mode, bp, lanes, st); break;
   }
+  // atoms per block of the instance batch_force_mode ran (it takes 1 lane
+  // for any count other than 2 and 4)
+  const int per_k = kBlock / ((lanes == 2 || lanes == 4) ? lanes : 1);
+  hipLaunchKernelGGL((k_batch_pred_reduce<real>), dim3(R), dim3(kBlock), 0, st, D, bp, per_k);
 }
 template void launch_batch_spin<double>(const RepDesc<double> *, int, int, const BatchPhase &, int, bool, hipStream_t);
 template void launch_batch_spin<float>(const RepDesc<float> *, int, int, const BatchPhase &, int, bool, hipStream_t);
