@@ -480,6 +480,9 @@ int sl_batch_get_mode(sl_batch *b, int *mode);
 int sl_batch_autotune(sl_batch *b, int steps, double dt, int *mode, int *lanes);
 /* Lanes per atom inside the persistent kernel (1, 2 or 4; speed only). */
 int sl_batch_set_lanes(sl_batch *b, int lanes);
+/* sl_set_row_order on every replica (one grid step for all; SL_E_ARG if
+ * negative or not finite). */
+int sl_batch_set_row_order(sl_batch *b, double quantum);
 int sl_batch_get_stats(sl_batch *b, int64_t *launches, int64_t *rebuilds, int *lanes);
 const char *sl_batch_last_error(const sl_batch *b);
 

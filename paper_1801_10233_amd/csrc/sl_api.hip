@@ -2360,6 +2360,7 @@ struct sl_batch {
   int graph_lanes = -1;
   int lanes = 2;
   int mode = SL_BATCH_PHASED;
+  double row_q = 0.0;  // list row order of every replica
   std::vector<sl_params> params;     // creation parameters, for autotune clones
   std::vector<sl_potential> pots;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -2806,6 +2807,7 @@ int sl_batch_autotune(sl_batch *B, int steps, double dt, int *mode, int *lanes) 
     sl_batch *C = nullptr;
     int rc = sl_batch_create(B->R, B->params.data(), B->pots.data(), &C);
     if (rc) return bfail(B, rc, std::string("autotune copy: ") + sl_batch_last_error(nullptr));
+    rc = sl_batch_set_row_order(C, B->row_q);
     for (int r = 0; r < B->R && rc == SL_OK; ++r) {
       sl_system *S = B->sys[r];
       std::vector<double> x, vv, sp, m;
@@ -2864,6 +2866,18 @@ int sl_batch_get_mode(sl_batch *B, int *mode) {
 int sl_batch_set_lanes(sl_batch *B, int lanes) {
   if (!B || !(lanes == 1 || lanes == 2 || lanes == 4)) return bfail(B, SL_E_ARG, "lanes must be 1, 2 or 4");
   B->lanes = lanes;
+  return SL_OK;
+}
+
+int sl_batch_set_row_order(sl_batch *B, double quantum) {
+  if (!B) return bfail(B, SL_E_ARG, "NULL batch");
+  if (!(quantum >= 0.0) || !std::isfinite(quantum))
+    return bfail(B, SL_E_ARG, "row-order grid step must be finite and >= 0");
+  for (int r = 0; r < B->R; ++r) {
+    const int rc = sl_set_row_order(B->sys[r], quantum);
+    if (rc) return bfail(B, rc, B->sys[r]->last_err);
+  }
+  B->row_q = quantum;
   return SL_OK;
 }
 

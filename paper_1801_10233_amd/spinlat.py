@@ -51,7 +51,7 @@ EXPORTS = [
     "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
     "sl_mlp_loss_grad", "sl_mlp_train",
     "sl_batch_create", "sl_batch_destroy", "sl_batch_set_state", "sl_batch_get_state",
-    "sl_batch_get_energy", "sl_batch_get_temperatures", "sl_batch_step", "sl_batch_set_lanes", "sl_batch_get_stats",
+    "sl_batch_get_energy", "sl_batch_get_temperatures", "sl_batch_step", "sl_batch_set_lanes", "sl_batch_set_row_order", "sl_batch_get_stats",
     "sl_batch_last_error", "sl_batch_set_mode", "sl_batch_get_mode", "sl_batch_autotune",
 ]
 
@@ -189,6 +189,7 @@ def lib():
         "sl_batch_get_temperatures": ([vp, C.c_int, dp, dp], C.c_int),
         "sl_batch_step": ([vp, i64, C.c_double], C.c_int),
         "sl_batch_set_lanes": ([vp, C.c_int], C.c_int),
+        "sl_batch_set_row_order": ([vp, C.c_double], C.c_int),
         "sl_batch_get_stats": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), ip], C.c_int),
         "sl_batch_last_error": ([vp], C.c_char_p),
         "sl_batch_set_mode": ([vp, C.c_int], C.c_int),
@@ -528,6 +529,9 @@ class Batch:
         self.N = [w.N for w in workloads]
         for k, w in enumerate(workloads):
             self.set_state(k, w.r, w.v, w.s, w.mass)
+        q = {float(getattr(w, "row_quantum", 0.0)) for w in workloads}
+        if len(q) == 1 and q.pop() > 0.0:
+            self.set_row_order(getattr(workloads[0], "row_quantum"))
 
     def close(self):
         if getattr(self, "h", None):
@@ -573,6 +577,10 @@ class Batch:
 
     def set_lanes(self, lanes):
         self._check(lib().sl_batch_set_lanes(self.h, int(lanes)))
+
+    def set_row_order(self, quantum):
+        """List-row order grid (A) of every replica; 0 keeps the cell-loop order."""
+        self._check(lib().sl_batch_set_row_order(self.h, float(quantum)))
 
     def set_mode(self, mode):
         self._check(lib().sl_batch_set_mode(self.h, int(mode)))

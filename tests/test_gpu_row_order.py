@@ -78,3 +78,20 @@ def test_row_order_rejects_bad_grid():
             g.set_row_order(bad)
         assert e.value.code == sl.SL_E_ARG
     g.step(2, 1e-4)
+
+
+def test_batch_row_order_parity_and_errors():
+    from paper_1801_10233_amd import spinlat as sl
+    ws = W.batched_replicas(R=3, seed=17, n_lo=5, n_hi=7)
+    b = sl.Batch(ws, precision=sl.SL_FP64)          # workload default: ordered rows
+    with pytest.raises(sl.SpinLatError) as e:
+        b.set_row_order(-0.5)
+    assert e.value.code == sl.SL_E_ARG
+    b.step(60, 1e-4)
+    for r, w in enumerate(ws):
+        o = make_oracle(w)
+        o.step(60, 1e-4)
+        ro, vo, so = o.get_state()
+        rg, vg, sg = b.get_state(r)
+        assert np.abs(rg - ro).max() / w.box[0] < 1e-10
+        assert np.abs(sg - so).max() < 1e-10
