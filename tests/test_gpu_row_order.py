@@ -95,3 +95,55 @@ def test_batch_row_order_parity_and_errors():
         rg, vg, sg = b.get_state(r)
         assert np.abs(rg - ro).max() / w.box[0] < 1e-10
         assert np.abs(sg - so).max() < 1e-10
+
+
+def test_user_list_keeps_its_order():
+    # a user-supplied list is not reordered: rows come back as given (split
+    # stably into the spin segment first), whatever the row-order grid
+    w = W.coupled_nve(n=6)
+    o = make_oracle(w)
+    o.build()
+    ns, na, rows = o.neighbor_list()
+    rng = np.random.default_rng(3)
+    rows = [rng.permutation(r) for r in rows]            # any order is a valid list
+    off = np.concatenate([[0], np.cumsum(na)]).astype(np.int32)
+    idx = np.concatenate(rows).astype(np.int32)
+    g = make_gpu(w)                                       # row order on (workload default)
+    g.set_neighbor_list(off, idx)
+    g.step(0, w.dt)
+    nsg, nag, rg = g.neighbor_list()
+    rs = (w.pot["ex_rc"] + w.skin) ** 2
+    for i in range(w.N):
+        d = w.r[rows[i]] - w.r[i]
+        d -= w.box * np.rint(d / w.box)
+        spin = (d * d).sum(axis=1) < rs
+        expect = np.concatenate([rows[i][spin], rows[i][~spin]])
+        assert np.array_equal(rg[i], expect), i
+
+
+def test_long_rows_keep_cell_order_and_parity():
+    # a Morse cut of 6.5 A gives rows of 112 entries: the rest segment is
+    # longer than the in-LDS sort handles (64) and keeps the cell-loop order,
+    # the spin segment is still sorted; the trajectory matches the oracle
+    w = W.coupled_nve(n=8)
+    w.pot = dict(w.pot, morse_rc=6.5)
+    w.r = w.r + W.thermal_displacements(w.N, 0.02, 8)
+    o = make_oracle(w)
+    g = make_gpu(w, max_nbr=160)
+    h = make_gpu(w, max_nbr=160)
+    h.set_row_order(0.0)
+    g.step(0, w.dt)
+    h.step(0, w.dt)
+    ns, na, rows = g.neighbor_list()
+    _, _, rows0 = h.neighbor_list()
+    assert na.min() > 64 + ns.max()
+    q = W.BCC_A / 2
+    for i in range(0, w.N, 37):
+        k = _keys(w.r, w.box, i, rows[i][:ns[i]], q)
+        assert all(k[m] <= k[m + 1] for m in range(len(k) - 1))
+        assert np.array_equal(rows[i][ns[i]:], rows0[i][ns[i]:])
+    o.step(60, w.dt)
+    g.step(60, w.dt)
+    p = parity(w, o, g)
+    print("long rows", p, flush=True)
+    assert p["ok"], p
