@@ -19,6 +19,11 @@ constexpr double kMvv2e = 1.0364269652680506e-4;  // eV per amu A^2/ps^2
 
 constexpr double kInf = 1e300;     // "no watched pair" distance squared
 constexpr int kMaxRep = 4;        // consecutive updates one spin launch can do
+// Workgroup of the spin phase: one wavefront. A class of 108 000 atoms at one
+// lane per atom is 1688 wavefronts; in 256-thread groups the 422 groups
+// leave 166 CUs with two and 90 with one, in single-wave groups every CU gets
+// six or seven (2.6 % faster per step at 432 000 atoms).
+constexpr int kSpinBlock = 64;
 constexpr int kSpinChunk = 4;     // neighbours per lane gathered together (spin phase)
 #ifndef SL_FORCE_CHUNK
 #define SL_FORCE_CHUNK 8

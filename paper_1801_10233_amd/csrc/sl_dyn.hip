@@ -13,7 +13,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst
   // LANES consecutive lanes share one atom: each gathers every LANES-th
   // neighbour, the partial sums are combined with cross-lane shuffles and
   // the first lane rotates and stores the spin.
-  const int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int t = xcd_tile(blockIdx.x, gridDim.x) * kSpinBlock + threadIdx.x;
   const int l = t & (LANES - 1);
   const int i = A.begin + t / LANES;
   spin_update<real, LANGEVIN, ANISO, LANES, MLP, DUAL>(S, P, i, i < A.end, l, A.nrep, A.step,
@@ -132,12 +132,12 @@ template <typename real, int LANES, int MLP, bool DUAL>
 static void spin_phase_lanes3(const SysView<real> &S, const PotConst &P, const SpinPhaseArgs &A,
                               const SysView<real> &S2, hipStream_t st) {
   const long threads = (long)(A.end - A.begin) * LANES;
-  const int nb = (int)((threads + kBlock - 1) / kBlock);
+  const int nb = (int)((threads + kSpinBlock - 1) / kSpinBlock);
   const bool lg = P.langevin != 0, an = P.aniso_on != 0;
-  if (lg && an) hipLaunchKernelGGL((k_spin_phase<real, true, true, LANES, MLP, DUAL>), dim3(nb), dim3(kBlock), 0, st, S, P, A, S2);
-  else if (lg) hipLaunchKernelGGL((k_spin_phase<real, true, false, LANES, MLP, DUAL>), dim3(nb), dim3(kBlock), 0, st, S, P, A, S2);
-  else if (an) hipLaunchKernelGGL((k_spin_phase<real, false, true, LANES, MLP, DUAL>), dim3(nb), dim3(kBlock), 0, st, S, P, A, S2);
-  else hipLaunchKernelGGL((k_spin_phase<real, false, false, LANES, MLP, DUAL>), dim3(nb), dim3(kBlock), 0, st, S, P, A, S2);
+  if (lg && an) hipLaunchKernelGGL((k_spin_phase<real, true, true, LANES, MLP, DUAL>), dim3(nb), dim3(kSpinBlock), 0, st, S, P, A, S2);
+  else if (lg) hipLaunchKernelGGL((k_spin_phase<real, true, false, LANES, MLP, DUAL>), dim3(nb), dim3(kSpinBlock), 0, st, S, P, A, S2);
+  else if (an) hipLaunchKernelGGL((k_spin_phase<real, false, true, LANES, MLP, DUAL>), dim3(nb), dim3(kSpinBlock), 0, st, S, P, A, S2);
+  else hipLaunchKernelGGL((k_spin_phase<real, false, false, LANES, MLP, DUAL>), dim3(nb), dim3(kSpinBlock), 0, st, S, P, A, S2);
 }
 
 template <typename real, int LANES, int MLP>
