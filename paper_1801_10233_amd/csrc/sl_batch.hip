@@ -171,9 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_spin(const RepDesc<real> *D, B
                                              d.rs2);
 }
 
-// Force, kicks and drift of every replica at one boundary, with each
-// replica's rebuild predictor reduced by its own last block into its own
-// pinned slot (as k_force does for one system).
+// Force, kicks and drift of every replica at one boundary; each block stores
+// its replica's rebuild predictor terms, which k_batch_pred_reduce joins into
+// the replica's pinned slot (as k_pred_reduce does for one system).
 template <typename real, int MODE, int LANES, int MLP>
 __global__ __launch_bounds__(kBlock) void k_batch_force(const RepDesc<real> *D, BatchPhase bp) {
   __shared__ double redm[kBlock / 64][3];

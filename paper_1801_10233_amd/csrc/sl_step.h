@@ -247,8 +247,9 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
 //          next step, written to the other position buffer)
 //   ENERGY: per-atom energies (pairs halved) and M, block partial sums.
 // Every launch with a kick also reduces max |r - r_build| and max |v| at
-// this boundary for the rebuild decision; the last block to finish hands
-// them, with the sticky error word, to pinned host memory.
+// this boundary for the rebuild decision, block by block; a one-block join
+// after the launch hands them, with the sticky error word, to pinned host
+// memory.
 // Per-atom part of the force launch (shared with the batched persistent
 // kernel): force on atom i over its list row, split over LANES lanes, then on
 // the first lane the kicks, the drift into the other position buffer, the
