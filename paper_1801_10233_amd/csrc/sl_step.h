@@ -483,7 +483,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
 
 // First pass of the embedded-atom terms: rho_i = sum_j f(r_ij) over the whole
 // list row, then F'(rho_i) and F(rho_i) for the force pass (one thread per
-// atom; 8 neighbours' positions in flight together).
+// atom; one force-gather chunk of neighbours' positions in flight together).
 template <typename real>
 __device__ __forceinline__ void eam_density_atom(const SysView<real> &S, const PotConst &P, int i) {
   const int na = S.nall[i], ld = S.ld;
