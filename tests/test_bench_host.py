@@ -51,3 +51,17 @@ def test_algorithmic_bytes_and_profile_lookup():
     # a summary of another launch shape or of older sources is never used
     assert B.counter_traffic("k_spin_phase", sl.SL_FP64, "lanes=3,jcache=0") is None
     assert B.counter_traffic("no_such_kernel", sl.SL_FP64, "lanes=1") is None
+
+
+def test_committed_counter_summaries_match_the_sources():
+    # the summaries under profiles/ were taken on the current kernel sources
+    # (same SHA-256) for the shape the autotuner picks at 432 000 atoms, so
+    # the benchmark reports their traffic instead of null
+    B = _bench()
+    sl = B.sl
+    t = B.counter_traffic("k_spin_phase", sl.SL_FP64, "lanes=1,jcache=0")
+    f = B.counter_traffic("k_force", sl.SL_FP64, "lanes=1")
+    assert t is not None and f is not None
+    alg_spin = B.SPIN_BYTES[sl.SL_FP64] * 108000
+    alg_force = B.FORCE_BYTES[sl.SL_FP64] * 432000
+    assert alg_spin < t < 5 * alg_spin and alg_force < f < 5 * alg_force
