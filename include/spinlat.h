@@ -197,6 +197,8 @@ int sl_set_neighbor(sl_system *sys, double skin, int max_nbr);
  * the cubic lattice constant for bcc and fcc) slot k of every row then holds
  * the neighbour at the same lattice offset, so a wavefront of spatially
  * sorted atoms gathers slot k from a short contiguous range of memory.
+ * A segment of more than 64 entries keeps the cell-loop order (the sort
+ * holds a segment's keys in LDS).
  * Applies from the next automatic list build (the list is invalidated);
  * user-supplied lists keep their order. SL_E_ARG if quantum < 0 or not
  * finite. */
