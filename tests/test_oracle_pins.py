@@ -514,8 +514,72 @@ def test_lattice_bath_off_is_nve_and_noise_uses_tagged_stream():
 
 
 # --------------------------------------------------------------------------
-# P14: Philox4x32-10 statistics (the published known-answer vectors are not
-# available here, so the exact stream is unpinned; its quality is).
+# P14: Philox4x32-10. The exact stream is pinned to rocRAND's engine (an
+# implementation of the SC'11 generator written apart from this repository,
+# shipped as C++ source with ROCm), compiled here as a host program and run
+# on the same (counter, key) blocks; its statistics are checked too.
+ROCRAND_REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rocrand_philox_ref.cpp")
+
+
+def _rocrand_philox(blocks, tmp_path):
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    exe = str(tmp_path / "rocrand_philox_ref")
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-O1", "-o", exe, ROCRAND_REF], check=True,
+                   capture_output=True, text=True)
+    text = "\n".join(" ".join(str(int(x)) for x in b) for b in blocks) + "\n"
+    out = subprocess.run([exe], input=text, check=True, capture_output=True, text=True).stdout
+    return np.array([[int(x) for x in line.split()] for line in out.splitlines()],
+                    dtype=np.uint64)
+
+
+def _split64(x):
+    x = int(x) & 0xFFFFFFFFFFFFFFFF
+    return x & 0xFFFFFFFF, x >> 32
+
+
+def test_philox_stream_equals_rocrand(tmp_path):
+    rng = np.random.default_rng(14)
+    blocks = [list(b) for b in rng.integers(0, 2 ** 32, size=(10000, 6), dtype=np.uint64)]
+    # single special words in every counter and key position
+    special = [0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFE, 0xFFFFFFFF]
+    for pos in range(6):
+        for w in special:
+            b = [int(x) for x in rng.integers(0, 2 ** 32, size=6, dtype=np.uint64)]
+            b[pos] = w
+            blocks.append(b)
+    blocks.append([0] * 6)
+    blocks.append([0xFFFFFFFF] * 6)
+    # the layouts the library draws with: counter (atom id, step low, step
+    # high, replica << 2 | sub), key = seed, or seed XOR the lattice tag,
+    # with high step and key words set
+    seeds = [1001, 3003, 4004, 11, 42, 0x0123456789ABCDEF]
+    for seed in seeds:
+        for key in (seed, seed ^ O.LATTICE_KEY_TAG):
+            k0, k1 = _split64(key)
+            for step in (0, 7, 123456789012, 2 ** 63 - 1):
+                s0, s1 = _split64(step)
+                for atom, rep, sub in ((0, 0, 0), (431999, 0, 3), (27647, 63, 2)):
+                    blocks.append([atom, s0, s1, (rep << 2) | sub, k0, k1])
+    ref = _rocrand_philox(blocks, tmp_path)
+    assert ref.shape == (len(blocks), 4)
+    ours = np.array([O.philox(b[:4], b[4:]) for b in blocks], dtype=np.uint64)
+    bad = np.nonzero((ours != ref).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} of {len(blocks)} blocks differ, first {blocks[bad[0]]}"
+    # the normals of one spin update are Box-Muller on that block's words
+    for seed, atom, step, rep, sub in ((3003, 5, 123456789012, 0, 1), (42, 27647, 9, 63, 3)):
+        k0, k1 = _split64(seed)
+        s0, s1 = _split64(step)
+        x = _rocrand_philox([[atom, s0, s1, (rep << 2) | sub, k0, k1]], tmp_path)[0]
+        u = (x.astype(np.float64) + 0.5) / 2.0 ** 32
+        ra, rb = math.sqrt(-2 * math.log(u[0])), math.sqrt(-2 * math.log(u[2]))
+        want = [ra * math.cos(2 * math.pi * u[1]), ra * math.sin(2 * math.pi * u[1]),
+                rb * math.cos(2 * math.pi * u[3])]
+        np.testing.assert_allclose(O.gauss3(seed, atom, step, rep, sub), want, rtol=1e-14,
+                                   atol=1e-14)
+
+
 def test_philox_statistics():
     key = (0x1234567, 0x89abcdef)
     outs = np.array([O.philox((i, 0, 0, 0), key) for i in range(20000)], dtype=np.float64)
