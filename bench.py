@@ -32,12 +32,14 @@ from paper_1801_10233_amd import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# Algorithmic bytes per atom for one launch of each kernel (compulsory
-# traffic, neighbour gathers counted as cache hits; 14 spin and 58 force
-# neighbours per atom in bcc at these cutoffs):
-#   spin phase: own s read + write, own r read, 14 int32 indices
-#   force (fused with kicks and drift): r, s, 58 indices, v read + write,
-#   mass, reference position, next position write
+# Algorithmic bytes of each kernel's unit of work (compulsory traffic,
+# neighbour gathers counted as cache hits; 14 spin and 58 force neighbours
+# per atom in bcc at these cutoffs):
+#   spin phase, per atom update: own s read + write, own r read, 14 int32
+#   indices (a launch that applies two successive updates to its class
+#   counts each of them, as four sweeps of single updates would)
+#   force (fused with kicks and drift), per atom: r, s, 58 indices, v read
+#   + write, mass, reference position, next position write
 SPIN_BYTES = {sl.SL_FP64: 24 + 24 + 24 + 14 * 4, sl.SL_FP32: 12 + 12 + 24 + 14 * 4}
 # with the exchange-coefficient cache the spin phase reads 14 cached J(r_ij)
 # instead of its own position; the cache is rebuilt once per drift (own r,
@@ -53,6 +55,11 @@ STEP_BYTES = {sl.SL_FP64: 4 * SPIN_BYTES[sl.SL_FP64] + FORCE_BYTES[sl.SL_FP64],
               sl.SL_FP32: 4 * SPIN_BYTES[sl.SL_FP32] + FORCE_BYTES[sl.SL_FP32]}
 STEP_BYTES_JC = {p: 4 * SPIN_BYTES_JC[p] + FORCE_BYTES[p] + JCACHE_BYTES[p]
                  for p in (sl.SL_FP64, sl.SL_FP32)}
+# the same step counted as unfused kernels: four spin sweeps, a force pass
+# that writes F (r, s, 58 indices, F), a kick + drift pass (v read + write, r
+# read + write, F) and a final kick (v read + write, F)
+STEP_BYTES_UNFUSED = {sl.SL_FP64: 4 * 128 + (24 + 24 + 58 * 4 + 24) + 120 + 72,
+                      sl.SL_FP32: 4 * 92 + (12 + 12 + 58 * 4 + 12) + 120 + 60}
 PROFILES = os.path.join(ROOT, "profiles")
 # the kernels and the list build, whose row order sets the gathers' memory pattern
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_10233_amd", "csrc", f)
@@ -244,10 +251,35 @@ def mlp_pairwise(w, mlp, steps=50):
                                  frac=round(tflops / MFMA_BF16_PEAK_TFLOPS, 4)))
 
 
+def slope_with_error(t, y):
+    """Least-squares slope of y(t) and its standard error, the residuals'
+    correlation taken into account by block averaging: the statistical
+    inefficiency is the largest b var(block means of b samples) / var over
+    block lengths b up to a tenth of the series."""
+    t = np.asarray(t, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    A = np.vstack([t, np.ones_like(t)]).T
+    coef, *_ = np.linalg.lstsq(A, y, rcond=None)
+    res = y - A @ coef
+    var = res.var()
+    n = res.size
+    g = 1.0
+    b = 1
+    while b <= max(1, n // 10):
+        m = n // b
+        bm = res[:m * b].reshape(m, b).mean(axis=1)
+        if var > 0:
+            g = max(g, b * bm.var() / var)
+        b *= 2
+    se = np.sqrt(g * var / np.sum((t - t.mean()) ** 2)) if n > 2 else float("nan")
+    return float(coef[0]), float(se), float(g)
+
+
 def drift_per_10ps(w, precision, steps, every=10, settle=2000, mlp=None):
     """Least-squares slope of E_total/N against time on the undamped twin,
-    scaled to 10 ps, over `steps` steps after `settle` steps in which the
-    spin and lattice subsystems start exchanging energy."""
+    scaled to 10 ps, with its block-averaged standard error, over `steps`
+    steps after `settle` steps in which the spin and lattice subsystems start
+    exchanging energy."""
     S = sl.system_from_workload(w, precision=precision, thermo_every=every)
     if mlp is not None:
         S.set_mlp(mlp)
@@ -256,9 +288,11 @@ def drift_per_10ps(w, precision, steps, every=10, settle=2000, mlp=None):
     keep = st > settle
     st, E = st[keep], E[keep]
     t = st * w.dt
-    slope = np.polyfit(t, E / w.N, 1)[0]
+    slope, se, g = slope_with_error(t, E / w.N)
     S.close()
-    return float(slope * 10.0), float(np.std(E / w.N))
+    return dict(drift_eV_per_atom_per_10ps=slope * 10.0, stderr=se * 10.0,
+                E_rms_eV_per_atom=float(np.std(E / w.N)), span_ps=float(t[-1] - t[0]),
+                samples=int(t.size), inefficiency=round(g, 1))
 
 
 def next_rows(w, steps, warmup, tune, base_value):
@@ -296,6 +330,25 @@ def next_rows(w, steps, warmup, tune, base_value):
                                        T_L=round(tl, 2), T_S=round(ts, 2))
         S.close()
     out["sectors"]["grid"] = [16, 16, 16]
+    return out
+
+
+def small_configs(repeats=3):
+    """Throughput of the two small workloads in FP64: the frozen-lattice spin
+    system (bcc 10^3 cells, 2000 atoms, 1000 steps) and the coupled NVE system
+    (bcc 20^3 cells, 16000 atoms, 1000 steps, rebuilds included); median of
+    `repeats` windows after 20 warm-up steps. Both are launch-latency bound."""
+    out = {}
+    for name, w, steps in (("spin_frozen_2000", W.spin_frozen(10), 1000),
+                           ("coupled_nve_16000", W.coupled_nve(n=20), 1000)):
+        S = sl.system_from_workload(w, precision=sl.SL_FP64, thermo_every=100)
+        S.step(20, w.dt)
+        els = sorted(timed_run(S, steps, w.dt)[0] for _ in range(repeats))
+        el = els[len(els) // 2]
+        out[name] = dict(value=round(w.N * steps / el, 1), unit="atom-steps/s", atoms=w.N,
+                         steps=steps, ms_per_step=round(el / steps * 1e3, 4),
+                         rebuilds=S.stats()["rebuilds"])
+        S.close()
     return out
 
 
@@ -346,6 +399,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip FP32 form and drift")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--drift-steps", type=int, default=10000)
+    ap.add_argument("--drift-validate-steps", type=int, default=100000,
+                    help="steps of the 16000-atom undamped drift run per form (0: skip)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shapes (no autotune before timing)")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -401,39 +456,52 @@ def main():
     log(f"timed {args.steps} steps: {el:.4f} s, {ms_step:.4f} ms/step, {value:.4e} atom-steps/s")
     st = S.stats()
 
-    # dominant kernel = largest summed event time in the timed region
+    # the profile holds whole steps only (the first of each window and every
+    # PROFILE_EVERY-th after it); the dominant kernel is the one with the
+    # largest summed event time in them
     kinds = {k: v for k, v in prof.items() if k in KIND_NAME and v[0] > 0}
     dom = max((k for k in kinds if k in (sl.PROF_SPIN, sl.PROF_FORCE)), key=lambda k: kinds[k][1])
     launches, ms, work = kinds[dom]
+    n_prof = kinds[sl.PROF_FORCE][0]          # one force launch per timed step
     tun = S.tuning()
     jc_on = tun["jcache"] > 0
-    per_atom = ((SPIN_BYTES_JC if jc_on else SPIN_BYTES)[prec] if dom == sl.PROF_SPIN
+    per_unit = ((SPIN_BYTES_JC if jc_on else SPIN_BYTES)[prec] if dom == sl.PROF_SPIN
                 else FORCE_BYTES[prec])
     shape = (f"lanes={tun['spin_lanes']},jcache={int(jc_on)}" if dom == sl.PROF_SPIN
              else f"lanes={tun['force_lanes']}")
     step_bytes = (STEP_BYTES_JC if jc_on else STEP_BYTES)[prec]
     avg_ms = ms / launches
-    bytes_per_launch = per_atom * work / launches
+    bytes_per_launch = per_unit * work / launches
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     other = {KIND_NAME[k]: dict(launches=v[0], total_ms=round(v[1], 4),
                                 avg_us=round(v[1] / max(v[0], 1) * 1e3, 3),
-                                atoms_per_launch=round(v[2] / max(v[0], 1), 1))
+                                per_step_us=round(v[1] / max(n_prof, 1) * 1e3, 2),
+                                work_items_per_launch=round(v[2] / max(v[0], 1), 1))
              for k, v in kinds.items()}
     log("kernels:", json.dumps(other))
     traffic = counter_traffic(KIND_NAME[dom], prec, shape)
+    unf = STEP_BYTES_UNFUSED[prec]
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic, 1),
                     traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     kernel=KIND_NAME[dom], launch_shape=shape, avg_launch_us=round(avg_ms * 1e3, 3),
-                    timing=f"HIP events on the library stream around every launch of every "
-                           f"{PROFILE_EVERY}th timed step",
-                    algorithmic_bytes_per_atom=per_atom,
+                    timing=f"HIP events on the library stream around every launch of the first "
+                           f"and every {PROFILE_EVERY}th step of each timed window",
+                    profiled_steps=n_prof,
+                    algorithmic_bytes_per_unit=per_unit,
+                    unit_of_work="atom update" if dom == sl.PROF_SPIN else "atom",
                     algorithmic_bytes_per_launch=round(bytes_per_launch, 1),
-                    atoms_per_launch=round(work / launches, 1), kernels=other,
-                    whole_step=dict(algorithmic_bytes_per_atom_step=step_bytes,
-                                    achieved_GBs=round(step_bytes * value / 1e9, 1),
-                                    frac=round(step_bytes * value / 1e9 / HBM_PEAK_GBS, 4)))
+                    units_per_launch=round(work / launches, 1), kernels=other,
+                    whole_step=dict(
+                        algorithmic_bytes_per_atom_step=unf,
+                        convention="unfused kernels (4 spin sweeps, force pass writing F, "
+                                   "kick + drift, final kick)",
+                        achieved_GBs=round(unf * value / 1e9, 1),
+                        frac=round(unf * value / 1e9 / HBM_PEAK_GBS, 4),
+                        fused=dict(algorithmic_bytes_per_atom_step=step_bytes,
+                                   achieved_GBs=round(step_bytes * value / 1e9, 1),
+                                   frac=round(step_bytes * value / 1e9 / HBM_PEAK_GBS, 4))))
 
     out = dict(metric="atom-steps/s, 432k-atom bcc spin-lattice, plain FP64 vs FP32/MLP form @ drift",
                value=round(value, 1), unit="atom-steps/s", n_gpus=1, steps=args.steps,
@@ -461,26 +529,36 @@ def main():
         S32.close()
         v32 = w.N * args.steps / el32
         twin = W.large_langevin(n=args.n, nve=True)
-        d64, f64 = drift_per_10ps(twin, sl.SL_FP64, args.drift_steps)
-        d32, f32 = drift_per_10ps(twin, sl.SL_FP32, args.drift_steps)
+        d64 = drift_per_10ps(twin, sl.SL_FP64, args.drift_steps)
+        d32 = drift_per_10ps(twin, sl.SL_FP32, args.drift_steps)
         mform, mlp = mlp_form(w, args.steps, args.warmup, not args.no_tune)
-        dml, fml = drift_per_10ps(twin, sl.SL_FP32, args.drift_steps, mlp=mlp)
+        dml = drift_per_10ps(twin, sl.SL_FP32, args.drift_steps, mlp=mlp)
         mpair = mlp_pairwise(w, mlp)
         out["forms"] = dict(
-            fp64=dict(value=round(value, 1), drift_eV_per_atom_per_10ps=d64, E_rms_eV_per_atom=f64),
-            fp32=dict(value=round(v32, 1), speedup_vs_fp64=round(v32 / value, 3),
-                      drift_eV_per_atom_per_10ps=d32, E_rms_eV_per_atom=f32),
-            mlp=dict(mform, speedup_vs_fp64=round(mform["value"] / value, 3),
-                     drift_eV_per_atom_per_10ps=dml, E_rms_eV_per_atom=fml,
+            fp64=dict(value=round(value, 1), drift=d64),
+            fp32=dict(value=round(v32, 1), speedup_vs_fp64=round(v32 / value, 3), drift=d32),
+            mlp=dict(mform, speedup_vs_fp64=round(mform["value"] / value, 3), drift=dml,
                      weights="paper_1801_10233_amd/data/mlp_bj_weights.npy (train_mlp.py)",
                      evaluation="spline of the network (SL_MLP_SPLINE)"),
             mlp_pairwise=dict(mpair, speedup_vs_fp64=round(mpair["value"] / value, 3),
                               evaluation="network per pair after every drift, BF16 MFMA "
                                          "(SL_MLP_PAIRWISE)"),
-            drift_run=f"undamped twin, 2000 settling steps then {args.drift_steps} steps "
-                      f"({args.drift_steps * twin.dt:.2f} ps), E sampled every 10 steps, "
-                      "least-squares slope scaled to 10 ps")
+            drift_run=f"undamped twin of the {w.N}-atom workload, 2000 settling steps then "
+                      f"{args.drift_steps} steps ({args.drift_steps * twin.dt:.2f} ps), E sampled "
+                      "every 10 steps, least-squares slope scaled to 10 ps, standard error by "
+                      "block averaging of the residuals")
+        if args.drift_validate_steps > 0:
+            # the same physics at 16 000 atoms over the whole 10 ps
+            small = W.large_langevin(n=20, nve=True)
+            out["forms"]["drift_16k_10ps"] = dict(
+                fp64=drift_per_10ps(small, sl.SL_FP64, args.drift_validate_steps),
+                fp32=drift_per_10ps(small, sl.SL_FP32, args.drift_validate_steps),
+                mlp=drift_per_10ps(small, sl.SL_FP32, args.drift_validate_steps, mlp=mlp),
+                run=f"undamped, bcc 20^3 cells (16000 atoms), 2000 settling steps then "
+                    f"{args.drift_validate_steps} steps")
         log("forms:", json.dumps(out["forms"]))
+        out["small_configs"] = small_configs()
+        log("small configs:", json.dumps(out["small_configs"]))
         out["batched"] = batched_throughput(args.batch_steps, tune=not args.no_tune)
         log("batched:", json.dumps(out["batched"]))
         out["next_rows"] = next_rows(w, min(args.steps, 300), args.warmup, not args.no_tune, value)

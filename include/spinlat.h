@@ -179,10 +179,11 @@ int sl_set_potential(sl_system *sys, const sl_potential *pot);
  * that are farther apart are watched instead.
  * Rebuild rule: before step k the list is rebuilt when, at the boundary
  * before step k-1,
- *   max_i |r_i - r_i^build| + 2|dt| max_i |v_i| >= skin/2 - 0.01 A, or
- *   min over watched pairs |r_i - r_j| - 4|dt| max_i |v_i| < ex_rc + 0.01 A
- * (a boundary that rebuilt counts its build positions and the colour
- * radius ex_rc + skin/3 instead). A rebuild keeps the colouring where
+ *   max_i |r_i - r_i^build| + 2a max_i |v_i| >= skin/2 - 0.01 A, or
+ *   min over watched pairs |r_i - r_j| - 4a max_i |v_i| < ex_rc + 0.01 A
+ * with a = max(|dt| of step k-1, |dt| of step k), the two differing only
+ * across calls that change dt (a boundary that rebuilt counts its build
+ * positions and the colour radius ex_rc + skin/3 instead). A rebuild keeps the colouring where
  * valid: ends of conflicting edges with the later key (z, y, x, id), and
  * atoms outside the palette of the last full colouring, are recoloured
  * first-fit in key order. */
@@ -321,15 +322,21 @@ int sl_get_tuning(sl_system *sys, sl_tuning *t);
 int sl_autotune(sl_system *sys, int steps, double dt, sl_tuning *chosen);
 
 /* Per-kernel timing with HIP events on the system's stream. With on = 1
- * every launch of the spin-phase, force, rebuild and table kernels is
- * bracketed by a pair of events; with on = N > 1 only the launches of every
- * N-th step are (the event packets themselves cost a few microseconds of
- * GPU time each); 0 stops. sl_get_profile returns, per kernel kind, the launch count
- * and the summed event time in ms since profiling was last switched on
- * (switching it off keeps the totals readable). Kinds: 0 spin phase,
- * 1 force, 2 neighbour rebuild, 3 pair-coefficient table (exchange cache
- * or per-pair learned potential), 4 pair pass of the split force (its
- * events are on the library's second stream). */
+ * every launch of the spin-phase, force, rebuild and table kernels inside
+ * the steps of sl_step is bracketed by a pair of events; with on = N > 1
+ * only the launches of the first step of each sl_step call and of every
+ * N-th step after it are (the event packets themselves cost a few
+ * microseconds of GPU time each); 0 stops. Launches outside whole steps
+ * (the force launch that opens a call, sl_get_energy and the like) are
+ * never timed, so the totals are those of whole steps. sl_get_profile
+ * returns, per kernel kind, the launch count, the summed event time in ms
+ * and the work items since profiling was last switched on (switching it off
+ * keeps the totals readable). Kinds and their work items: 0 spin phase
+ * (atom updates: a launch that applies two successive updates to a class
+ * counts its atoms twice), 1 force (atoms), 2 neighbour rebuild (atoms),
+ * 3 pair-coefficient table (exchange cache: atoms; per-pair learned
+ * potential: pairs), 4 pair pass of the split force (atoms; its events are
+ * on the library's second stream). */
 int sl_set_profiling(sl_system *sys, int on);
 int sl_get_profile(sl_system *sys, int kind, int64_t *launches, double *ms,
                    double *work_items);

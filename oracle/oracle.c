@@ -54,10 +54,10 @@ struct orc_sys {
     double *F;
     int have_F;
 
-    /* rebuild predictors of the previous step boundary: displacement D and
-     * the closest approach W of two same-colour spins, less the motion
-     * bound of the two drifts ahead */
-    double D_prev, W_prev;
+    /* terms of the rebuild predictor taken at the previous step boundary:
+     * largest displacement since the build, largest speed, closest
+     * same-colour spin pair, and |dt| of the step that followed it */
+    double disp_prev, vmax_prev, wmin_prev, adt_prev;
     int have_D;
 
     /* learned pair potential standing in for J and V (NULL: analytic) */
@@ -1028,16 +1028,18 @@ static void prepare_classes(orc_sys *S)
  *
  * Verlet rebuild rule (the paper uses the host code's defaults, unstated):
  * at the boundary before step k the list is rebuilt when
- *   D_{k-1} = max_i |r_i - r_i^build| + 2 |dt| max_i |v_i| >= skin/2 - 0.01 A,
- * with D evaluated at the previous boundary (after that boundary's own
- * rebuild, if any). The extra 2|dt| max|v| covers the two drifts that can
- * happen before the next decision. It is also rebuilt when
- *   W_{k-1} = min |r_i - r_j| - 4 |dt| max|v| < ex_rc + 0.01 A
+ *   D_{k-1} = max_i |r_i - r_i^build| + 2 a max_i |v_i| >= skin/2 - 0.01 A,
+ * with the displacement and speed taken at the previous boundary (after that
+ * boundary's own rebuild, if any) and a = max(|dt_{k-1}|, |dt_k|), the
+ * larger of the two step lengths involved (they differ only when a call
+ * changes dt). The extra 2 a max|v| covers the two drifts that can happen
+ * before the next decision. It is also rebuilt when
+ *   W_{k-1} = min |r_i - r_j| - 4 a max|v| < ex_rc + 0.01 A
  * over same-colour pairs of spin-segment entries at the previous boundary:
  * such a pair must not come within the exchange cutoff before the next
- * decision (each of the two ends moves at most 2|dt| max|v|). A boundary
- * that rebuilt takes W = colour radius - 4|dt| max|v| (after a colouring no
- * same-colour pair is closer). The classes are frozen for the step.
+ * decision (each of the two ends moves at most 2 a max|v|). A boundary that
+ * rebuilt takes the colour radius for the closest pair (after a colouring
+ * no same-colour pair is closer). The classes are frozen for the step.
  * ---------------------------------------------------------------------- */
 static double watch_min(const orc_sys *S)
 {
@@ -1127,17 +1129,22 @@ int orc_step(orc_sys *S, int64_t n, double dt)
         if (!S->have_list) {
             int rc = orc_build_now(S); if (rc) return rc;
             rebuilt = 1;
-        } else if (!S->user_list && S->have_D &&
-                   (S->D_prev >= S->skin / 2.0 - 0.01 ||
-                    (S->ordering == ORC_COLOUR && S->W_prev < S->pot.ex_rc + 0.01))) {
-            int rc = rebuild(S); if (rc) return rc;
-            rebuilt = 1;
+        } else if (!S->user_list && S->have_D) {
+            const double a = fmax(S->adt_prev, fabs(dt));
+            const double D = S->disp_prev + 2.0 * a * S->vmax_prev;
+            const double W = S->wmin_prev - 4.0 * a * S->vmax_prev;
+            if (D >= S->skin / 2.0 - 0.01 ||
+                (S->ordering == ORC_COLOUR && W < S->pot.ex_rc + 0.01)) {
+                int rc = rebuild(S); if (rc) return rc;
+                rebuilt = 1;
+            }
         }
         if (S->ordering == ORC_COLOUR && !S->have_colour) colour_update(S);
-        const double vmax = max_speed(S);
-        S->D_prev = max_disp(S) + 2.0 * fabs(dt) * vmax;
-        if (S->ordering == ORC_COLOUR)
-            S->W_prev = (rebuilt ? colour_radius(S) : watch_min(S)) - 4.0 * fabs(dt) * vmax;
+        S->vmax_prev = max_speed(S);
+        S->disp_prev = max_disp(S);
+        S->wmin_prev = S->ordering != ORC_COLOUR ? 1e300
+                       : (rebuilt ? colour_radius(S) : watch_min(S));
+        S->adt_prev = fabs(dt);
         S->have_D = 1;
         prepare_classes(S);
         if (!S->have_F) forces(S);

@@ -773,7 +773,7 @@ void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps
   A.seed = S->prm.seed;
   A.replica = S->prm.replica;
   A.rs2 = S->pot.ex_rc * S->pot.ex_rc;
-  ProfScope ps(S, 0, (double)(A.end - A.begin));  // atoms (a dual launch counts them once)
+  ProfScope ps(S, 0, (double)(A.end - A.begin) * nrep);  // atom updates
   if (dual) {
     const SysView<real> v2 = view<real>(S, 1 - posbuf);
     launch_spin_phase<real>(view<real>(S, posbuf), S->pc, A, S->spin_lanes, S->st, &v2);
@@ -903,11 +903,12 @@ void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) 
   size_t q = 0;
   while (q < items.size()) {
     size_t r = q;
-    long tot = 0;
+    long tot = 0, upd = 0;
     while (r < items.size() && (int)(r - q) < kMaxTail) {
       const int sz = size_of(items[r].c);
       if (sz > S->small_class || tot + sz > kTailTotalMax) break;
       tot += sz;
+      upd += (long)sz * items[r].nrep;
       ++r;
     }
     if (r - q >= 2) {
@@ -929,7 +930,7 @@ void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) 
       T.seed = S->prm.seed;
       T.replica = S->prm.replica;
       T.rs2 = S->pot.ex_rc * S->pot.ex_rc;
-      ProfScope ps(S, 0, (double)tot);
+      ProfScope ps(S, 0, (double)upd);
       launch_spin_tail<real>(view<real>(S, posbuf), S->pc, T, S->spin_lanes, S->st);
       q = r;
     } else {
@@ -1051,13 +1052,15 @@ int energy_now(sl_system *S, double out[8]) {
 
 // Wait until the force kernel of `boundary` finished and decide from its
 // predictor whether the list must be rebuilt before the step after next:
-//   D = max|r - r_build| + 2|dt| max|v|        >= skin/2 - 0.01, or
-//   W = min watched |r_i - r_j| - 4|dt| max|v| <  ex_rc + 0.01,
-// the watched pairs being same-colour spin-segment entries. When the list
-// was rebuilt at that boundary after the predictor was taken, the build
-// positions are that boundary's (D term 0) and no same-colour pair is
-// closer than the colour radius.
-int wait_predictor(sl_system *S, int64_t boundary, bool *due) {
+//   D = max|r - r_build| + 2a max|v|        >= skin/2 - 0.01, or
+//   W = min watched |r_i - r_j| - 4a max|v| <  ex_rc + 0.01,
+// the watched pairs being same-colour spin-segment entries, and a the larger
+// of |dt| of the step after `boundary` and |dt_next| of the step to be
+// decided (they differ when a call changes dt). When the list was rebuilt at
+// that boundary after the predictor was taken, the build positions are that
+// boundary's (D term 0) and no same-colour pair is closer than the colour
+// radius.
+int wait_predictor(sl_system *S, int64_t boundary, double dt_next, bool *due) {
   *due = false;
   const int slot = (int)(boundary & 3);
   if (boundary < 0 || S->meta[slot].boundary != boundary) return SL_OK;
@@ -1067,7 +1070,7 @@ int wait_predictor(sl_system *S, int64_t boundary, bool *due) {
   S->sticky |= (int)o[2];
   CHK(sticky_code(S));
   const bool rb = S->meta[slot].rebuilt_after;
-  const double adt = std::fabs(S->meta[slot].dt);
+  const double adt = std::max(std::fabs(S->meta[slot].dt), std::fabs(dt_next));
   const double D = (rb ? 0.0 : o[0]) + 2.0 * adt * o[1];
   const double W = (rb ? colour_radius(S) : std::sqrt(o[4])) - 4.0 * adt * o[1];
   *due = D >= S->skin / 2.0 - 0.01 ||
@@ -1080,6 +1083,7 @@ int step_frozen(sl_system *S, int64_t n, double dt) {
   const double h = dt / 4.0;
   const int te = S->prm.thermo_every;
   int64_t k = 0;
+  S->prof_now = S->prof;  // every launch of a frozen run is timed
   while (k < n) {
     // steps up to the next thermo sample go in one merged update list
     int64_t chunk = n - k;
@@ -1109,6 +1113,7 @@ int step_frozen(sl_system *S, int64_t n, double dt) {
       CHK(record_thermo(S, S->step));
     }
   }
+  S->prof_now = false;
   return SL_OK;
 }
 
@@ -1120,7 +1125,7 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
   // decision for the first step uses the predictor of the boundary before it
   if (!S->user_list && S->have_D) {
     bool due;
-    CHK(wait_predictor(S, k0 - 1, &due));
+    CHK(wait_predictor(S, k0 - 1, dt, &due));
     if (due) {
       CHK(rebuild(S));
       built = true;
@@ -1131,15 +1136,16 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
   if (built) S->meta[k0 & 3].rebuilt_after = true;
   S->have_D = true;
   for (int64_t k = k0; k < k0 + n; ++k) {
+    // timed steps: the first of the call and every prof_every-th after it
+    S->prof_now = S->prof && ((k - k0) % S->prof_every == 0);
     if (k > k0 && !S->user_list) {
       bool due;
-      CHK(wait_predictor(S, k - 1, &due));
+      CHK(wait_predictor(S, k - 1, dt, &due));
       if (due) {
         CHK(rebuild(S));
         S->meta[k & 3].rebuilt_after = true;
       }
     }
-    S->prof_now = S->prof && (k % S->prof_every == 0);
     const int64_t b = k + 1;
     int mode = kModeFinal;
     if (k + 1 < k0 + n) mode |= kModeNext;
@@ -1192,7 +1198,7 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
     S->pos = 1 - S->pos;
     S->step = b;
   }
-  S->prof_now = S->prof;
+  S->prof_now = false;
   return SL_OK;
 }
 
@@ -1809,7 +1815,7 @@ int sl_set_profiling(sl_system *S, int on) {
     }
   S->prof = on != 0;
   S->prof_every = on > 1 ? on : 1;
-  S->prof_now = S->prof;
+  S->prof_now = false;  // set per step inside sl_step
   return SL_OK;
 }
 
@@ -2483,7 +2489,7 @@ int batch_step(sl_batch *B, int64_t n, double dt) {
     bool built = S->rebuilds != rb0;
     BatchRep &q = B->rep[r];
     if (!S->user_list && S->have_D && q.valid && q.have_prev) {
-      const double adt = std::fabs(q.prev_dt);
+      const double adt = std::max(std::fabs(q.prev_dt), std::fabs(dt));
       const double D = (q.prev_rebuilt ? 0.0 : q.prev_dm) + 2.0 * adt * q.prev_vm;
       const double W = (q.prev_rebuilt ? colour_radius(S) : std::sqrt(q.prev_wm)) - 4.0 * adt * q.prev_vm;
       if (D >= S->skin / 2.0 - 0.01 || W < S->pot.ex_rc + 0.01) {
@@ -2495,7 +2501,7 @@ int batch_step(sl_batch *B, int64_t n, double dt) {
     k0[r] = S->step;
     BSYS(B, r, force_launch<real>(S, S->pos, kModeNext, dt, S->step));
     bool due_unused;
-    BSYS(B, r, wait_predictor(S, S->step, &due_unused));
+    BSYS(B, r, wait_predictor(S, S->step, dt, &due_unused));
     const double *o = S->ring + 8 * (int)(S->step & 3);
     q.prev_dm = q.cur_dm; q.prev_vm = q.cur_vm; q.prev_dt = q.cur_dt; q.prev_wm = q.cur_wm;
     q.prev_rebuilt = q.cur_rebuilt; q.have_prev = q.valid ? 1 : 0;
@@ -2561,7 +2567,7 @@ int batch_step_phased(sl_batch *B, int64_t n, double dt) {
     bool built = S->rebuilds != rb0;
     BatchRep &q = B->rep[r];
     if (!S->user_list && S->have_D && q.valid && q.have_prev) {
-      const double adt = std::fabs(q.prev_dt);
+      const double adt = std::max(std::fabs(q.prev_dt), std::fabs(dt));
       const double D = (q.prev_rebuilt ? 0.0 : q.prev_dm) + 2.0 * adt * q.prev_vm;
       const double W = (q.prev_rebuilt ? colour_radius(S) : std::sqrt(q.prev_wm)) - 4.0 * adt * q.prev_vm;
       if (D >= S->skin / 2.0 - 0.01 || W < S->pot.ex_rc + 0.01) {

@@ -65,3 +65,30 @@ def test_committed_counter_summaries_match_the_sources():
     alg_spin = B.SPIN_BYTES[sl.SL_FP64] * 108000
     alg_force = B.FORCE_BYTES[sl.SL_FP64] * 432000
     assert alg_spin < t < 5 * alg_spin and alg_force < f < 5 * alg_force
+
+
+def test_whole_step_byte_conventions():
+    # the unfused count of one FP64 atom-step: four spin sweeps of 128 B, a
+    # force pass writing F (304 B), kick + drift (120 B), final kick (72 B)
+    B = _bench()
+    sl = B.sl
+    assert B.STEP_BYTES_UNFUSED[sl.SL_FP64] == 1008
+    assert B.STEP_BYTES[sl.SL_FP64] == 4 * 128 + 384 == 896
+
+
+def test_drift_slope_and_standard_error():
+    # a known slope under correlated noise: the estimate is within a few
+    # standard errors, and the error grows with the correlation time
+    import numpy as np
+    B = _bench()
+    rng = np.random.default_rng(3)
+    t = np.linspace(0.0, 10.0, 4000)
+    white = rng.standard_normal(t.size)
+    slow = np.convolve(rng.standard_normal(t.size + 99), np.ones(100) / 10.0, mode="valid")
+    for noise in (white, slow):
+        y = 2.5e-3 * t + 1e-2 * noise
+        s, se, g = B.slope_with_error(t, y)
+        assert abs(s - 2.5e-3) < 4 * se
+    _, se_w, g_w = B.slope_with_error(t, 2.5e-3 * t + 1e-2 * white)
+    _, se_s, g_s = B.slope_with_error(t, 2.5e-3 * t + 1e-2 * slow)
+    assert g_w < 3 and g_s > 20 and se_s > 3 * se_w

@@ -19,6 +19,15 @@ def _print(*a):
     print(*a, flush=True)
 
 
+def _assert_magnetization(o, g, tol=1e-10):
+    # M = sum_i s_i, the second accuracy observable (|M|, Eq. relative_deviation):
+    # each component within tol per atom of the oracle's
+    Mo, Mg = o.magnetization(), g.magnetization()
+    N = len(o.get_state()[2])
+    _print("M oracle", Mo, "gpu", Mg)
+    assert np.abs(Mg - Mo).max() <= tol * N, (Mg, Mo)
+
+
 def test_frozen_lattice_parity_and_exact_energy():
     w = W.spin_frozen(10)                       # 2000 atoms, K = 4
     o = make_oracle(w)
@@ -37,6 +46,7 @@ def test_frozen_lattice_parity_and_exact_energy():
     assert p["ok"], p
     e1 = g.energy()["total"]
     assert abs((e1 - e0) / e0) < 1e-12
+    _assert_magnetization(o, g)
     _, _, s = g.get_state()
     assert np.abs(np.linalg.norm(s, axis=1) - 1).max() < 1e-13
 
@@ -68,6 +78,7 @@ def test_coupled_nve_parity_100_steps(n):
     eo, eg = o.energy(), g.energy()
     for k in eo:
         assert eg[k] == pytest.approx(eo[k], rel=1e-11, abs=1e-11), k
+    _assert_magnetization(o, g)
 
 
 @pytest.mark.parametrize("spin_lanes,force_lanes,small,jcache", [
@@ -117,6 +128,7 @@ def test_langevin_anisotropy_parity():
     p = parity(w, o, g)
     _print("langevin parity", p)
     assert p["ok"], p
+    _assert_magnetization(o, g)
 
 
 def test_neighbor_lists_and_colouring_exact_on_disordered_input():
@@ -195,14 +207,17 @@ def test_thermo_samples_match_oracle_energies():
     w = W.coupled_nve(n=6)
     o = make_oracle(w)
     g = make_gpu(w, thermo_every=10)
-    Es = []
+    Es, Ms = [], []
     for _ in range(5):
         o.step(10, w.dt)
         Es.append(o.energy()["total"])
+        Ms.append(o.magnetization())
     g.step(50, w.dt)
     steps, Eg, M = g.thermo()
     assert list(steps) == [10, 20, 30, 40, 50]
     assert np.allclose(Eg, Es, rtol=1e-11, atol=1e-9)
+    # the sampled M = sum_i s_i of every sample, against the oracle's
+    assert np.abs(np.asarray(M) - np.asarray(Ms)).max() <= 1e-10 * w.N
 
 
 def test_checkpoint_resume():
@@ -270,22 +285,39 @@ def test_fp32_form_error_vs_oracle():
     assert abs(eg - eo) / w.N < 1e-5
 
 
-@pytest.mark.parametrize("shape", [(4, 1, 0, -1), (2, 1, 0, -1), (1, 1, 0, 1)])
-def test_full_size_large_system_sampled_parity(shape):
-    # the 432000-atom workload in the launch shapes the benchmark's autotuner
-    # chooses between (4 spin lanes without the exchange cache is its pick on
-    # MI355X): two FP64 steps (a dual spin launch in each) on the GPU and in
-    # the oracle, every atom compared
+def test_full_size_large_system_sampled_parity():
+    # the 432000-atom workload, every atom compared with the oracle:
+    #  - the shape the benchmark's autotuner picks on MI355X with rows in
+    #    displacement order (1 spin lane, 1 force lane, fused small classes up
+    #    to 512 atoms, no exchange cache) over 10 steps, with M;
+    #  - the other candidate shapes (4 and 2 spin lanes, the cache on) over
+    #    the first 2 steps (a dual spin launch in each step)
     w = W.large_langevin(n=60)
-    g = make_gpu(w)
-    g.set_tuning(*shape)
-    g.step(2, w.dt)
     o = make_oracle(w)
     o.step(2, w.dt)
+    for shape in ((4, 1, 0, -1), (2, 1, 0, -1), (1, 1, 0, 1)):
+        g = make_gpu(w)
+        g.set_tuning(*shape)
+        g.step(2, w.dt)
+        p = parity(w, o, g)
+        _print("432k parity 2 steps", shape, p)
+        assert p["ok"], p
+        g.close()
+    g = make_gpu(w)
+    g.set_tuning(1, 1, 512, -1)
+    assert g.tuning() == dict(spin_lanes=1, force_lanes=1, small_class=512, jcache=-1,
+                              overlap=-1)
+    g.step(4, w.dt)                   # two calls: the call-start force launch too
+    g.step(6, w.dt)
+    o.step(8, w.dt)
     p = parity(w, o, g)
-    _print("432k parity", p)
+    _print("432k parity 10 steps, benchmarked shape", p)
     assert p["ok"], p
     assert g.coloring()[1] == o.coloring()[1] == 4
+    _assert_magnetization(o, g)
+    eo, eg = o.energy(), g.energy()
+    for k in eo:
+        assert eg[k] == pytest.approx(eo[k], rel=1e-10, abs=1e-8), k
 
 
 def test_full_size_widened_step_parity():

@@ -768,3 +768,46 @@ def test_colouring_repair_rule_through_dynamics():
         cc = o.coloring()[0]
         assert np.all(cc[pi] != cc[pj])
     assert checked >= 5 and seen_overflow >= 1 and seen_return >= 1, (checked, seen_overflow, seen_return)
+
+
+# --------------------------------------------------------------------------
+# Rebuild rule across calls that change dt: the decision before the first
+# step of a call takes the larger of the two step lengths, so the list stays
+# valid (no atom more than skin/2 from its build position at any boundary)
+# when a call raises |dt|. One atom in free flight at 10 A/ps among atoms at
+# rest, no interactions that move atoms (exchange with zero amplitude, no
+# Morse), 5 steps of 1 fs, then steps of 12 fs (0.12 A each, under the
+# 0.14 A threshold, so a valid rule exists). Taking the earlier call's dt
+# would let the atom reach 0.17 A before the next rebuild.
+def _free_flight_system():
+    r, box = W.bcc_lattice(4)
+    N = r.shape[0]
+    v = np.zeros((N, 3))
+    v[0] = (10.0, 0.0, 0.0)
+    p = dict(W.EXCHANGE_BJ, ex_alpha=0.0)
+    return O.Oracle(r, v, W.random_unit_spins(N, 1), np.full(N, W.FE_MASS), box, p,
+                    frozen=False, skin=0.3), r
+
+
+def test_rebuild_rule_covers_a_larger_dt_in_the_next_call():
+    o, r0 = _free_flight_system()
+    r_build, prev = r0.copy(), r0.copy()
+    worst = 0.0
+    for dt, n in ((1e-3, 5), (1.2e-2, 6)):
+        for _ in range(n):
+            nb = o.num_rebuilds
+            o.step(1, dt)
+            if o.num_rebuilds != nb:
+                r_build = prev           # built at the boundary before this step
+            r, _, _ = o.get_state()
+            worst = max(worst, np.linalg.norm(r - r_build, axis=1).max())
+            prev = r
+    assert worst <= 0.3 / 2 - 0.01 + 1e-12, worst
+    # the first 12 fs step rebuilt the list at its start (1 initial build,
+    # then one before every 12 fs step: 0.12 A per step leaves no room for two)
+    assert o.num_rebuilds == 1 + 6
+    # control: in one call of constant dt the same rule rebuilds late enough
+    # to keep the earlier pace (no rebuild during the 1 fs steps)
+    o2, _ = _free_flight_system()
+    o2.step(5, 1e-3)
+    assert o2.num_rebuilds == 1
