@@ -374,6 +374,23 @@ int sl_mlp_get_weights(sl_mlp *m, float *params, int n, int where);
 int sl_mlp_eval(sl_mlp *m, const double *r, int64_t P, double *out, int where);
 const char *sl_mlp_last_error(const sl_mlp *m);
 
+/* sl_mlp_eval without any device allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same arguments, output layout and
+ * results (bit for bit) as sl_mlp_eval, for P <= SL_MLP_EVAL_STATIC_MAX
+ * distances (SL_E_ARG beyond). Its staging lives in one library-owned static
+ * device array per GPU (52 bytes per distance, about 1.7 MB), held from the
+ * first call on that GPU until the process ends; no call allocates or frees
+ * device memory. Every call on a GPU reuses that GPU's array: calls that
+ * overlap on one GPU (from other threads or on other streams) race on it.
+ * The handle's device must be the current one (SL_E_ARG otherwise). With
+ * where = SL_DEVICE the call only enqueues work on the handle's stream (r
+ * must be ready on that stream; out is valid once the stream has reached the
+ * end of the call); with SL_HOST it synchronises the stream before
+ * returning. */
+#define SL_MLP_EVAL_STATIC_MAX 32768
+int sl_mlp_eval_static(sl_mlp *m, const double *r, int64_t P, double *out, int where);
+
 /* Use the learned potential for J and the mechanical pair energy of this
  * system (replacing Morse and Bethe-Slater; Zeeman, anisotropy and the bath
  * are kept); NULL restores the analytic potential. FP32 form only. The

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,7 @@ int sl_mlp_create(const sl_mlp_spec *spec, sl_mlp **out) {
   if (!out) return mfail(nullptr, SL_E_ARG, "out is NULL");
   *out = nullptr;
   sl_mlp *m = new sl_mlp();
+  if (hipGetDevice(&m->device) != hipSuccess) m->device = 0;
   if (spec) {
     if (spec->sigma > 0) m->sigma = spec->sigma;
     if (spec->mu_step > 0) m->mu_step = spec->mu_step;
@@ -174,5 +176,107 @@ int sl_mlp_eval(sl_mlp *m, const double *r, int64_t P, double *out, int where) {
 }
 
 const char *sl_mlp_last_error(const sl_mlp *m) { return m ? m->last_err.c_str() : g_mlp_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// sl_mlp_eval without device allocation. Its staging (FP32 distances, the
+// network's FP32 outputs, FP64 outputs or host input) lives in one file-scope
+// device array per GPU, `scratch`, of SL_MLP_EVAL_STATIC_MAX distances:
+//   [0, 4 MAX)         float  r32[MAX]
+//   [4 MAX, 20 MAX)    float4 o4[MAX]
+//   [20 MAX, 52 MAX)   double o64[4 MAX] (also the staging of host input)
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address is resolved once per device with hipGetSymbolAddress and
+// only that address is ever passed to kernels and copies.
+namespace {
+
+constexpr size_t kStaticMax = SL_MLP_EVAL_STATIC_MAX;
+constexpr size_t kStaticBytes = kStaticMax * (4 + 16 + 32);
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's `scratch` (resolved on the first call on
+// the device, with that device current).
+int scratch_address(sl_mlp *m, int dev, unsigned char **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return mfail(m, SL_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (unsigned char *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SL_OK;
+}
+
+__global__ void k_f64_to_f32(const double *src, float *dst, int P) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < P) dst[q] = (float)src[q];
+}
+
+__global__ void k_f32x4_to_f64(const float4 *src, double *dst, int P) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < P) {
+    const float4 o = src[q];
+    dst[4 * (size_t)q] = o.x;
+    dst[4 * (size_t)q + 1] = o.y;
+    dst[4 * (size_t)q + 2] = o.z;
+    dst[4 * (size_t)q + 3] = o.w;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sl_mlp_eval_static(sl_mlp *m, const double *r, int64_t P, double *out, int where) {
+  if (!m || (P > 0 && (!r || !out))) return mfail(m, SL_E_ARG, "NULL argument");
+  if (where != SL_HOST && where != SL_DEVICE) return mfail(m, SL_E_ARG, "bad `where`");
+  if (!m->have_weights) return mfail(m, SL_E_STATE, "no weights set");
+  if (P < 0 || P > (int64_t)kStaticMax)
+    return mfail(m, SL_E_ARG, "P = " + std::to_string(P) + " outside [0, SL_MLP_EVAL_STATIC_MAX = " +
+                                  std::to_string(kStaticMax) + "]");
+  if (P == 0) return SL_OK;
+  int dev = -1;
+  MCHK(m, hipGetDevice(&dev));
+  if (dev != m->device)
+    return mfail(m, SL_E_ARG, "device " + std::to_string(dev) + " is current, the handle's is " +
+                                  std::to_string(m->device));
+  if (dev < 0 || dev >= kMaxDevices) return mfail(m, SL_E_ARG, "device index out of range");
+  unsigned char *base = nullptr;
+  const int rc = scratch_address(m, dev, &base);
+  if (rc) return rc;
+  float *r32 = (float *)base;
+  float4 *o4 = (float4 *)(base + 4 * kStaticMax);
+  double *o64 = (double *)(base + 20 * kStaticMax);
+  const int n = (int)P;
+  const dim3 grid((n + 255) / 256), block(256);
+  const double *src = r;
+  if (where == SL_HOST) {
+    MCHK(m, hipMemcpyAsync(o64, r, sizeof(double) * P, hipMemcpyHostToDevice, m->st));
+    src = o64;
+  }
+  hipLaunchKernelGGL(k_f64_to_f32, grid, block, 0, m->st, src, r32, n);
+  launch_mlp_eval(r32, n, m->w, m->cfg(), m->yc, 0, o4, m->st);
+  if (where == SL_DEVICE) {
+    hipLaunchKernelGGL(k_f32x4_to_f64, grid, block, 0, m->st, o4, out, n);
+    MCHK(m, hipGetLastError());
+    return SL_OK;  // asynchronous on the handle's stream
+  }
+  hipLaunchKernelGGL(k_f32x4_to_f64, grid, block, 0, m->st, o4, o64, n);
+  MCHK(m, hipMemcpyAsync(out, o64, sizeof(double) * 4 * P, hipMemcpyDeviceToHost, m->st));
+  MCHK(m, hipStreamSynchronize(m->st));
+  return SL_OK;
+}
 
 }  // extern "C"

@@ -9,6 +9,7 @@ struct sl_mlp {
   double sigma = 0.4, mu_step = 5.0 / 15.0, sJ = 0.01, sP = 1.0, ex_rc = 3.5, rc = 5.0;
   hipStream_t st = nullptr;
   bool own_stream = false;
+  int device = 0;                       // device current at creation
   float *master = nullptr;              // FP32 master parameters (device)
   sl::MlpDevWeights *w = nullptr;       // BF16 operand copy (device)
   float *yc = nullptr;                  // raw y1(rc), y1'(rc) (device)

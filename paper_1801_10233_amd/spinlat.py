@@ -48,7 +48,7 @@ EXPORTS = [
     "sl_set_mlp_mode", "sl_set_ordering", "sl_set_row_order",
     "sl_get_profile", "sl_last_error",
     "sl_mlp_create", "sl_mlp_destroy", "sl_mlp_set_weights", "sl_mlp_get_weights",
-    "sl_mlp_eval", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
+    "sl_mlp_eval", "sl_mlp_eval_static", "sl_mlp_last_error", "sl_set_mlp", "sl_get_fields",
     "sl_mlp_loss_grad", "sl_mlp_train",
     "sl_batch_create", "sl_batch_destroy", "sl_batch_set_state", "sl_batch_get_state",
     "sl_batch_get_energy", "sl_batch_get_temperatures", "sl_batch_step", "sl_batch_set_lanes", "sl_batch_set_row_order", "sl_batch_get_stats",
@@ -56,6 +56,7 @@ EXPORTS = [
 ]
 
 SL_MLP_NPARAM = 5378
+SL_MLP_EVAL_STATIC_MAX = 32768
 
 
 class sl_params(C.Structure):
@@ -174,6 +175,7 @@ def lib():
         "sl_mlp_set_weights": ([vp, vp, C.c_int, C.c_int], C.c_int),
         "sl_mlp_get_weights": ([vp, vp, C.c_int, C.c_int], C.c_int),
         "sl_mlp_eval": ([vp, vp, C.c_int64, vp, C.c_int], C.c_int),
+        "sl_mlp_eval_static": ([vp, vp, C.c_int64, vp, C.c_int], C.c_int),
         "sl_mlp_last_error": ([vp], C.c_char_p),
         "sl_set_mlp": ([vp, vp], C.c_int),
         "sl_get_fields": ([vp, vp, vp, C.c_int], C.c_int),
@@ -468,6 +470,20 @@ class Mlp:
         r = np.ascontiguousarray(r, dtype=np.float64).ravel()
         out = np.zeros((r.size, 4))
         self._check(lib().sl_mlp_eval(self.h, r.ctypes.data, r.size, out.ctypes.data, SL_HOST))
+        return out
+
+    def eval_static(self, r, out=None):
+        """sl_mlp_eval_static: host arrays (returns a new [P][4] array), or
+        device tensors r (float64, P) and out (float64, P x 4) on the
+        handle's stream (asynchronous)."""
+        if hasattr(r, "data_ptr"):
+            self._check(lib().sl_mlp_eval_static(self.h, r.data_ptr(), r.numel(), out.data_ptr(),
+                                                 SL_DEVICE))
+            return out
+        r = np.ascontiguousarray(r, dtype=np.float64).ravel()
+        out = np.zeros((r.size, 4))
+        self._check(lib().sl_mlp_eval_static(self.h, r.ctypes.data, r.size, out.ctypes.data,
+                                             SL_HOST))
         return out
 
 

@@ -48,3 +48,18 @@ def test_product_package_does_not_reach_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert not bad.search(src), f
+
+
+def test_static_mlp_eval_allocates_nothing():
+    # the no-allocation entry point and its helpers call no device allocator
+    # and take the static array only through its resolved device address
+    src = open(os.path.join(ROOT, "paper_1801_10233_amd", "csrc", "sl_mlp_api.hip")).read()
+    start = src.index("// sl_mlp_eval without device allocation.")
+    body = src[start:]
+    for bad in ("hipMalloc", "hipFree", "hipHostMalloc", "std::vector", "new ", "malloc("):
+        assert bad not in body, bad
+    # `scratch` appears only in its definition and in hipGetSymbolAddress
+    code = re.sub(r"//[^\n]*", "", body)
+    code = re.sub(r'"[^"\n]*"', '""', code)
+    assert re.findall(r"\bscratch\b(?!_)", code) == ["scratch", "scratch"]
+    assert "HIP_SYMBOL(scratch)" in code
