@@ -251,6 +251,33 @@ def mlp_pairwise(w, mlp, steps=50):
                                  frac=round(tflops / MFMA_BF16_PEAK_TFLOPS, 4)))
 
 
+def mlp_part(steps):
+    """The learned potential's kernels alone, for profiling: the per-pair
+    BF16-MFMA table on the 432000-atom workload for `steps` steps, then the
+    loss gradient of one 16000-atom snapshot (forward, tangent and reverse
+    MFMA kernels) twice."""
+    w = W.large_langevin(n=60)
+    mlp = load_mlp()
+    out = dict(pairwise=mlp_pairwise(w, mlp, steps=steps))
+    snap = W.coupled_nve(n=20, T=600.0, spin_seed=5151, vel_seed=5152)
+    snap.r = snap.r + W.thermal_displacements(snap.N, 0.07, 5153)
+    A = sl.system_from_workload(snap)
+    F, hw = A.fields()
+    e = A.energy()
+    A.close()
+    ds = sl.Dataset(snap.box, snap.r[None], snap.s[None], np.array([e["pair"] + e["exchange"]]),
+                    F[None], hw[None])
+    t = []
+    for _ in range(2):
+        sync()
+        t0 = time.perf_counter()
+        loss, _ = sl.mlp_loss_grad(mlp, ds, 0, (1.0, 1.0, 30.0))
+        sync()
+        t.append(time.perf_counter() - t0)
+    out["loss_grad_16000_atoms"] = dict(loss=loss, ms=[round(x * 1e3, 2) for x in t])
+    return out
+
+
 def slope_with_error(t, y):
     """Least-squares slope of y(t) and its standard error, the residuals'
     correlation taken into account by block averaging: the statistical
@@ -275,7 +302,10 @@ def slope_with_error(t, y):
     return float(coef[0]), float(se), float(g)
 
 
-def drift_per_10ps(w, precision, steps, every=10, settle=2000, mlp=None):
+SERIES_DIR = None    # --save-series: where the E(t) series of the drift runs go
+
+
+def drift_per_10ps(w, precision, steps, every=10, settle=2000, mlp=None, tag=None):
     """Least-squares slope of E_total/N against time on the undamped twin,
     scaled to 10 ps, with its block-averaged standard error, over `steps`
     steps after `settle` steps in which the spin and lattice subsystems start
@@ -290,9 +320,19 @@ def drift_per_10ps(w, precision, steps, every=10, settle=2000, mlp=None):
     t = st * w.dt
     slope, se, g = slope_with_error(t, E / w.N)
     S.close()
+    if SERIES_DIR and tag:
+        os.makedirs(SERIES_DIR, exist_ok=True)
+        np.save(os.path.join(SERIES_DIR, f"E_{tag}.npy"), np.stack([t, E / w.N]))
     return dict(drift_eV_per_atom_per_10ps=slope * 10.0, stderr=se * 10.0,
                 E_rms_eV_per_atom=float(np.std(E / w.N)), span_ps=float(t[-1] - t[0]),
                 samples=int(t.size), inefficiency=round(g, 1))
+
+
+def smooth(w):
+    """The workload with the smooth forms on: shifted-force exchange and the
+    symmetric anisotropy split."""
+    w.pot = dict(w.pot, ex_shift=1, aniso_split=1)
+    return w
 
 
 def next_rows(w, steps, warmup, tune, base_value):
@@ -331,6 +371,21 @@ def next_rows(w, steps, warmup, tune, base_value):
         S.close()
     out["sectors"]["grid"] = [16, 16, 16]
     return out
+
+
+def form_throughput(w, precision, steps, warmup, tune, mlp=None):
+    """atom-steps/s of one form on workload w (autotuned shape, median of 3
+    windows)."""
+    S = sl.system_from_workload(w, precision=precision, thermo_every=100)
+    if mlp is not None:
+        S.set_mlp(mlp)
+    S.step(0, w.dt)
+    if tune:
+        S.autotune(TUNE_STEPS, w.dt)
+    S.step(warmup, w.dt)
+    els = sorted(timed_run(S, steps, w.dt)[0] for _ in range(3))
+    S.close()
+    return w.N * steps / els[1]
 
 
 def small_configs(repeats=3):
@@ -399,6 +454,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip FP32 form and drift")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--drift-steps", type=int, default=10000)
+    ap.add_argument("--save-series", metavar="DIR",
+                    help="save the E(t) series of the drift runs as .npy files in DIR")
     ap.add_argument("--drift-validate-steps", type=int, default=100000,
                     help="steps of the 16000-atom undamped drift run per form (0: skip)")
     ap.add_argument("--no-tune", action="store_true",
@@ -411,6 +468,8 @@ def main():
                          "(spin lanes, force lanes, exchange cache 1/-1, split force 1/-1)")
     ap.add_argument("--summarize", nargs="+", metavar="CSV",
                     help="print per-kernel averages of rocprofv3 CSV files and exit")
+    ap.add_argument("--part", choices=["all", "mlp"], default="all",
+                    help="mlp: only the learned potential's kernels (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -418,6 +477,8 @@ def main():
     if args.summarize:
         summarize(args.summarize)
         return
+    global SERIES_DIR
+    SERIES_DIR = args.save_series
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this "
               "library: a large system would shard spatially into bricks with halo exchange, "
@@ -427,6 +488,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.part == "mlp":
+        print(json.dumps(mlp_part(args.steps)), flush=True)
         return
 
     prec = sl.SL_FP64 if args.precision == "fp64" else sl.SL_FP32
@@ -548,14 +612,36 @@ def main():
                       "every 10 steps, least-squares slope scaled to 10 ps, standard error by "
                       "block averaging of the residuals")
         if args.drift_validate_steps > 0:
-            # the same physics at 16 000 atoms over the whole 10 ps
-            small = W.large_langevin(n=20, nve=True)
+            # the same physics at 16 000 atoms over the whole 10 ps: the
+            # literal form, the literal cut without anisotropy (diagnostic),
+            # and the smooth forms in FP64, FP32 and with the learned potential
+            n16, ns = 20, args.drift_validate_steps
+            lit = W.large_langevin(n=n16, nve=True)
+            nok = W.large_langevin(n=n16, nve=True)
+            nok.pot = dict(nok.pot, aniso_K=0.0)
+            sm = smooth(W.large_langevin(n=n16, nve=True))
             out["forms"]["drift_16k_10ps"] = dict(
-                fp64=drift_per_10ps(small, sl.SL_FP64, args.drift_validate_steps),
-                fp32=drift_per_10ps(small, sl.SL_FP32, args.drift_validate_steps),
-                mlp=drift_per_10ps(small, sl.SL_FP32, args.drift_validate_steps, mlp=mlp),
-                run=f"undamped, bcc 20^3 cells (16000 atoms), 2000 settling steps then "
-                    f"{args.drift_validate_steps} steps")
+                fp64_literal=drift_per_10ps(lit, sl.SL_FP64, ns, tag="fp64_literal"),
+                fp64_literal_no_anisotropy=drift_per_10ps(nok, sl.SL_FP64, ns, tag="fp64_K0"),
+                fp64_smooth=drift_per_10ps(sm, sl.SL_FP64, ns, tag="fp64_smooth"),
+                fp32_smooth=drift_per_10ps(sm, sl.SL_FP32, ns, tag="fp32_smooth"),
+                mlp_smooth=drift_per_10ps(sm, sl.SL_FP32, ns, mlp=mlp, tag="mlp_smooth"),
+                run=f"undamped, bcc {n16}^3 cells ({lit.N} atoms), 2000 settling steps then "
+                    f"{ns} steps; smooth = shifted-force exchange + symmetric anisotropy split")
+            # throughput of the smooth forms on the benchmark workload
+            sw = smooth(W.large_langevin(n=args.n))
+            v64 = form_throughput(sw, sl.SL_FP64, args.steps, args.warmup, not args.no_tune)
+            v32 = form_throughput(sw, sl.SL_FP32, args.steps, args.warmup, not args.no_tune)
+            vml = form_throughput(sw, sl.SL_FP32, args.steps, args.warmup, not args.no_tune,
+                                  mlp=mlp)
+            d = out["forms"]["drift_16k_10ps"]
+            out["forms"]["smooth_at_drift"] = dict(
+                fp64=dict(value=round(v64, 1), drift=d["fp64_smooth"]),
+                fp32=dict(value=round(v32, 1), speedup_vs_fp64=round(v32 / v64, 3),
+                          drift=d["fp32_smooth"]),
+                mlp=dict(value=round(vml, 1), speedup_vs_fp64=round(vml / v64, 3),
+                         drift=d["mlp_smooth"]),
+                bar_eV_per_atom_per_10ps=1e-6)
         log("forms:", json.dumps(out["forms"]))
         out["small_configs"] = small_configs()
         log("small configs:", json.dumps(out["small_configs"]))

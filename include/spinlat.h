@@ -110,7 +110,19 @@ typedef struct {
  *    phi(r) = (r - eam_c)^2 (eam_c0 + eam_c1 r + eam_c2 r^2) for r < eam_c.
  *    Forces take two passes (densities, then the gather with
  *    F'(rho_i) + F'(rho_j)); the list radius covers eam_d and eam_c. Its
- *    energy is reported in `pair`. Not with a learned pair potential. */
+ *    energy is reported in `pair`. Not with a learned pair potential.
+ *  - Optional smooth forms (both 0 by default, the paper's literal form):
+ *    ex_shift = 1 shifts the exchange in r^2,
+ *    J(r) - J(ex_rc) - (r^2 - ex_rc^2) J'(ex_rc) / (2 ex_rc) for r < ex_rc,
+ *    so J and J' are continuous at the cutoff (Eq. BSfunction cuts J with a step, which
+ *    changes the energy by J(ex_rc) s_i.s_j at every crossing); a learned J
+ *    takes the same rule. aniso_split = 1 applies each single-spin update
+ *    without a spin bath as A(h/2) X(h) A(h/2): A rotates about n by the
+ *    anisotropy's own flow (s.n is constant under it), X about the rest of
+ *    omega_i. Taking the whole omega_i at the spin's value before the update
+ *    (the default) loses exactly K (delta s.n)^2 of energy per update; the
+ *    split form is time-reversible and keeps the energy without drift.
+ *    With the spin bath on, the anisotropy stays in omega_i. */
 typedef struct {
     int morse_on;
     double morse_D, morse_alpha, morse_r0, morse_rc;
@@ -129,6 +141,8 @@ typedef struct {
     double dmi_n[3];
     int eam_on;
     double eam_A, eam_d, eam_beta, eam_c, eam_c0, eam_c1, eam_c2;
+    int ex_shift;
+    int aniso_split;
 } sl_potential;
 
 /* Energies in eV: kinetic sum_i m v^2/2, pair, exchange (the magnetic pair

@@ -148,6 +148,14 @@ void mlp_eval(const mlp_cfg *c, const double *p, double r, double out[4])
     out[0] = J; out[1] = dJ; out[2] = P; out[3] = dP;
 }
 
+void mlp_raw(const mlp_cfg *c, const double *p, double r, double y[2], double dy[2])
+{
+    mlp_tape t;
+    raw_forward(c, p, r, &t);
+    y[0] = t.y[0]; y[1] = t.y[1];
+    dy[0] = t.dy[0]; dy[1] = t.dy[1];
+}
+
 /* Gradient of a linear functional of the physical outputs at a set of
  * distances: L = sum_q (aJ_q J(r_q) + adJ_q J'(r_q) + aP_q phi(r_q) +
  * adP_q phi'(r_q)). The shifted-force terms of phi bring in y1(rc) and

@@ -79,18 +79,38 @@ struct orc_sys {
  * BSfunction): J(r) = 4 alpha u (1 - gamma u) exp(-u), u = (r/delta)^2, cut
  * by a Heaviside step at R_c. dJ/dr = (8 alpha r/delta^2) exp(-u)
  * (1 - (1+2 gamma) u + gamma u^2) inside the cutoff. */
+static double bs_exchange(const orc_pot *p, double r, double *dJdr)
+{
+    double u = (r / p->ex_delta) * (r / p->ex_delta);
+    double e = exp(-u);
+    *dJdr = 8.0 * p->ex_alpha * r / (p->ex_delta * p->ex_delta) * e *
+            (1.0 - (1.0 + 2.0 * p->ex_gamma) * u + p->ex_gamma * u * u);
+    return 4.0 * p->ex_alpha * u * (1.0 - p->ex_gamma * u) * e;
+}
+
+/* The printed cut leaves a step of J(R_c) in the pair energy, which a
+ * symplectic integrator cannot follow: each crossing of R_c changes the
+ * total energy by J(R_c) s_i.s_j. With ex_shift set the exchange is
+ * shifted in r^2 inside the cutoff,
+ *   J(r) - J(R_c) - (r^2 - R_c^2) J'(R_c) / (2 R_c),
+ * which vanishes at R_c together with its derivative J'(r) - r J'(R_c)/R_c
+ * (the Morse rule in r, written in r^2 so that it needs no square root). */
 double orc_J(const orc_pot *p, double r, double *dJdr)
 {
     if (!(r < p->ex_rc) || p->ex_alpha == 0.0) {
         if (dJdr) *dJdr = 0.0;
         return 0.0;
     }
-    double u = (r / p->ex_delta) * (r / p->ex_delta);
-    double e = exp(-u);
-    double J = 4.0 * p->ex_alpha * u * (1.0 - p->ex_gamma * u) * e;
-    if (dJdr)
-        *dJdr = 8.0 * p->ex_alpha * r / (p->ex_delta * p->ex_delta) * e *
-                (1.0 - (1.0 + 2.0 * p->ex_gamma) * u + p->ex_gamma * u * u);
+    double dJ;
+    double J = bs_exchange(p, r, &dJ);
+    if (p->ex_shift) {
+        double dJc;
+        const double rc = p->ex_rc;
+        double Jc = bs_exchange(p, rc, &dJc);
+        J -= Jc + (r * r - rc * rc) * dJc / (2.0 * rc);
+        dJ -= r * dJc / rc;
+    }
+    if (dJdr) *dJdr = dJ;
     return J;
 }
 
@@ -149,6 +169,14 @@ static void pair_terms(const orc_sys *S, double r, double *J, double *dJ, double
         double o[4];
         mlp_eval(&S->mcfg, S->mparams, r, o);
         *J = o[0]; *dJ = o[1]; *V = o[2]; *dV = o[3];
+        if (S->pot.ex_shift && r < S->mcfg.ex_rc) {
+            /* the shift of orc_J on the learned J = sJ y0 */
+            double yc[2], dyc[2];
+            const double rc = S->mcfg.ex_rc;
+            mlp_raw(&S->mcfg, S->mparams, rc, yc, dyc);
+            *J -= S->mcfg.sJ * (yc[0] + (r * r - rc * rc) * dyc[0] / (2.0 * rc));
+            *dJ -= S->mcfg.sJ * r * dyc[0] / rc;
+        }
         return;
     }
     *J = orc_J(&S->pot, r, dJ);
@@ -910,6 +938,28 @@ static void update_spin(orc_sys *S, int i, double h, int sub, const double w[3])
     const orc_pot *p = &S->pot;
     double *si = S->s + 3 * i;
     double W[3];
+    if (p->aniso_split && p->aniso_K != 0.0 && !(p->lambda > 0.0)) {
+        /* Symmetric split of the single-spin propagator: A(h/2) X(h) A(h/2).
+         * A is the flow of the anisotropy alone, ds/dt = (2K/hbar)(s.n) n x s:
+         * a rotation about n that keeps s.n, so its rate is fixed by the spin
+         * it starts from and A(-h/2) undoes A(h/2) exactly. X rotates about
+         * omega without its anisotropy term, which does not depend on s_i.
+         * The composition is time-reversible; taking the whole omega at the
+         * spin's value before the update is not, and loses exactly
+         * K (delta s.n)^2 of energy per update. */
+        double sn = dot3(si, p->aniso_n);
+        double Wx[3], Wa[3], out[3];
+        for (int a = 0; a < 3; ++a)
+            Wx[a] = w[a] - 2.0 * p->aniso_K * sn * p->aniso_n[a] / ORC_HBAR;
+        for (int a = 0; a < 3; ++a) Wa[a] = 2.0 * p->aniso_K * sn * p->aniso_n[a] / ORC_HBAR;
+        orc_cayley(si, Wa, 0.5 * h, out);
+        orc_cayley(out, Wx, h, si);
+        sn = dot3(si, p->aniso_n);
+        for (int a = 0; a < 3; ++a) Wa[a] = 2.0 * p->aniso_K * sn * p->aniso_n[a] / ORC_HBAR;
+        orc_cayley(si, Wa, 0.5 * h, out);
+        for (int a = 0; a < 3; ++a) si[a] = out[a];
+        return;
+    }
     if (p->lambda > 0.0) {
         double lam = p->lambda;
         double DS = lam * (1.0 + lam * lam) * ORC_KB * p->temperature / ORC_HBAR;

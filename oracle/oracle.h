@@ -51,6 +51,17 @@ typedef struct {
      * phi(r) = (r-c)^2 (c0 + c1 r + c2 r^2) (r < c) */
     int eam_on;
     double eam_A, eam_d, eam_beta, eam_c, eam_c0, eam_c1, eam_c2;
+    /* optional readings where the paper's literal form breaks exact energy
+     * conservation (both off by default):
+     * ex_shift = 1: J(r) shifted in r^2,
+     *   J(r) - J(rc) - (r^2 - rc^2) J'(rc)/(2 rc) for r < rc, so J and J'
+     *   are continuous at the cutoff (the learned J likewise);
+     * aniso_split = 1: without a spin bath, each single-spin update splits
+     *   the uniaxial anisotropy off symmetrically, A(h/2) X(h) A(h/2), A the
+     *   rotation about n of the anisotropy flow (s.n conserved) and X the
+     *   rotation about the rest of omega (which does not depend on s_i). */
+    int ex_shift;
+    int aniso_split;
 } orc_pot;
 
 /* Key tag of the lattice-noise Philox stream: key = seed XOR this value. */

@@ -231,6 +231,13 @@ void make_potconst(sl_system *S) {
   c.eInvD2 = 1.0 / (p.ex_delta * p.ex_delta);
   c.eRc2 = p.ex_rc * p.ex_rc;
   c.eA8InvD2 = 8.0 * p.ex_alpha / (p.ex_delta * p.ex_delta);
+  if (p.ex_shift && p.ex_rc > 0.0) {
+    const double u = p.ex_rc * p.ex_rc / (p.ex_delta * p.ex_delta), e = std::exp(-u);
+    const double dJc = c.eA8InvD2 * p.ex_rc * e * (1.0 - (1.0 + 2.0 * p.ex_gamma) * u + p.ex_gamma * u * u);
+    c.eJc = 4.0 * p.ex_alpha * u * (1.0 - p.ex_gamma * u) * e;
+    c.eJq = dJc / (2.0 * p.ex_rc);
+    c.eJr = dJc / p.ex_rc;
+  }
   for (int d = 0; d < 3; ++d) {
     c.zB[d] = p.zeeman_g * kMuB * p.B[d];
     c.zw[d] = c.zB[d] / kHbar;
@@ -239,6 +246,7 @@ void make_potconst(sl_system *S) {
   c.aK = p.aniso_K;
   c.aK2h = 2.0 * p.aniso_K / kHbar;
   c.aniso_on = p.aniso_K != 0.0 ? 1 : 0;
+  c.aniso_split = (c.aniso_on && p.aniso_split && !(p.lambda > 0.0)) ? 1 : 0;
   c.langevin = p.lambda > 0.0 ? 1 : 0;
   c.lam = p.lambda;
   c.lamfac = 1.0 / (1.0 + p.lambda * p.lambda);
@@ -301,8 +309,12 @@ SysView<real> view(sl_system *S, int posbuf) {
   const bool jc_use = (!S->mlp || S->mlp_mode == SL_MLP_SPLINE) && S->jcache > 0 && !S->pc.soc_on;
   v.jc = (jc_use && S->jc_ok[posbuf]) ? (const real *)S->jc[posbuf] : nullptr;
   v.eam = S->pc.eam_on ? S->eam : nullptr;
-  if (S->mlp && S->mlp_mode == SL_MLP_SPLINE) v.spl = S->mlp->spline_view();
-  else if (S->mlp) v.tab = S->tab[posbuf];
+  if (S->mlp && S->mlp_mode == SL_MLP_SPLINE) {
+    v.spl = S->mlp->spline_view();
+    v.spl.jshift = S->pot.ex_shift ? 1 : 0;
+  } else if (S->mlp) {
+    v.tab = S->tab[posbuf];
+  }
   return v;
 }
 
@@ -563,7 +575,9 @@ int ensure_table(sl_system *S, int b) {
   T.tab = S->tab[b];
   {
     ProfScope ps(S, 3, (double)S->npair);
-    launch_mlp_table(T, S->mlp->w, S->mlp->cfg(), S->mlp->yc, S->st);
+    MlpCfgDev cfg = S->mlp->cfg();
+    cfg.jshift = S->pot.ex_shift ? 1 : 0;
+    launch_mlp_table(T, S->mlp->w, cfg, S->mlp->yc, S->st);
   }
   S->tab_ok[b] = true;
   return SL_OK;

@@ -49,12 +49,16 @@ struct PotConst {
   double mMc, mdMc, mRc;  // shifted-force offsets M(rc), M'(rc); 0 if plain
   int ex_on;
   double eA4, eG, eInvD2, eRc2, eA8InvD2;  // 4 alpha, gamma, 1/delta^2, rc^2, 8 alpha/delta^2
+  // shifted exchange J(r) - eJc - (r^2 - rc^2) eJq, derivative J'(r) - r eJr,
+  // eJc = J(rc), eJq = J'(rc)/(2 rc), eJr = J'(rc)/rc; all three 0 when off
+  double eJc, eJq, eJr;
   double zw[3];       // g mu_B B / hbar, rad/ps
   double zB[3];       // g mu_B B, eV (energy)
   double aK;          // K, eV
   double aK2h;        // 2K/hbar
   double an[3];
   int aniso_on;
+  int aniso_split;    // symmetric anisotropy split of the update (no bath)
   int langevin;
   double lam, lamfac;  // lambda, 1/(1+lambda^2)
   int lat_on;          // lattice bath
@@ -73,6 +77,16 @@ struct PotConst {
   double fA, fd, fbeta, fc, fc0, fc1, fc2, fd2, fcc2;  // fd2 = d^2, fcc2 = c^2
 };
 
+// Exchange J(r) at r^2 < rc^2 (Eq. BSfunction), less the shift in r^2 (its
+// constants are 0 unless the shifted form is on, so the plain form's value is
+// unchanged bit for bit). `real` sets the precision of the exp.
+template <typename real>
+__device__ __forceinline__ real exch_J(const PotConst &P, double r2) {
+  const real u = (real)(r2 * P.eInvD2);
+  const real J = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+  return J - ((real)P.eJc + (real)(r2 - P.eRc2) * (real)P.eJq);
+}
+
 // Key tag of the lattice-noise Philox stream (key = seed ^ tag).
 constexpr uint64_t kLatticeKeyTag = 0x6C61747469636521ull;
 
@@ -88,6 +102,8 @@ struct SplineView {
   float sJ, sP;      // output scales
   float y1c, d1c;    // raw y1(rc), y1'(rc) (shifted-force constants)
   float exrc, rc;    // cuts of J (Heaviside) and phi
+  int jshift;        // J in shifted-force form at exrc (the potential's ex_shift)
+  float y0c, d0c;    // raw y0(exrc), y0'(exrc) of the spline
 };
 
 // (J, J', phi, phi') at r from the spline (cut and shifted-force rules as
@@ -107,8 +123,9 @@ __device__ __forceinline__ float4 spline_phys(const SplineView &s, float r) {
   const float d1 = g00 * (a.z - b.z) * s.idr + g10 * a.w + g11 * b.w;
   float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
   if (r < s.exrc) {
-    o.x = s.sJ * y0;
-    o.y = s.sJ * d0;
+    o.x = s.jshift ? s.sJ * (y0 - s.y0c - (r * r - s.exrc * s.exrc) * s.d0c / (2.0f * s.exrc))
+                   : s.sJ * y0;
+    o.y = s.jshift ? s.sJ * (d0 - r * s.d0c / s.exrc) : s.sJ * d0;
   }
   if (r < s.rc) {
     o.z = s.sP * (y1 - s.y1c - (r - s.rc) * s.d1c);

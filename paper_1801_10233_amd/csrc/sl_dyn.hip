@@ -85,9 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_jcache(SysView<real> S, PotConst P, 
       if (SPL) {  // learned potential (spline form): J with its own cut
         out[(size_t)k * S.ld + i] = (real)spline_phys(S.spl, (float)sqrt(r2)).x;
       } else {
-        const real u = (real)(r2 * P.eInvD2);
-        const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
-        out[(size_t)k * S.ld + i] = r2 < rs2 ? Jc : (real)0;
+        out[(size_t)k * S.ld + i] = r2 < rs2 ? exch_J<real>(P, r2) : (real)0;
       }
     }
   }

@@ -25,6 +25,7 @@ struct __attribute__((aligned(16))) MlpDevWeightsT {
 
 struct MlpCfgDev {
   float inv_sigma, mu_step, sJ, sP, ex_rc, rc;
+  int jshift;  // J in shifted-force form at ex_rc (a system's ex_shift)
 };
 
 struct MlpTableArgs {

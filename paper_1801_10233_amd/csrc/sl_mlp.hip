@@ -40,7 +40,19 @@ __host__ __device__ inline int l2_unit(int kb, int h, int e) {
   return 32 * (kb >> 1) + 16 * (kb & 1) + 8 * (e >> 2) + 4 * h + (e & 3);
 }
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// Logistic sigmoid with the hardware reciprocal (about 1 ulp): the IEEE
+// division took ten instructions per unit, the largest share of the VALU
+// work of the per-pair network (the result feeds BF16 operands).
+__device__ __forceinline__ float sigm(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
+// silu(z) = z s and its derivative s + z s (1 - s) = s + a - a s, s = sigm(z).
+__device__ __forceinline__ void silu_d(float z, float &a, float &da) {
+  const float s = sigm(z);
+  a = z * s;
+  da = fmaf(-a, s, s + a);
+}
 
 // Swizzle FP32 master parameters (layout W1[64x16], c1, W2[64x64], c2,
 // W3[2x64], c3) into the MFMA operand layout.
@@ -69,6 +81,15 @@ __global__ void k_mlp_swizzle(const float *p, MlpDevWeights *w) {
 // All 64 lanes must call it; lanes j and j+32 evaluate the same pair.
 __device__ __forceinline__ float4 mlp_tile(const MlpDevWeights &w, const MlpCfgDev &c, float r) {
   const int l = threadIdx.x & 63, h = l >> 5;
+  // An opaque zero added to the bias and layer-3 indices: it keeps those LDS
+  // reads inside the caller's tile loop. Hoisted out of it they held 128
+  // registers per lane and left one wave per SIMD.
+  int lo = 0;
+  asm volatile("" : "+s"(lo));
+  // lane half h holds rows 8q + 4h + (0..3) of each 32-row tile (c_row):
+  // float4 q of tile t sits at float4 index 8t + 2q + h
+  const float4 *c1p = (const float4 *)w.c1 + h + lo, *c2p = (const float4 *)w.c2 + h + lo;
+  const float4 *w30 = (const float4 *)w.W3[0] + h + lo, *w31 = (const float4 *)w.W3[1] + h + lo;
   bf16x8 bv, bd;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -82,10 +103,12 @@ __device__ __forceinline__ float4 mlp_tile(const MlpDevWeights &w, const MlpCfgD
   for (int t = 0; t < 2; ++t) {
     const bf16x8 a = *(const bf16x8 *)&w.W1s[t][l][0];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      z1[t][v] = w.c1[32 * t + c_row(v, h)];
-      d1[t][v] = 0.0f;
+    for (int q = 0; q < 4; ++q) {
+      const float4 b = c1p[8 * t + 2 * q];
+      z1[t][4 * q] = b.x; z1[t][4 * q + 1] = b.y; z1[t][4 * q + 2] = b.z; z1[t][4 * q + 3] = b.w;
     }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) d1[t][v] = 0.0f;
     z1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, z1[t], 0, 0, 0);
     d1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bd, d1[t], 0, 0, 0);
   }
@@ -95,19 +118,22 @@ __device__ __forceinline__ float4 mlp_tile(const MlpDevWeights &w, const MlpCfgD
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const float z = z1[t][v], s = sigm(z);
+      float a, da;
+      silu_d(z1[t][v], a, da);
       const int kb = 2 * t + (v >> 3), e = v & 7;
-      av[kb][e] = (__bf16)(z * s);
-      ad[kb][e] = (__bf16)(s * (1.0f + z * (1.0f - s)) * d1[t][v]);
+      av[kb][e] = (__bf16)a;
+      ad[kb][e] = (__bf16)(da * d1[t][v]);
     }
   f32x16 z2[2], d2[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      z2[t][v] = w.c2[32 * t + c_row(v, h)];
-      d2[t][v] = 0.0f;
+    for (int q = 0; q < 4; ++q) {
+      const float4 b = c2p[8 * t + 2 * q];
+      z2[t][4 * q] = b.x; z2[t][4 * q + 1] = b.y; z2[t][4 * q + 2] = b.z; z2[t][4 * q + 3] = b.w;
     }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) d2[t][v] = 0.0f;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
       const bf16x8 a = *(const bf16x8 *)&w.W2s[t][kb][l][0];
@@ -119,14 +145,19 @@ __device__ __forceinline__ float4 mlp_tile(const MlpDevWeights &w, const MlpCfgD
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float z = z2[t][v], s = sigm(z);
-      const float a2 = z * s, da2 = s * (1.0f + z * (1.0f - s)) * d2[t][v];
-      const int u = 32 * t + c_row(v, h);
-      y0 += w.W3[0][u] * a2;
-      y1 += w.W3[1][u] * a2;
-      dy0 += w.W3[0][u] * da2;
-      dy1 += w.W3[1][u] * da2;
+    for (int q = 0; q < 4; ++q) {
+      const float4 u0 = w30[8 * t + 2 * q], u1 = w31[8 * t + 2 * q];
+      const float a0[4] = {u0.x, u0.y, u0.z, u0.w}, a1[4] = {u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float a2, da2;
+        silu_d(z2[t][4 * q + e], a2, da2);
+        da2 *= d2[t][4 * q + e];
+        y0 += a0[e] * a2;
+        y1 += a1[e] * a2;
+        dy0 += a0[e] * da2;
+        dy1 += a1[e] * da2;
+      }
     }
   y0 += __shfl_xor(y0, 32, 64);
   y1 += __shfl_xor(y1, 32, 64);
@@ -135,13 +166,16 @@ __device__ __forceinline__ float4 mlp_tile(const MlpDevWeights &w, const MlpCfgD
   return make_float4(y0 + w.c3[0], dy0, y1 + w.c3[1], dy1);
 }
 
-// Physical outputs from the raw ones (cut and shifted-force rules).
+// Physical outputs from the raw ones (cut and shifted-force rules); yc holds
+// y1(rc), y1'(rc), y0(ex_rc), y0'(ex_rc).
 __device__ __forceinline__ float4 mlp_physical(const MlpCfgDev &c, const float *yc, float r,
                                                float4 y) {
   float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
   if (r < c.ex_rc) {
-    o.x = c.sJ * y.x;
-    o.y = c.sJ * y.y;
+    // shifted J: y0(r) - y0(ex_rc) - (r^2 - ex_rc^2) y0'(ex_rc) / (2 ex_rc)
+    o.x = c.jshift ? c.sJ * (y.x - yc[2] - (r * r - c.ex_rc * c.ex_rc) * yc[3] / (2.0f * c.ex_rc))
+                   : c.sJ * y.x;
+    o.y = c.jshift ? c.sJ * (y.y - r * yc[3] / c.ex_rc) : c.sJ * y.y;
   }
   if (r < c.rc) {
     o.z = c.sP * (y.z - yc[0] - (r - c.rc) * yc[1]);
@@ -179,7 +213,7 @@ __global__ __launch_bounds__(256) void k_mlp_eval(const float *r, int P, const M
 
 // Per-pair table for the dynamics: for every list entry (i, k) with j > i,
 // the outputs at r_ij are written to the entry and to its mirror (j, k').
-__global__ __launch_bounds__(256) void k_mlp_table(MlpTableArgs A, const MlpDevWeights *wg,
+__global__ __launch_bounds__(256, 2) void k_mlp_table(MlpTableArgs A, const MlpDevWeights *wg,
                                                    MlpCfgDev c, const float *yc) {
   __shared__ MlpDevWeights w;
   stage_weights(w, wg);
@@ -644,6 +678,8 @@ __global__ void k_fields(SysView<real> S, PotConst P, FieldArgs A) {
         const double u = r2 * P.eInvD2, eu = exp(-u);
         J = P.eA4 * u * (1.0 - P.eG * u) * eu;
         dJ = P.eA8InvD2 * r * eu * (1.0 - (1.0 + 2.0 * P.eG) * u + P.eG * u * u);
+        J -= P.eJc + (r2 - P.eRc2) * P.eJq;
+        dJ -= r * P.eJr;
       }
       if (P.morse_on && r2 < P.mRc2) {
         const double ex = exp(-P.mA * (r - P.mR0));

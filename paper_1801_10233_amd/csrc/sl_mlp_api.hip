@@ -1,6 +1,7 @@
 // sl_mlp_api.hip -- C ABI of the per-pair learned potential (sl_mlp_*).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -95,12 +96,15 @@ int sl_mlp_destroy(sl_mlp *m) {
 int mlp_refresh(sl_mlp *m) {
   launch_mlp_swizzle(m->master, m->w, m->st);
   launch_mlp_swizzle_t(m->master, m->wt, m->st);
-  // raw outputs at r = rc -> yc = (y1(rc), y1'(rc))
-  float rc = (float)m->rc;
+  // raw outputs at r = rc and r = ex_rc -> yc = (y1(rc), y1'(rc), y0(ex_rc),
+  // y0'(ex_rc)): the shifted-force constants of phi and of a shifted J
+  const float rr[2] = {(float)m->rc, (float)m->ex_rc};
   float *d_r = (float *)(m->scratch4 + 32);
-  MCHK(m, hipMemcpyAsync(d_r, &rc, sizeof(float), hipMemcpyHostToDevice, m->st));
-  launch_mlp_eval(d_r, 1, m->w, m->cfg(), m->yc, 1, m->scratch4, m->st);
+  MCHK(m, hipMemcpyAsync(d_r, rr, sizeof(rr), hipMemcpyHostToDevice, m->st));
+  launch_mlp_eval(d_r, 2, m->w, m->cfg(), m->yc, 1, m->scratch4, m->st);
   MCHK(m, hipMemcpyAsync(m->yc, (float *)m->scratch4 + 2, 2 * sizeof(float), hipMemcpyDeviceToDevice, m->st));
+  MCHK(m, hipMemcpyAsync(m->yc + 2, (float *)(m->scratch4 + 1), 2 * sizeof(float),
+                         hipMemcpyDeviceToDevice, m->st));
   // spline table: the master network in FP64 on the grid; its last point is
   // rc, which gives the shifted-force constants of the spline form
   const double dr = (m->rc - sl_mlp::kSplineR0) / (sl_mlp::kSplinePoints - 1);
@@ -109,9 +113,24 @@ int mlp_refresh(sl_mlp *m) {
   float4 last;
   MCHK(m, hipMemcpyAsync(&last, m->spl + sl_mlp::kSplinePoints - 1, sizeof(float4),
                          hipMemcpyDeviceToHost, m->st));
+  // the spline's y0 and y0' at ex_rc (its cubic Hermite interpolant there),
+  // the constants of a shifted J in the spline form
+  double u = (m->ex_rc - sl_mlp::kSplineR0) / dr;
+  u = std::min(std::max(u, 0.0), (double)(sl_mlp::kSplinePoints - 1));
+  const int k = std::min((int)u, sl_mlp::kSplinePoints - 2);
+  float4 ab[2];
+  MCHK(m, hipMemcpyAsync(ab, m->spl + k, 2 * sizeof(float4), hipMemcpyDeviceToHost, m->st));
   MCHK(m, hipStreamSynchronize(m->st));
   m->spl_yc[0] = last.z;
   m->spl_yc[1] = last.w;
+  {
+    const float x = (float)(u - k), x2 = x * x, x3 = x2 * x, fdr = (float)dr, idr = (float)(1.0 / dr);
+    const float h00 = 2.0f * x3 - 3.0f * x2 + 1.0f, h10 = x3 - 2.0f * x2 + x;
+    const float h01 = 3.0f * x2 - 2.0f * x3, h11 = x3 - x2;
+    const float g00 = 6.0f * (x2 - x), g10 = 3.0f * x2 - 4.0f * x + 1.0f, g11 = 3.0f * x2 - 2.0f * x;
+    m->spl_j0[0] = h00 * ab[0].x + h01 * ab[1].x + fdr * (h10 * ab[0].y + h11 * ab[1].y);
+    m->spl_j0[1] = g00 * (ab[0].x - ab[1].x) * idr + g10 * ab[0].y + g11 * ab[1].y;
+  }
   m->have_weights = true;
   return SL_OK;
 }

@@ -24,6 +24,7 @@ struct sl_mlp {
   static constexpr double kSplineR0 = 0.5;  // A; closer pairs take the end value
   float4 *spl = nullptr;
   float spl_yc[2] = {0.f, 0.f};             // spline's y1(rc), y1'(rc)
+  float spl_j0[2] = {0.f, 0.f};             // spline's y0(ex_rc), y0'(ex_rc)
   std::string last_err;
   sl::SplineView spline_view() const {
     sl::SplineView v;
@@ -38,6 +39,9 @@ struct sl_mlp {
     v.d1c = spl_yc[1];
     v.exrc = (float)ex_rc;
     v.rc = (float)rc;
+    v.jshift = 0;  // set by the system that uses it
+    v.y0c = spl_j0[0];
+    v.d0c = spl_j0[1];
     return v;
   }
   sl::MlpCfgDev cfg() const {
@@ -48,6 +52,7 @@ struct sl_mlp {
     c.sP = (float)sP;
     c.ex_rc = (float)ex_rc;
     c.rc = (float)rc;
+    c.jshift = 0;  // set by the system that uses it
     return c;
   }
 };

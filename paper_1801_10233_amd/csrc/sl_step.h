@@ -13,6 +13,22 @@
 
 namespace sl {
 
+// Cayley rotation of Sec. 3 about w with step h, in place (an exact
+// rotation by 2 atan(h|w|/2); |s| is kept in exact arithmetic).
+template <typename real>
+__device__ __forceinline__ void cayley_rot(real &sx, real &sy, real &sz, real wx, real wy, real wz,
+                                           real h) {
+  const real cx = wy * sz - wz * sy, cy = wz * sx - wx * sz, cz = wx * sy - wy * sx;
+  const real ws = wx * sx + wy * sy + wz * sz;
+  const real w2 = wx * wx + wy * wy + wz * wz;
+  const real q = h * h * (real)0.25;
+  const real inv = (real)1 / ((real)1 + q * w2);
+  const real nx = (sx + h * cx + q * ((real)2 * wx * ws - w2 * sx)) * inv;
+  const real ny = (sy + h * cy + q * ((real)2 * wy * ws - w2 * sy)) * inv;
+  const real nz = (sz + h * cz + q * ((real)2 * wz * ws - w2 * sz)) * inv;
+  sx = nx; sy = ny; sz = nz;
+}
+
 // ---------------------------------------------------------------------------
 // Spin colour phase. For every atom i of one class (no two of them
 // interact): omega_i = (1/hbar)[sum_j J(r_ij) s_j + g mu_B B + 2K(s_i.n)n]
@@ -29,9 +45,18 @@ namespace sl {
 // Neighbour slots one lane gathers per round of the spin phase: with one or
 // two lanes per atom the first round covers 16 list slots (the whole spin
 // segment of bcc at the exchange cutoff, 14 entries) in one go.
-template <int LANES>
+template <int LANES, int MLP = 0>
 struct SpinChunk {
   static constexpr int value = LANES >= 8 ? 2 : (LANES >= 4 ? 4 : 8);
+};
+// The spin-orbit variant holds a field vector per slot besides the
+// coefficient, and its dual form a second one: 4 slots per round keep it
+// well below the 256-register limit (at 8 its dual forms reached 256
+// registers plus accumulation-register spills and gave wrong results on
+// MI355X, in instances that changed with unrelated code edits).
+template <int LANES>
+struct SpinChunk<LANES, 4> {
+  static constexpr int value = LANES >= 8 ? 2 : 4;
 };
 
 // DUAL: two successive updates of one class at two sets of positions (the
@@ -53,7 +78,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
   // and any index outside [0, n) is replaced by i before it is used). The
   // gathers of positions and spins follow in one batch, and the Philox
   // noise of the first update is computed while they are in flight.
-  constexpr int CH = SpinChunk<LANES>::value;
+  constexpr int CH = SpinChunk<LANES, MLP>::value;
   real ax = 0, ay = 0, az = 0;
   real bx = 0, by = 0, bz = 0;  // DUAL: field at the positions of S2
   real sx = 0, sy = 0, sz = 0;
@@ -120,8 +145,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
           const double dy = min_image(riy - py[c], S.L[1], S.invL[1]);
           const double dz = min_image(riz - pz[c], S.L[2], S.invL[2]);
           const double r2 = dx * dx + dy * dy + dz * dz;
-          const real u = (real)(r2 * P.eInvD2);
-          const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+          const real Jc = exch_J<real>(P, r2);
           J[c] = (in && r2 < rs2) ? Jc : (real)0;
           if (MLP == 4) {
             hx[c] = hy[c] = hz[c] = (real)0;
@@ -148,8 +172,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
             const double dy = min_image(riy2 - py2[c], S.L[1], S.invL[1]);
             const double dz = min_image(riz2 - pz2[c], S.L[2], S.invL[2]);
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const real u = (real)(r2 * P.eInvD2);
-            const real Jc = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+            const real Jc = exch_J<real>(P, r2);
             J2[c] = (in && r2 < rs2) ? Jc : (real)0;
             if (MLP == 4) {
               hx2[c] = hy2[c] = hz2[c] = (real)0;
@@ -199,6 +222,24 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
     const bool second = DUAL && rep == 1;
     real ex = (second ? bx : ax) + (real)P.zB[0], ey = (second ? by : ay) + (real)P.zB[1],
          ez = (second ? bz : az) + (real)P.zB[2];
+    if (ANISO && P.aniso_split) {  // set only without the spin bath
+      // symmetric split A(h/2) X(h) A(h/2): A rotates about n at the rate
+      // (2K/hbar)(s.n), which A itself keeps fixed; X about the field
+      // without the anisotropy (it does not depend on s_i)
+      const real n0 = (real)P.an[0], n1 = (real)P.an[1], n2 = (real)P.an[2];
+      const real k2 = (real)2 * (real)P.aK * ih;
+      const real hh = (real)0.5 * h;
+      real c = k2 * (sx * n0 + sy * n1 + sz * n2);
+      cayley_rot<real>(sx, sy, sz, c * n0, c * n1, c * n2, hh);
+      cayley_rot<real>(sx, sy, sz, ex * ih, ey * ih, ez * ih, h);
+      c = k2 * (sx * n0 + sy * n1 + sz * n2);
+      cayley_rot<real>(sx, sy, sz, c * n0, c * n1, c * n2, hh);
+      if (sizeof(real) == 4) {
+        const real rn = (real)rsqrtf((float)(sx * sx + sy * sy + sz * sz));
+        sx *= rn; sy *= rn; sz *= rn;
+      }
+      continue;
+    }
     if (ANISO) {
       const real sn2 = (real)2 * (real)P.aK * (sx * (real)P.an[0] + sy * (real)P.an[1] + sz * (real)P.an[2]);
       ex += sn2 * (real)P.an[0];
@@ -365,11 +406,14 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
               const real u = (real)(r2d * P.eInvD2);
               const real eu = exp(-u);
               const real dJ = (real)P.eA8InvD2 * r * eu *
-                              ((real)1 - ((real)1 + (real)2 * (real)P.eG) * u + (real)P.eG * u * u);
+                                  ((real)1 - ((real)1 + (real)2 * (real)P.eG) * u + (real)P.eG * u * u) -
+                              r * (real)P.eJr;
               cc += dJ * sij[c];
-              if (MODE & kModeEnergy)
-                ee -= use ? (real)0.5 * (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * eu * sij[c]
-                          : (real)0;
+              if (MODE & kModeEnergy) {
+                const real Jv = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * eu -
+                                ((real)P.eJc + (real)(r2d - P.eRc2) * (real)P.eJq);
+                ee -= use ? (real)0.5 * Jv * sij[c] : (real)0;
+              }
             }
           }
           if (kEam && eam) {

@@ -81,7 +81,7 @@ class sl_potential(C.Structure):
                 ("dmi_n", C.c_double * 3), ("eam_on", C.c_int),
                 ("eam_A", C.c_double), ("eam_d", C.c_double), ("eam_beta", C.c_double),
                 ("eam_c", C.c_double), ("eam_c0", C.c_double), ("eam_c1", C.c_double),
-                ("eam_c2", C.c_double)]
+                ("eam_c2", C.c_double), ("ex_shift", C.c_int), ("aniso_split", C.c_int)]
 
 
 class sl_energy(C.Structure):

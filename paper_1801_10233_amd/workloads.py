@@ -140,7 +140,8 @@ def _pot(**kw):
                 neel_alpha=0.0, neel_gamma=0.0, neel_delta=1.0, neel_rc=0.0,
                 dmi_alpha=0.0, dmi_gamma=0.0, dmi_delta=1.0, dmi_rc=0.0,
                 dmi_n=(0.0, 0.0, 1.0), eam_on=0, eam_A=0.0, eam_d=0.0,
-                eam_beta=0.0, eam_c=0.0, eam_c0=0.0, eam_c1=0.0, eam_c2=0.0)
+                eam_beta=0.0, eam_c=0.0, eam_c0=0.0, eam_c1=0.0, eam_c2=0.0,
+                ex_shift=0, aniso_split=0)
     base.update(kw)
     return base
 

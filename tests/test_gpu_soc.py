@@ -59,10 +59,14 @@ def test_soc_with_both_baths_parity():
     assert p["ok"], p
 
 
+@pytest.mark.parametrize("lam", [0.0, 0.01])
 @pytest.mark.parametrize("spin_lanes,force_lanes,small", [
-    (1, 1, -1), (2, 4, 4096), (8, 8, -1)])
-def test_soc_launch_shapes(spin_lanes, force_lanes, small):
-    w = W.soc_coupled(n=6, lam=0.01)
+    (1, 1, -1), (2, 1, -1), (4, 2, -1), (8, 8, -1), (2, 4, 4096)])
+def test_soc_launch_shapes(spin_lanes, force_lanes, small, lam):
+    # every lane count, with and without the spin bath; small = -1 runs each
+    # class in its own launch, so both the regular and the dual (across the
+    # drift) spin launches of the spin-orbit variant are exercised
+    w = W.soc_coupled(n=6, lam=lam)
     o, g = make_oracle(w), make_gpu(w)
     g.set_tuning(spin_lanes, force_lanes, small, 1)   # cache request ignored with SOC
     o.step(50, w.dt)
