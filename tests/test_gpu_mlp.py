@@ -116,10 +116,13 @@ def _dataset(n=4, S=3, seed=0):
 # parameter blocks of the network, in the order of the master vector
 BLOCKS = (("W1", 64 * 16), ("c1", 64), ("W2", 64 * 64), ("c2", 64), ("W3", 2 * 64), ("c3", 2))
 # largest error of a GPU gradient component against the FP64 oracle's, as a
-# fraction of the largest oracle component of its block (BF16 operands with
-# unit roundoff 2^-9 in the forward, tangent and reverse products, FP32
-# accumulation: a few per cent of the block scale)
-GRAD_TOL = 5e-2
+# fraction of the largest oracle component of its block. Every product of the
+# forward, tangent and reverse passes takes BF16 operands (unit roundoff
+# u = 2^-9); a weight gradient sums, over the pairs, products carried through
+# up to three such rounded layers (weights, activations, adjoints), about 6u
+# per term, and the sums cancel partly against the block's largest entry.
+# 15u = 3e-2; measured on MI355X: 0.6 % to 1.6 % over three snapshots.
+GRAD_TOL = 3e-2
 
 
 def _blocks(g):
