@@ -388,21 +388,24 @@ def form_throughput(w, precision, steps, warmup, tune, mlp=None):
     return w.N * steps / els[1]
 
 
-def small_configs(repeats=3):
+def small_configs(repeats=3, tune=True):
     """Throughput of the two small workloads in FP64: the frozen-lattice spin
     system (bcc 10^3 cells, 2000 atoms, 1000 steps) and the coupled NVE system
-    (bcc 20^3 cells, 16000 atoms, 1000 steps, rebuilds included); median of
-    `repeats` windows after 20 warm-up steps. Both are launch-latency bound."""
+    (bcc 20^3 cells, 16000 atoms, 1000 steps, rebuilds included); autotuned
+    launch shape, median of `repeats` windows after 20 warm-up steps. Both are
+    launch-latency bound."""
     out = {}
     for name, w, steps in (("spin_frozen_2000", W.spin_frozen(10), 1000),
                            ("coupled_nve_16000", W.coupled_nve(n=20), 1000)):
         S = sl.system_from_workload(w, precision=sl.SL_FP64, thermo_every=100)
+        S.step(0, w.dt)
+        tuned = S.autotune(TUNE_STEPS, w.dt) if tune else None
         S.step(20, w.dt)
         els = sorted(timed_run(S, steps, w.dt)[0] for _ in range(repeats))
         el = els[len(els) // 2]
         out[name] = dict(value=round(w.N * steps / el, 1), unit="atom-steps/s", atoms=w.N,
                          steps=steps, ms_per_step=round(el / steps * 1e3, 4),
-                         rebuilds=S.stats()["rebuilds"])
+                         rebuilds=S.stats()["rebuilds"], tuning=tuned)
         S.close()
     return out
 
@@ -643,7 +646,7 @@ def main():
                          drift=d["mlp_smooth"]),
                 bar_eV_per_atom_per_10ps=1e-6)
         log("forms:", json.dumps(out["forms"]))
-        out["small_configs"] = small_configs()
+        out["small_configs"] = small_configs(tune=not args.no_tune)
         log("small configs:", json.dumps(out["small_configs"]))
         out["batched"] = batched_throughput(args.batch_steps, tune=not args.no_tune)
         log("batched:", json.dumps(out["batched"]))

@@ -296,7 +296,7 @@ int sl_synchronize(sl_system *sys);
  * consecutive wavefront lanes cooperate on one atom (0 = default: 2 for
  * the spin phase, 1 for forces).
  * Runs of consecutive colour classes of at most small_class atoms each are
- * applied by one single-workgroup launch (0 = default 512, -1 = never). */
+ * applied by one single-workgroup launch (0 = default 128, -1 = never). */
 typedef struct {
     int spin_lanes;
     int force_lanes;
@@ -319,7 +319,7 @@ int sl_set_tuning(sl_system *sys, const sl_tuning *t);
 int sl_get_tuning(sl_system *sys, sl_tuning *t);
 
 /* Autotuner. Runs windows of `steps` steps of length dt under each
- * candidate launch shape (spin lanes 1, 2, 4; force lanes 1, 2; the
+ * candidate launch shape (spin lanes 1, 2, 4, 8; force lanes 1, 2; the
  * exchange-coefficient cache on or off) on a scratch copy of the system
  * (same parameters, interactions, learned potential, user list, state and
  * step counter; its own stream and memory, freed before returning), times

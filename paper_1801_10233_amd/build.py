@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspinlat.so")
-SOURCES = ["sl_api.hip", "sl_dyn.hip", "sl_force.hip", "sl_batch.hip", "sl_sect.hip", "sl_nbr.hip",
-           "sl_mlp.hip",
+SOURCES = ["sl_system.hip", "sl_rebuild.hip", "sl_train.hip", "sl_tune.hip", "sl_batch_api.hip",
+           "sl_dyn.hip", "sl_force.hip", "sl_batch.hip", "sl_sect.hip", "sl_nbr.hip", "sl_mlp.hip",
            "sl_mlp_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -289,7 +289,7 @@ def test_full_size_large_system_sampled_parity():
     # the 432000-atom workload, every atom compared with the oracle:
     #  - the shape the benchmark's autotuner picks on MI355X with rows in
     #    displacement order (1 spin lane, 1 force lane, fused small classes up
-    #    to 512 atoms, no exchange cache) over 10 steps, with M;
+    #    to the default 128 atoms, no exchange cache) over 10 steps, with M;
     #  - the other candidate shapes (4 and 2 spin lanes, the cache on) over
     #    the first 2 steps (a dual spin launch in each step)
     w = W.large_langevin(n=60)
@@ -304,8 +304,8 @@ def test_full_size_large_system_sampled_parity():
         assert p["ok"], p
         g.close()
     g = make_gpu(w)
-    g.set_tuning(1, 1, 512, -1)
-    assert g.tuning() == dict(spin_lanes=1, force_lanes=1, small_class=512, jcache=-1,
+    g.set_tuning(1, 1, 0, -1)
+    assert g.tuning() == dict(spin_lanes=1, force_lanes=1, small_class=128, jcache=-1,
                               overlap=-1)
     g.step(4, w.dt)                   # two calls: the call-start force launch too
     g.step(6, w.dt)
