@@ -42,6 +42,40 @@ def test_literal_anisotropy_loses_energy_every_step(K):
     assert 1e-14 < np.abs(d).max() / w.N < abs(K) * 1e-3
 
 
+def test_literal_update_loses_exactly_K_delta_sn_squared():
+    # One spin in a field with anisotropy. With omega taken at the spin's
+    # value before the update, the rotation keeps s.omega, so
+    # mu B.ds + 2K (s0.n) d(s.n) = 0 and the energy -mu B.s - K (s.n)^2
+    # changes by exactly -K (d(s.n))^2. A wrong factor in the anisotropy's
+    # share of omega, or omega taken after the update, breaks the identity.
+    B = (0.2, -0.4, 1.0)
+    K = 0.03
+    n = np.array([0.0, 0.6, 0.8])
+    s0 = np.array([[0.48, 0.6, 0.64]])
+    o = O.Oracle(np.zeros((1, 3)), np.zeros((1, 3)), s0, np.ones(1), np.array([20.0] * 3),
+                 W._pot(B=B, aniso_K=K, aniso_n=tuple(n)), frozen=True, skin=0.0)
+    dt = 4e-3
+    s = s0[0].copy()
+    E = o.energy()["total"]
+    loss = 0.0
+    for _ in range(4):                     # one step of a one-class system: 4 updates of dt/4
+        w = o.omega()[0]
+        s1 = O.cayley(s, w, dt / 4)
+        o.set_state(s=s1[None, :])
+        E1 = o.energy()["total"]
+        d = float(np.dot(s1 - s, n))
+        assert d != 0.0
+        assert abs((E1 - E) - (-K * d * d)) < 1e-15 * max(1.0, abs(E)), (E1 - E, -K * d * d)
+        loss += K * d * d
+        s, E = s1, E1
+    # the oracle's own step is those four updates
+    o.set_state(s=s0)
+    E0 = o.energy()["total"]
+    o.step(1, dt)
+    assert np.abs(o.get_state()[2][0] - s).max() < 1e-15
+    assert abs((o.energy()["total"] - E0) + loss) < 1e-15
+
+
 def test_literal_anisotropy_loss_is_first_order_in_dt():
     # one spin in a field with anisotropy: each update loses K (delta s.n)^2
     # = O(h^2), so over a fixed time the total loss is O(dt): halving dt
