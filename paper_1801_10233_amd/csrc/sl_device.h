@@ -233,6 +233,8 @@ struct ForceArgs {
   double *fp;                 // [4][ld] split force: pair force x, y, z and the
                               // pair energy of each atom, written by the pair
                               // pass and added by the spin pass
+  const int2 *tiles;          // [ntiles] atom range [x, y) of each block, or
+  int ntiles;                 // null: blocks cover the atom order in tiles
 };
 
 enum : int { kModeFinal = 1, kModeNext = 2, kModeEnergy = 4 };

@@ -30,17 +30,31 @@ template <typename real, int MODE, int LANES, int MLP>
 __global__ __launch_bounds__(kBlock, kForceWaves) void k_force(SysView<real> S, PotConst P, ForceArgs A) {
   __shared__ double red[kBlock / 64][8];
   __shared__ double redm[kBlock / 64][3];
-  // Tiles are taken from the end of the atom order first: the last colour
-  // classes may hold a few atoms scattered over the whole box (repairs),
-  // whose gathers miss the caches; starting them first hides their latency
-  // behind the bulk instead of leaving them as the tail of the launch.
-  const int tile = gridDim.x - 1 - xcd_tile(blockIdx.x, gridDim.x);
-  const int t = tile * kBlock + threadIdx.x;
-  const int l = t & (LANES - 1);
-  const int i = t / LANES;
+  // With a tile table (A.tiles) block b takes the atom range the host gave
+  // it: XCD b % 8 holds the same spatial slab of every colour class, so its
+  // L2 serves the neighbour gathers of all classes of that slab. Without
+  // one, tiles are taken from the end of the atom order first: the last
+  // colour classes may hold a few atoms scattered over the whole box
+  // (repairs), whose gathers miss the caches; starting them first hides
+  // their latency behind the bulk instead of leaving them as the tail.
+  int tile, i, l;
+  bool valid;
+  if (A.tiles) {
+    const int2 rg = A.tiles[blockIdx.x];
+    tile = blockIdx.x;
+    i = rg.x + (int)threadIdx.x / LANES;
+    l = threadIdx.x & (LANES - 1);
+    valid = i < rg.y;
+  } else {
+    tile = gridDim.x - 1 - xcd_tile(blockIdx.x, gridDim.x);
+    const int t = tile * kBlock + threadIdx.x;
+    l = t & (LANES - 1);
+    i = t / LANES;
+    valid = i < S.n;
+  }
   double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double dm = 0.0, vm = 0.0, wm = kInf;
-  force_atom<real, MODE, LANES, MLP>(S, P, A, i, i < S.n, l, e, dm, vm, wm);
+  force_atom<real, MODE, LANES, MLP>(S, P, A, i, valid, l, e, dm, vm, wm);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (MODE & kModeEnergy) {
 #pragma unroll
@@ -123,7 +137,7 @@ template <typename real, int LANES, int MLP>
 static void force_lanes2(const SysView<real> &S, const PotConst &P, const ForceArgs &A,
                          hipStream_t st) {
   const long threads = (long)S.n * LANES;
-  const int nb = (int)((threads + kBlock - 1) / kBlock);
+  const int nb = A.tiles ? A.ntiles : (int)((threads + kBlock - 1) / kBlock);
   switch (A.mode) {
 #define SL_FORCE_CASE(m) \
   case m: hipLaunchKernelGGL((k_force<real, m, LANES, MLP>), dim3(nb), dim3(kBlock), 0, st, S, P, A); break;

@@ -97,6 +97,10 @@ struct sl_system {
   unsigned long long *jpmask[2] = {nullptr, nullptr};  // conflict / earlier-key slot masks
   unsigned long long *dslot = nullptr;
   double *pred = nullptr;  // [force blocks][3] predictor terms of one launch
+  int2 *ftile = nullptr;   // [force blocks] atom range of each force block (slabs per XCD)
+  int ftile_n = 0;         // blocks of the tiled force launch (0: untiled)
+  int ftile_lanes = -1;    // force lanes the tiles were made for (-1: stale)
+  std::vector<int2> ftile_host;
   unsigned int *done = nullptr;
   double *partial = nullptr, *red_out = nullptr;
   double *thermo = nullptr;
@@ -280,6 +284,9 @@ int record_thermo(sl_system *S, int64_t boundary);
 int wait_predictor(sl_system *S, int64_t boundary, double dt_next, bool *due);
 int load_aos(sl_system *S, const double *src, int where, std::vector<double> &host);
 // (instantiated for double and float)
+int force_tiles(sl_system *S);
+int force_nb(const sl_system *S);
+int force_block_cap(int n);
 template <typename real>
 int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary,
                  bool split = false);

@@ -81,12 +81,16 @@ void launch_scan(const int *in, int *out, int n, hipStream_t st);
 void launch_bucket_scatter(int n, const int *key, const int *start, int *fill, int *out,
                            hipStream_t st);
 void launch_bucket_sort(int nbucket, const int *start, int *items, hipStream_t st);
+// Each bucket's items ascending by (x[item], item).
+void launch_bucket_sort_x(int nbucket, const int *start, int *items, const double *x,
+                          hipStream_t st);
 
 struct NbrBuildArgs {
   int n, ld, max_nbr, max_spin;
   double rs2, rl2;
   CellGrid G;
   const double *rx, *ry, *rz;
+  const double *cx, *cy, *cz;  // positions in cell order (cx[p] = rx[catoms[p]])
   const int *cell, *cstart, *catoms;
   int *nbr, *nspin, *nall;
   double *bx, *by, *bz;   // reference positions written at build time
@@ -96,6 +100,9 @@ struct NbrBuildArgs {
                           // rounded to this grid step (A); 0: cell-loop order
 };
 void launch_nbr_build(const NbrBuildArgs &A, hipStream_t st);
+// Positions in cell order, for the neighbour build.
+void launch_cell_positions(int n, const int *catoms, const double *rx, const double *ry,
+                           const double *rz, double *cx, double *cy, double *cz, hipStream_t st);
 
 // Lexicographic colouring keys (z, y, x wrapped) of the current positions.
 void launch_keys(int n, const double *rx, const double *ry, const double *rz, const double L[3],
@@ -134,9 +141,17 @@ void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t s
 void launch_watch_mask(int n, int ld, const int *nbr, const int *nspin, const int *colour,
                        unsigned long long *wmask, hipStream_t st);
 
-// Permutation to (colour, cell) order.
-void launch_sort_key(int n, const int *colour, const int *cell, int ncell, int *key, int *count,
-                     hipStream_t st);
+// Permutation key of the atom order: colour class, then the rows of a fine
+// (y, z) grid, z slowest (one bucket per class and row); inside a row the
+// atoms go by x (launch_bucket_sort_x). Row y of the grid collects the
+// positions within half a spacing of y * Ly / ny, so that lattice planes at
+// multiples of the spacing keep their row through thermal motion.
+struct RowGrid {
+  int ny, nz;
+  double inv_y, inv_z;  // ny / Ly, nz / Lz
+};
+void launch_row_key(int n, const int *colour, const double *ky, const double *kz,
+                    const RowGrid &R, int *key, int *count, hipStream_t st);
 void launch_inverse(int n, const int *perm, int *inv, hipStream_t st);
 
 struct PermuteArgs {

@@ -1,6 +1,6 @@
 // sl_nbr.hip -- rebuild-step kernels on gfx950: cell binning, neighbour
 // lists, colour classes of non-interacting spins and the permutation of
-// the per-atom arrays into (colour, cell) order.
+// the per-atom arrays into (colour, row, x) order.
 //
 // Colour classes play the role of the paper's sectors (Sec. 5.1): a set of
 // spins none of which interact, so all of them can be rotated at once while
@@ -66,6 +66,35 @@ __global__ void k_bucket_scatter(int n, const int *key, const int *start, int *f
   out[start[b] + atomicAdd(&fill[b], 1)] = i;
 }
 
+__global__ void k_bucket_sort_x(int nbucket, const int *start, int *items, const double *x) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbucket) return;
+  const int a = start[b], e = start[b + 1];
+  for (int p = a + 1; p < e; ++p) {
+    const int v = items[p];
+    const double xv = x[v];
+    int q = p - 1;
+    while (q >= a) {
+      const int u = items[q];
+      const double xu = x[u];
+      if (xu < xv || (xu == xv && u < v)) break;
+      items[q + 1] = u;
+      --q;
+    }
+    items[q + 1] = v;
+  }
+}
+
+__global__ void k_cell_positions(int n, const int *catoms, const double *rx, const double *ry,
+                                 const double *rz, double *cx, double *cy, double *cz) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int j = catoms[p];
+  cx[p] = rx[j];
+  cy[p] = ry[j];
+  cz[p] = rz[j];
+}
+
 __global__ void k_bucket_sort(int nbucket, const int *start, int *items) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbucket) return;
@@ -90,15 +119,19 @@ __global__ void k_bucket_sort(int nbucket, const int *start, int *items) {
 // cells: a counting sweep, a segmented prefix sum over the lanes, then a
 // writing sweep that puts every entry at its place in that order. With 16
 // lanes the serial chain per thread is ~16x shorter, which small systems
-// (too few atoms to fill the device) need; large systems keep one lane per
-// atom, whose list writes stay coalesced across the wavefront.
+// (too few atoms to fill the device) need; large systems take one lane per
+// atom. Atoms are taken in cell order (thread group p builds the row of
+// catoms[p]) and candidates' positions come from the cell-ordered copy
+// (cx, cy, cz), so the lanes of a wavefront work on a few cells and read
+// the same candidate runs, whatever the order of the atom arrays.
 constexpr int kNbrManyAtoms = 1 << 16;  // from here on one lane per atom
 
 template <int kNbrLanes>
 __global__ __launch_bounds__(kBlock) void k_nbr_build(NbrBuildArgs A) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = (int)(t / kNbrLanes), l = (int)(t % kNbrLanes);
-  const bool valid = i < A.n;
+  const int p0 = (int)(t / kNbrLanes), l = (int)(t % kNbrLanes);
+  const bool valid = p0 < A.n;
+  const int i = valid ? A.catoms[p0] : 0;
   const int ox = A.G.nc[0] >= 3 ? 1 : 0, oy = A.G.nc[1] >= 3 ? 1 : 0, oz = A.G.nc[2] >= 3 ? 1 : 0;
   const int wx = 2 * ox + 1, wy = 2 * oy + 1, M = wx * wy * (2 * oz + 1);
   const int m0 = M * l / kNbrLanes, m1 = M * (l + 1) / kNbrLanes;
@@ -107,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(NbrBuildArgs A) {
   double rix = 0, riy = 0, riz = 0;
   int cx = 0, cy = 0, cz = 0;
   if (valid) {
-    rix = A.rx[i]; riy = A.ry[i]; riz = A.rz[i];
+    rix = A.cx[p0]; riy = A.cy[p0]; riz = A.cz[p0];
     const int c = A.cell[i];
     cx = c % A.G.nc[0]; cy = (c / A.G.nc[0]) % A.G.nc[1]; cz = c / (A.G.nc[0] * A.G.nc[1]);
   }
@@ -122,11 +155,10 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(NbrBuildArgs A) {
         const int qz = (cz + dz + A.G.nc[2]) % A.G.nc[2];
         const int q = (qz * A.G.nc[1] + qy) * A.G.nc[0] + qx;
         for (int p = A.cstart[q]; p < A.cstart[q + 1]; ++p) {
-          const int j = A.catoms[p];
-          if (j == i) continue;
-          const double ddx = min_image(rix - A.rx[j], Lx, iLx);
-          const double ddy = min_image(riy - A.ry[j], Ly, iLy);
-          const double ddz = min_image(riz - A.rz[j], Lz, iLz);
+          if (p == p0) continue;
+          const double ddx = min_image(rix - A.cx[p], Lx, iLx);
+          const double ddy = min_image(riy - A.cy[p], Ly, iLy);
+          const double ddz = min_image(riz - A.cz[p], Lz, iLz);
           const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
           if (r2 >= A.rl2 && r2 >= A.rs2) continue;
           const int seg = r2 < A.rs2 ? 0 : 1;
@@ -134,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(NbrBuildArgs A) {
             ++cnt[seg];
           } else {
             const int k = off[seg]++;
-            if (k < A.max_nbr) A.nbr[(size_t)k * A.ld + i] = j;
+            if (k < A.max_nbr) A.nbr[(size_t)k * A.ld + i] = A.catoms[p];
           }
         }
       }
@@ -383,11 +415,16 @@ __global__ void k_watch_mask(int n, int ld, const int *nbr, const int *nspin, co
   wmask[i] = m;
 }
 
-__global__ void k_sort_key(int n, const int *colour, const int *cell, int ncell, int *key,
-                           int *count) {
+// ky, kz are wrapped positions in [0, L): the row is the nearest multiple
+// of the spacing, the last half spacing wrapping to row 0.
+__global__ void k_row_key(int n, const int *colour, const double *ky, const double *kz,
+                          RowGrid R, int *key, int *count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int k = colour[i] * ncell + cell[i];
+  int y = (int)floor(ky[i] * R.inv_y + 0.5), z = (int)floor(kz[i] * R.inv_z + 0.5);
+  y = y >= R.ny ? y - R.ny : (y < 0 ? 0 : y);
+  z = z >= R.nz ? z - R.nz : (z < 0 ? 0 : z);
+  const int k = (colour[i] * R.nz + z) * R.ny + y;
   key[i] = k;
   atomicAdd(&count[k], 1);
 }
@@ -522,6 +559,14 @@ void launch_bucket_scatter(int n, const int *key, const int *start, int *fill, i
                            hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks(n)), dim3(kBlock), 0, st, n, key, start, fill, out);
 }
+void launch_bucket_sort_x(int nbucket, const int *start, int *items, const double *x,
+                          hipStream_t st) {
+  if (nbucket > 0) hipLaunchKernelGGL(k_bucket_sort_x, dim3(nblocks(nbucket)), dim3(kBlock), 0, st, nbucket, start, items, x);
+}
+void launch_cell_positions(int n, const int *catoms, const double *rx, const double *ry,
+                           const double *rz, double *cx, double *cy, double *cz, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_cell_positions, dim3(nblocks(n)), dim3(kBlock), 0, st, n, catoms, rx, ry, rz, cx, cy, cz);
+}
 void launch_bucket_sort(int nbucket, const int *start, int *items, hipStream_t st) {
   if (nbucket > 0) hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks(nbucket)), dim3(kBlock), 0, st, nbucket, start, items);
 }
@@ -566,9 +611,9 @@ void launch_watch_mask(int n, int ld, const int *nbr, const int *nspin, const in
                        unsigned long long *wmask, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_watch_mask, dim3(nblocks(n)), dim3(kBlock), 0, st, n, ld, nbr, nspin, colour, wmask);
 }
-void launch_sort_key(int n, const int *colour, const int *cell, int ncell, int *key, int *count,
-                     hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_sort_key, dim3(nblocks(n)), dim3(kBlock), 0, st, n, colour, cell, ncell, key, count);
+void launch_row_key(int n, const int *colour, const double *ky, const double *kz,
+                    const RowGrid &R, int *key, int *count, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_row_key, dim3(nblocks(n)), dim3(kBlock), 0, st, n, colour, ky, kz, R, key, count);
 }
 void launch_inverse(int n, const int *perm, int *inv, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_inverse, dim3(nblocks(n)), dim3(kBlock), 0, st, n, perm, inv);

@@ -1,7 +1,7 @@
 // sl_rebuild.hip -- the rebuild pipeline of a system: cell binning, the
 // device neighbour-list build with the rows' order, colour classes (a full
 // colouring or the repair of the last one) and the permutation of every
-// per-atom array into (colour, cell) order.
+// per-atom array into (colour, row, x) order.
 #include "sl_host.h"
 
 namespace sl {
@@ -131,8 +131,28 @@ int mlp_pairs(sl_system *S) {
   return SL_OK;
 }
 
+// Rows of the atom order: spaced by the list rows' order grid when there is
+// one (a lattice spacing), else by the mean interatomic distance; at most
+// about one row per atom.
+RowGrid row_grid(const sl_system *S) {
+  const double V = S->L[0] * S->L[1] * S->L[2];
+  const double h = S->row_q > 0.0 ? S->row_q : std::cbrt(V / std::max(1, S->n));
+  int ny = std::max(1, std::min(4096, (int)std::lround(S->L[1] / h)));
+  int nz = std::max(1, std::min(4096, (int)std::lround(S->L[2] / h)));
+  while ((long)ny * nz > std::max(1, S->n) && (ny > 1 || nz > 1)) {
+    ny = std::max(1, (ny * 4) / 5);
+    nz = std::max(1, (nz * 4) / 5);
+  }
+  RowGrid R;
+  R.ny = ny;
+  R.nz = nz;
+  R.inv_y = ny / S->L[1];
+  R.inv_z = nz / S->L[2];
+  return R;
+}
+
 // Colour classes (repairing the previous colouring when there is one) and
-// permutation of all per-atom arrays into (colour, cell) order.
+// permutation of all per-atom arrays into (colour, row, x) order.
 int colour_and_permute(sl_system *S, bool repair) {
   ProfScope ps(S, 2, 0.0);
   const int n = S->n;
@@ -172,17 +192,24 @@ int colour_and_permute(sl_system *S, bool repair) {
   if (set_base) S->Kbase = S->K;
   S->have_colour = true;
 
-  // permutation: counting sort by colour * ncell + cell, buckets in old order
-  const int nbin = S->K * S->ncell;
+  // permutation: counting sort by (colour, row of the fine grid), each row
+  // by x. With the rows one lattice spacing apart, consecutive atoms of a
+  // class run along a lattice row, and so do their neighbours at one list
+  // slot (rows ordered by displacement): a wavefront's gather of one slot
+  // reads a few runs of consecutive atoms instead of one or two atoms from
+  // each of many cells.
+  const RowGrid R = row_grid(S);
+  const int nrow = R.ny * R.nz;
+  const int nbin = S->K * nrow;
   CHK(ensure_bins(S, nbin));
   Atoms &A = S->a[S->cur];
   Atoms &B = S->a[1 - S->cur];
   launch_zero_i(nbin, S->bcount, S->st);
-  launch_sort_key(n, A.colour, A.cell, S->ncell, S->skey, S->bcount, S->st);
+  launch_row_key(n, A.colour, S->ky, S->kz, R, S->skey, S->bcount, S->st);
   launch_scan(S->bcount, S->bstart, nbin, S->st);
   launch_zero_i(nbin, S->bfill, S->st);
   launch_bucket_scatter(n, S->skey, S->bstart, S->bfill, S->perm, S->st);
-  launch_bucket_sort(nbin, S->bstart, S->perm, S->st);
+  launch_bucket_sort_x(nbin, S->bstart, S->perm, S->kx, S->st);
   launch_inverse(n, S->perm, S->inv, S->st);
   PermuteArgs P;
   std::memset(&P, 0, sizeof(P));
@@ -225,7 +252,8 @@ int colour_and_permute(sl_system *S, bool repair) {
   HIPCHK(S, hipMemcpyAsync(bs.data(), S->bstart, sizeof(int) * (nbin + 1), hipMemcpyDeviceToHost, S->st));
   HIPCHK(S, hipStreamSynchronize(S->st));
   S->class_off.assign(S->K + 1, 0);
-  for (int c = 0; c <= S->K; ++c) S->class_off[c] = bs[(size_t)c * S->ncell];
+  for (int c = 0; c <= S->K; ++c) S->class_off[c] = bs[(size_t)c * nrow];
+  S->ftile_lanes = -1;  // the force launch's tiles follow the classes
   {
     Atoms &N = S->a[S->cur];
     launch_watch_mask(n, S->ld, N.nbr, N.nspin, N.colour, N.wmask, S->st);
@@ -258,6 +286,12 @@ int rebuild(sl_system *S) {
     B.cell = A.cell;
     B.cstart = S->cstart;
     B.catoms = S->catoms;
+    // cell-ordered positions in the staging buffer (free during a rebuild)
+    B.cx = S->stage;
+    B.cy = S->stage + S->n;
+    B.cz = S->stage + 2 * (size_t)S->n;
+    launch_cell_positions(S->n, S->catoms, B.rx, B.ry, B.rz, S->stage, S->stage + S->n,
+                          S->stage + 2 * (size_t)S->n, S->st);
     B.nbr = A.nbr;
     B.nspin = A.nspin;
     B.nall = A.nall;

@@ -439,6 +439,71 @@ void half_step_updates(const sl_system *S, int64_t step, int sub_fwd, std::vecto
   for (int c = S->K - 1; c >= 0; --c) u.push_back({c, step, sub_fwd + 1});
 }
 
+// Capacity of the per-block buffers of a force launch: untiled launches of up
+// to 8 lanes per atom, or a tile table (at most 8 partial tiles per class).
+int force_block_cap(int n) { return force_blocks(n, 8) + 8 * (kMaxClass + 8); }
+
+// Blocks of the current force launch (the rows of its partial sums).
+int force_nb(const sl_system *S) {
+  return S->ftile_n > 0 && S->ftile_lanes == S->force_lanes ? S->ftile_n
+                                                             : force_blocks(S->n, S->force_lanes);
+}
+
+// Tile table of the force launch. Blocks are dispatched to the eight XCDs
+// round-robin (block b to XCD b % 8), and each XCD has its own L2. XCD x is
+// given the x-th eighth, in cell order, of every colour class: one slab of
+// the box, whose neighbour data its L2 then serves for all classes, instead
+// of half of the box for one class. Inside an XCD the tiles of the classes
+// are interleaved by their place in the slab, so the blocks in flight on an
+// XCD cover a thin layer of it. Classes of fewer than 8 tiles (the few atoms
+// a repair adds, scattered over the box) go first, spread over the XCDs.
+// Launches of fewer than 64 tiles stay untiled.
+int force_tiles(sl_system *S) {
+  if (S->ftile_lanes == S->force_lanes) return SL_OK;
+  S->ftile_lanes = S->force_lanes;
+  S->ftile_n = 0;
+  const int per = kBlock / S->force_lanes;
+  if (S->K <= 0 || S->n <= 0 || !S->ftile || (int)S->class_off.size() < S->K + 1) return SL_OK;
+  struct Tile {
+    double key;
+    int a, b;
+  };
+  std::vector<Tile> xl[8];
+  int total = 0, spread = 0;
+  for (int c = S->K - 1; c >= 0; --c) {
+    const int b0 = S->class_off[c], b1 = S->class_off[c + 1];
+    const int T = (b1 - b0 + per - 1) / per;
+    total += T;
+    for (int t = 0; t < T; ++t) {
+      const int a = b0 + t * per, b = std::min(b1, a + per);
+      if (T < 8) {
+        xl[spread % 8].push_back({-1.0, a, b});
+        ++spread;
+      } else {
+        const int x = (int)(((long)t * 8) / T);
+        const int lo = (int)(((long)T * x + 7) / 8), hi = (int)(((long)T * (x + 1) + 7) / 8);
+        xl[x].push_back({(t - lo + 0.5) / (double)std::max(1, hi - lo), a, b});
+      }
+    }
+  }
+  if (total < 64) return SL_OK;
+  size_t m = 0;
+  for (auto &v : xl) {
+    std::stable_sort(v.begin(), v.end(), [](const Tile &p, const Tile &q) { return p.key < q.key; });
+    m = std::max(m, v.size());
+  }
+  const int nb = (int)(8 * m);
+  if (nb > force_block_cap(S->n)) return SL_OK;
+  S->ftile_host.assign((size_t)nb, make_int2(0, 0));
+  for (int x = 0; x < 8; ++x)
+    for (size_t k = 0; k < xl[x].size(); ++k)
+      S->ftile_host[8 * k + x] = make_int2(xl[x][k].a, xl[x][k].b);
+  HIPCHK(S, hipMemcpyAsync(S->ftile, S->ftile_host.data(), sizeof(int2) * nb,
+                           hipMemcpyHostToDevice, S->st));
+  S->ftile_n = nb;
+  return SL_OK;
+}
+
 // With split set, the pair pass of this boundary (pair_launch) has filled
 // S->fp and the launch is the spin pass.
 template <typename real>
@@ -471,6 +536,9 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   F.replica = S->prm.replica;
   F.step = boundary;
   F.fp = split ? S->fp : nullptr;
+  CHK(force_tiles(S));
+  F.tiles = S->ftile_n > 0 ? S->ftile : nullptr;
+  F.ntiles = S->ftile_n;
   CHK(ensure_table(S, posbuf));
   if (mode & kModeNext) S->tab_ok[1 - posbuf] = S->jc_ok[1 - posbuf] = false;
   const int slot = (int)(boundary & 3);
@@ -492,7 +560,7 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
     }
   }
   if (mode & (kModeFinal | kModeNext))
-    launch_pred_reduce(S->pred, force_blocks(S->n, S->force_lanes), S->err, F.host_out, S->st);
+    launch_pred_reduce(S->pred, force_nb(S), S->err, F.host_out, S->st);
   if (mode & (kModeFinal | kModeNext)) HIPCHK(S, hipEventRecord(S->ev[slot], S->st));
   return SL_OK;
 }
@@ -525,7 +593,7 @@ void pair_launch(sl_system *S, int posbuf, bool energy) {
 }
 
 int record_thermo(sl_system *S, int64_t boundary) {
-  const int nb = force_blocks(S->n, S->force_lanes);
+  const int nb = force_nb(S);
   const int k = (int)S->thermo_steps.size();
   if (k >= kThermoCap) return SL_OK;
   launch_reduce8(S->partial, nb, S->thermo + (size_t)k * 8, S->st);
@@ -536,7 +604,7 @@ int record_thermo(sl_system *S, int64_t boundary) {
 template <typename real>
 int energy_now(sl_system *S, double out[8]) {
   CHK(force_launch<real>(S, S->pos, kModeEnergy, 0.0, -1));
-  const int nb = force_blocks(S->n, S->force_lanes);
+  const int nb = force_nb(S);
   launch_reduce8(S->partial, nb, S->red_out, S->st);
   HIPCHK(S, hipMemcpyAsync(out, S->red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, S->st));
   CHK(read_err(S));
@@ -825,7 +893,7 @@ int sl_create(const sl_params *p, sl_system **out) {
   }
   if ((rc = alloc_atoms(S, S->a[0])) || (rc = alloc_atoms(S, S->a[1]))) return bail(rc == SL_E_HIP ? SL_E_NOMEM : rc);
   const int n = S->n;
-  const int nb = force_blocks(n, 8);
+  const int nb = force_block_cap(n);
 #define A_(x) if (hipSuccess != (x)) { S->last_err = #x; return bail(SL_E_NOMEM); }
   A_(dalloc(&S->catoms, n));
   A_(dalloc(&S->skey, n));
@@ -849,6 +917,7 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(dalloc(&S->done, 1));
   A_(dalloc(&S->partial, (size_t)nb * 8));
   A_(dalloc(&S->pred, (size_t)nb * 3));
+  A_(dalloc(&S->ftile, (size_t)nb));
   A_(dalloc(&S->red_out, 8));
   A_(dalloc(&S->thermo, (size_t)kThermoCap * 8));
   A_(hipHostMalloc((void **)&S->ring, 32 * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
@@ -894,7 +963,7 @@ int sl_destroy(sl_system *S) {
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
                   (void *)S->jplist[0], (void *)S->jplist[1], (void *)S->jpmask[0],
                   (void *)S->jpmask[1],
-                  (void *)S->done, (void *)S->partial, (void *)S->pred, (void *)S->red_out, (void *)S->thermo,
+                  (void *)S->done, (void *)S->partial, (void *)S->pred, (void *)S->ftile, (void *)S->red_out, (void *)S->thermo,
                   (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
                   (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1], (void *)S->eam,
                   (void *)S->skeys[0], (void *)S->skeys[1], (void *)S->svals[0],

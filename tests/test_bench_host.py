@@ -47,7 +47,7 @@ def test_algorithmic_bytes_and_profile_lookup():
     # plain spin update: s r/w, own r, 14 indices; cached: 14 J instead of r
     assert B.SPIN_BYTES[sl.SL_FP64] == 128 and B.SPIN_BYTES_JC[sl.SL_FP64] == 216
     assert B.FORCE_BYTES[sl.SL_FP64] == 384
-    assert B.STEP_BYTES_JC[sl.SL_FP64] == 4 * 216 + 384 + 192
+    assert B.JCACHE_BYTES[sl.SL_FP64] == 192
     # a summary of another launch shape or of older sources is never used
     assert B.counter_traffic("k_spin_phase", sl.SL_FP64, "lanes=3,jcache=0") is None
     assert B.counter_traffic("no_such_kernel", sl.SL_FP64, "lanes=1") is None
@@ -60,8 +60,9 @@ def test_committed_counter_summaries_match_the_sources():
     B = _bench()
     sl = B.sl
     t = B.counter_traffic("k_spin_phase", sl.SL_FP64, "lanes=1,jcache=0")
+    tc = B.counter_traffic("k_spin_phase", sl.SL_FP64, "lanes=1,jcache=1")
     f = B.counter_traffic("k_force", sl.SL_FP64, "lanes=1")
-    assert t is not None and f is not None
+    assert t is not None and tc is not None and f is not None
     alg_spin = B.SPIN_BYTES[sl.SL_FP64] * 108000
     alg_force = B.FORCE_BYTES[sl.SL_FP64] * 432000
     assert alg_spin < t < 5 * alg_spin and alg_force < f < 5 * alg_force
