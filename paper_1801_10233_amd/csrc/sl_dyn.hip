@@ -51,9 +51,19 @@ __global__ __launch_bounds__(kTailBlock) void k_spin_tail(SysView<real> S, PotCo
 // positions move, and only then).
 template <typename real, bool SPL>
 __global__ __launch_bounds__(kBlock) void k_jcache(SysView<real> S, PotConst P, real *out,
-                                                   double rs2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S.n) return;
+                                                   double rs2, const int2 *tiles) {
+  // with a tile table, block b takes the atom range of entry b (one spatial
+  // slab of every class per XCD, as in the force launch)
+  int i, end;
+  if (tiles) {
+    const int2 rg = tiles[blockIdx.x];
+    i = rg.x + (int)threadIdx.x;
+    end = rg.y;
+  } else {
+    i = blockIdx.x * blockDim.x + threadIdx.x;
+    end = S.n;
+  }
+  if (i >= end) return;
   const int ns = S.nspin[i];
   const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
   // slots in chunks of 8 with all loads of a chunk issued before use; the
@@ -93,14 +103,16 @@ __global__ __launch_bounds__(kBlock) void k_jcache(SysView<real> S, PotConst P, 
 
 template <typename real>
 void launch_jcache(const SysView<real> &S, const PotConst &P, real *out, double rs2,
-                   hipStream_t st) {
+                   const int2 *tiles, int ntiles, hipStream_t st) {
   if (S.n <= 0) return;
-  const dim3 grid((S.n + kBlock - 1) / kBlock);
-  if (S.spl.t) hipLaunchKernelGGL((k_jcache<real, true>), grid, dim3(kBlock), 0, st, S, P, out, rs2);
-  else hipLaunchKernelGGL((k_jcache<real, false>), grid, dim3(kBlock), 0, st, S, P, out, rs2);
+  const dim3 grid(tiles ? ntiles : (S.n + kBlock - 1) / kBlock);
+  if (S.spl.t) hipLaunchKernelGGL((k_jcache<real, true>), grid, dim3(kBlock), 0, st, S, P, out, rs2, tiles);
+  else hipLaunchKernelGGL((k_jcache<real, false>), grid, dim3(kBlock), 0, st, S, P, out, rs2, tiles);
 }
-template void launch_jcache<double>(const SysView<double> &, const PotConst &, double *, double, hipStream_t);
-template void launch_jcache<float>(const SysView<float> &, const PotConst &, float *, double, hipStream_t);
+template void launch_jcache<double>(const SysView<double> &, const PotConst &, double *, double,
+                                    const int2 *, int, hipStream_t);
+template void launch_jcache<float>(const SysView<float> &, const PotConst &, float *, double,
+                                   const int2 *, int, hipStream_t);
 
 // Fixed-order sum of nb partial rows of 8 doubles (deterministic result).
 __global__ __launch_bounds__(256) void k_reduce8(const double *partial, int nb, double *out) {

@@ -101,6 +101,9 @@ struct sl_system {
   int ftile_n = 0;         // blocks of the tiled force launch (0: untiled)
   int ftile_lanes = -1;    // force lanes the tiles were made for (-1: stale)
   std::vector<int2> ftile_host;
+  int2 *jtile = nullptr;   // the same slab tiles with 256 atoms per block (exchange cache)
+  int jtile_n = 0;
+  std::vector<int2> jtile_host;
   unsigned int *done = nullptr;
   double *partial = nullptr, *red_out = nullptr;
   double *thermo = nullptr;

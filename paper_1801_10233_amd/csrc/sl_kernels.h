@@ -38,10 +38,11 @@ void launch_batch_run(RepDesc<real> *D, int R, int lanes, int variant, hipStream
 // of a view, before the force launch that reads them.
 template <typename real>
 void launch_eam_density(const SysView<real> &S, const PotConst &P, hipStream_t st);
-// Exchange-coefficient cache: J(r_ij) per spin-segment entry (ELL layout).
+// Exchange-coefficient cache: J(r_ij) per spin-segment entry (ELL layout);
+// tiles (or null): atom range of each 256-thread block.
 template <typename real>
 void launch_jcache(const SysView<real> &S, const PotConst &P, real *out, double rs2,
-                   hipStream_t st);
+                   const int2 *tiles, int ntiles, hipStream_t st);
 // Phase-batched mode: one colour phase of every replica (max_class = the
 // largest class of any replica) and one force pass of every replica (max_n =
 // the largest replica; mode kModeNext at the call start, kModeFinal with or

@@ -394,7 +394,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
             }
           } else {
             if (!kSpinPass && P.morse_on && r2d < P.mRc2) {
-              const real ex = exp(-(real)P.mA * (r - (real)P.mR0));
+              const real ex = exp_pair(-(real)P.mA * (r - (real)P.mR0));
               const real dM = -(real)2 * (real)P.mA * (real)P.mD * (ex * ex - ex);
               cc -= dM - (real)P.mdMc;
               if (MODE & kModeEnergy)
@@ -404,7 +404,7 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
             }
             if (!kPairPass && seg == 0 && P.ex_on && r2d < P.eRc2) {
               const real u = (real)(r2d * P.eInvD2);
-              const real eu = exp(-u);
+              const real eu = exp_pair(-u);
               const real dJ = (real)P.eA8InvD2 * r * eu *
                                   ((real)1 - ((real)1 + (real)2 * (real)P.eG) * u + (real)P.eG * u * u) -
                               r * (real)P.eJr;

@@ -236,7 +236,9 @@ int ensure_jcache(sl_system *S, int b) {
   SysView<real> v = view<real>(S, b);
   {
     ProfScope ps(S, 3, (double)S->n);
-    launch_jcache<real>(v, S->pc, (real *)S->jc[b], S->pot.ex_rc * S->pot.ex_rc, S->st);
+    CHK(force_tiles(S));
+    launch_jcache<real>(v, S->pc, (real *)S->jc[b], S->pot.ex_rc * S->pot.ex_rc,
+                        S->jtile_n > 0 ? S->jtile : nullptr, S->jtile_n, S->st);
   }
   S->jc_ok[b] = true;
   return SL_OK;
@@ -449,21 +451,19 @@ int force_nb(const sl_system *S) {
                                                              : force_blocks(S->n, S->force_lanes);
 }
 
-// Tile table of the force launch. Blocks are dispatched to the eight XCDs
+// Tile tables of the force launch (per atoms per block) and of the
+// exchange-cache launch (256). Blocks are dispatched to the eight XCDs
 // round-robin (block b to XCD b % 8), and each XCD has its own L2. XCD x is
-// given the x-th eighth, in cell order, of every colour class: one slab of
+// given the x-th eighth, in the atom order (z slowest), of every colour class: one slab of
 // the box, whose neighbour data its L2 then serves for all classes, instead
 // of half of the box for one class. Inside an XCD the tiles of the classes
 // are interleaved by their place in the slab, so the blocks in flight on an
 // XCD cover a thin layer of it. Classes of fewer than 8 tiles (the few atoms
 // a repair adds, scattered over the box) go first, spread over the XCDs.
 // Launches of fewer than 64 tiles stay untiled.
-int force_tiles(sl_system *S) {
-  if (S->ftile_lanes == S->force_lanes) return SL_OK;
-  S->ftile_lanes = S->force_lanes;
-  S->ftile_n = 0;
-  const int per = kBlock / S->force_lanes;
-  if (S->K <= 0 || S->n <= 0 || !S->ftile || (int)S->class_off.size() < S->K + 1) return SL_OK;
+static int slab_tiles(sl_system *S, int per, int2 *dev, std::vector<int2> &host, int &nout) {
+  nout = 0;
+  if (S->K <= 0 || S->n <= 0 || !dev || (int)S->class_off.size() < S->K + 1) return SL_OK;
   struct Tile {
     double key;
     int a, b;
@@ -494,14 +494,19 @@ int force_tiles(sl_system *S) {
   }
   const int nb = (int)(8 * m);
   if (nb > force_block_cap(S->n)) return SL_OK;
-  S->ftile_host.assign((size_t)nb, make_int2(0, 0));
+  host.assign((size_t)nb, make_int2(0, 0));
   for (int x = 0; x < 8; ++x)
-    for (size_t k = 0; k < xl[x].size(); ++k)
-      S->ftile_host[8 * k + x] = make_int2(xl[x][k].a, xl[x][k].b);
-  HIPCHK(S, hipMemcpyAsync(S->ftile, S->ftile_host.data(), sizeof(int2) * nb,
-                           hipMemcpyHostToDevice, S->st));
-  S->ftile_n = nb;
+    for (size_t k = 0; k < xl[x].size(); ++k) host[8 * k + x] = make_int2(xl[x][k].a, xl[x][k].b);
+  HIPCHK(S, hipMemcpyAsync(dev, host.data(), sizeof(int2) * nb, hipMemcpyHostToDevice, S->st));
+  nout = nb;
   return SL_OK;
+}
+
+int force_tiles(sl_system *S) {
+  if (S->ftile_lanes == S->force_lanes) return SL_OK;
+  S->ftile_lanes = S->force_lanes;
+  CHK(slab_tiles(S, kBlock / S->force_lanes, S->ftile, S->ftile_host, S->ftile_n));
+  return slab_tiles(S, kBlock, S->jtile, S->jtile_host, S->jtile_n);
 }
 
 // With split set, the pair pass of this boundary (pair_launch) has filled
@@ -918,6 +923,7 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(dalloc(&S->partial, (size_t)nb * 8));
   A_(dalloc(&S->pred, (size_t)nb * 3));
   A_(dalloc(&S->ftile, (size_t)nb));
+  A_(dalloc(&S->jtile, (size_t)nb));
   A_(dalloc(&S->red_out, 8));
   A_(dalloc(&S->thermo, (size_t)kThermoCap * 8));
   A_(hipHostMalloc((void **)&S->ring, 32 * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
@@ -963,7 +969,7 @@ int sl_destroy(sl_system *S) {
                   (void *)S->seen, (void *)S->jpcnt, (void *)S->maxc, (void *)S->dslot,
                   (void *)S->jplist[0], (void *)S->jplist[1], (void *)S->jpmask[0],
                   (void *)S->jpmask[1],
-                  (void *)S->done, (void *)S->partial, (void *)S->pred, (void *)S->ftile, (void *)S->red_out, (void *)S->thermo,
+                  (void *)S->done, (void *)S->partial, (void *)S->pred, (void *)S->ftile, (void *)S->jtile, (void *)S->red_out, (void *)S->thermo,
                   (void *)S->mpairs, (void *)S->mirror, (void *)S->mcnt, (void *)S->mstart,
                   (void *)S->tab[0], (void *)S->tab[1], S->jc[0], S->jc[1], (void *)S->eam,
                   (void *)S->skeys[0], (void *)S->skeys[1], (void *)S->svals[0],
