@@ -136,6 +136,11 @@ void launch_colour_indeg(const ColourArgs &A, int *indeg, unsigned long long *cm
 void launch_colour_round(const ColourArgs &A, int *indeg, const unsigned long long *cmask,
                          const unsigned long long *emask, const int *in, const int *in_count,
                          int *out, int *out_count, int *clear_next, hipStream_t st);
+// Rounds from r0 in one workgroup while the ready list is non-empty and at
+// most nmax long (at most max_rounds); done[0] = rounds run.
+void launch_colour_finish(const ColourArgs &A, int *indeg, const unsigned long long *cmask,
+                          const unsigned long long *emask, int *list0, int *list1, int *count,
+                          int r0, int max_rounds, int nmax, int *done, hipStream_t st);
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st);
 
 // Per atom, the spin-segment slots (< 64) whose entry has the atom's colour.

@@ -348,47 +348,93 @@ __global__ void k_colour_indeg(ColourArgs A, int *indeg, unsigned long long *cma
 // in this round). The slot loads of a chunk go out together, then the
 // colour loads: each ready atom costs a few memory round trips.
 constexpr int kColourChunk = 16;
+// Load of a word another thread of the workgroup may have written in an
+// earlier round of the same launch: an agent-scope atomic load, which reads
+// the L2 (the device-wide rounds get the same guarantee from their launch
+// boundaries).
+__device__ __forceinline__ int load_l2(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One ready atom of a round: first-fit colour against its coloured
+// conflicting neighbours, then the later-key uncoloured neighbours lose one
+// wait each, and the one whose count reaches zero joins the next list.
+template <bool L2>
+__device__ __forceinline__ void colour_one(const ColourArgs &A, int i, int *indeg,
+                                           const unsigned long long *cmask,
+                                           const unsigned long long *emask, int *out,
+                                           int *out_count) {
+  const unsigned long long cm = cmask[i], em = emask[i];
+  const int ns = A.nspin[i] < 64 ? A.nspin[i] : 64;
+  unsigned long long used = 0ull;
+  for (int k0 = 0; k0 < ns; k0 += kColourChunk) {
+    int jj[kColourChunk];
+#pragma unroll
+    for (int q = 0; q < kColourChunk; ++q) {
+      const int k = k0 + q;
+      jj[q] = (k < ns && ((cm >> k) & 1ull)) ? A.nbr[(size_t)k * A.ld + i] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kColourChunk; ++q) {
+      const int cj = jj[q] >= 0 ? (L2 ? load_l2(&A.colour[jj[q]]) : A.colour[jj[q]]) : -1;
+      if (cj >= 0) used |= 1ull << (cj & 63);
+    }
+  }
+  A.colour[i] = __ffsll((long long)~used) - 1;
+  const unsigned long long later = cm & ~em;
+  for (int k0 = 0; k0 < ns; k0 += kColourChunk) {
+    int jj[kColourChunk];
+#pragma unroll
+    for (int q = 0; q < kColourChunk; ++q) {
+      const int k = k0 + q;
+      jj[q] = (k < ns && ((later >> k) & 1ull)) ? A.nbr[(size_t)k * A.ld + i] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kColourChunk; ++q) {
+      const int j = jj[q];
+      if (j >= 0 && (L2 ? load_l2(&A.colour[j]) : A.colour[j]) < 0 && atomicSub(&indeg[j], 1) == 1)
+        out[atomicAdd(out_count, 1)] = j;
+    }
+  }
+}
+
 __global__ void k_colour_round(ColourArgs A, int *indeg, const unsigned long long *cmask,
                                const unsigned long long *emask, const int *in,
                                const int *in_count, int *out, int *out_count, int *clear_next) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *clear_next = 0;
   const int m = *in_count;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
-    const int i = in[t];
-    const unsigned long long cm = cmask[i], em = emask[i];
-    const int ns = A.nspin[i] < 64 ? A.nspin[i] : 64;
-    unsigned long long used = 0ull;
-    for (int k0 = 0; k0 < ns; k0 += kColourChunk) {
-      int jj[kColourChunk];
-#pragma unroll
-      for (int q = 0; q < kColourChunk; ++q) {
-        const int k = k0 + q;
-        jj[q] = (k < ns && ((cm >> k) & 1ull)) ? A.nbr[(size_t)k * A.ld + i] : -1;
-      }
-#pragma unroll
-      for (int q = 0; q < kColourChunk; ++q) {
-        const int cj = jj[q] >= 0 ? A.colour[jj[q]] : -1;
-        if (cj >= 0) used |= 1ull << (cj & 63);
-      }
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x)
+    colour_one<false>(A, in[t], indeg, cmask, emask, out, out_count);
+}
+
+// Rounds r0, r0 + 1, ... in one workgroup, with a workgroup barrier between
+// rounds, for as long as the ready list is non-empty and at most nmax long
+// and at most max_rounds rounds: most rounds of a colouring, and all of a
+// repair, hold a few dozen atoms, which one workgroup serves in a few
+// microseconds while a launch per round costs its dispatch. Lists and
+// counters follow the rotation of k_colour_round (round r reads list r % 2
+// with count r % 3); done[0] gets the number of rounds run.
+constexpr int kFinishBlock = 1024;
+__global__ __launch_bounds__(kFinishBlock) void k_colour_finish(
+    ColourArgs A, int *indeg, const unsigned long long *cmask, const unsigned long long *emask,
+    int *list0, int *list1, int *count, int r0, int max_rounds, int nmax, int *done) {
+  __shared__ int m_s;
+  int r = r0;
+  for (; r < r0 + max_rounds; ++r) {
+    if (threadIdx.x == 0) {
+      m_s = load_l2(&count[r % 3]);
+      atomicExch(&count[(r + 2) % 3], 0);
     }
-    A.colour[i] = __ffsll((long long)~used) - 1;
-    // later-key uncoloured neighbours lose one wait; the last one queues them
-    const unsigned long long later = cm & ~em;
-    for (int k0 = 0; k0 < ns; k0 += kColourChunk) {
-      int jj[kColourChunk];
-#pragma unroll
-      for (int q = 0; q < kColourChunk; ++q) {
-        const int k = k0 + q;
-        jj[q] = (k < ns && ((later >> k) & 1ull)) ? A.nbr[(size_t)k * A.ld + i] : -1;
-      }
-#pragma unroll
-      for (int q = 0; q < kColourChunk; ++q) {
-        const int j = jj[q];
-        if (j >= 0 && A.colour[j] < 0 && atomicSub(&indeg[j], 1) == 1)
-          out[atomicAdd(out_count, 1)] = j;
-      }
-    }
+    __syncthreads();
+    const int m = m_s;
+    if (m == 0 || m > nmax) break;
+    const int *in = (r & 1) ? list1 : list0;
+    int *out = (r & 1) ? list0 : list1;
+    for (int t = threadIdx.x; t < m; t += kFinishBlock)
+      colour_one<true>(A, load_l2(&in[t]), indeg, cmask, emask, out, &count[(r + 1) % 3]);
+    __syncthreads();
   }
+  if (threadIdx.x == 0) done[0] = r - r0;
 }
 
 __global__ void k_colour_stats(ColourArgs A, int *maxc, int *err) {
@@ -603,6 +649,12 @@ void launch_colour_round(const ColourArgs &A, int *indeg, const unsigned long lo
                          int *out, int *out_count, int *clear_next, hipStream_t st) {
   hipLaunchKernelGGL(k_colour_round, dim3(64), dim3(kBlock), 0, st, A, indeg, cmask, emask, in,
                      in_count, out, out_count, clear_next);
+}
+void launch_colour_finish(const ColourArgs &A, int *indeg, const unsigned long long *cmask,
+                          const unsigned long long *emask, int *list0, int *list1, int *count,
+                          int r0, int max_rounds, int nmax, int *done, hipStream_t st) {
+  hipLaunchKernelGGL(k_colour_finish, dim3(1), dim3(kFinishBlock), 0, st, A, indeg, cmask, emask,
+                     list0, list1, count, r0, max_rounds, nmax, done);
 }
 void launch_colour_stats(const ColourArgs &A, int *maxc, int *err, hipStream_t st) {
   if (A.n > 0) hipLaunchKernelGGL(k_colour_stats, dim3(nblocks(A.n)), dim3(kBlock), 0, st, A, maxc, err);

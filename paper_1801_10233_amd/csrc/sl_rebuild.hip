@@ -90,20 +90,30 @@ ColourArgs colour_args(sl_system *S) {
 
 // Colouring rounds until every atom has a colour. Round r reads ready list
 // r % 2 with count r % 3 and writes list (r + 1) % 2 with count (r + 1) % 3.
+// Rounds with at most kFinishMax ready atoms run in one workgroup
+// (k_colour_finish, up to kFinishRounds per launch); longer lists take
+// batches of kJpBatch device-wide rounds. One host synchronisation per
+// launch of the workgroup loop: a repair usually needs just one.
+constexpr int kFinishMax = 4096, kFinishRounds = 4096;
 int jp_rounds(sl_system *S, const ColourArgs &C) {
-  HIPCHK(S, hipMemsetAsync(S->jpcnt, 0, 3 * sizeof(int), S->st));
+  HIPCHK(S, hipMemsetAsync(S->jpcnt, 0, 4 * sizeof(int), S->st));
   launch_colour_indeg(C, S->ctmp, S->jpmask[0], S->jpmask[1], S->jplist[0], &S->jpcnt[0], S->st);
   int r = 0;
   for (;;) {
-    for (int b = 0; b < kJpBatch; ++b, ++r)
-      launch_colour_round(C, S->ctmp, S->jpmask[0], S->jpmask[1], S->jplist[r & 1],
-                          &S->jpcnt[r % 3], S->jplist[(r + 1) & 1], &S->jpcnt[(r + 1) % 3],
-                          &S->jpcnt[(r + 2) % 3], S->st);
-    int rem = 0;
-    HIPCHK(S, hipMemcpyAsync(&rem, &S->jpcnt[r % 3], sizeof(int), hipMemcpyDeviceToHost, S->st));
+    launch_colour_finish(C, S->ctmp, S->jpmask[0], S->jpmask[1], S->jplist[0], S->jplist[1],
+                         S->jpcnt, r, kFinishRounds, kFinishMax, &S->jpcnt[3], S->st);
+    int h[4] = {0, 0, 0, 0};
+    HIPCHK(S, hipMemcpyAsync(h, S->jpcnt, sizeof(h), hipMemcpyDeviceToHost, S->st));
     HIPCHK(S, hipStreamSynchronize(S->st));
+    r += h[3];
+    const int rem = h[r % 3];
     if (rem == 0) break;
     if (r > S->n + 2 * kJpBatch) return fail(S, SL_E_COLOR, "colouring rounds made no progress");
+    if (rem > kFinishMax)
+      for (int b = 0; b < kJpBatch; ++b, ++r)
+        launch_colour_round(C, S->ctmp, S->jpmask[0], S->jpmask[1], S->jplist[r & 1],
+                            &S->jpcnt[r % 3], S->jplist[(r + 1) & 1], &S->jpcnt[(r + 1) % 3],
+                            &S->jpcnt[(r + 2) % 3], S->st);
   }
   S->jp_rounds = r;
   return SL_OK;

@@ -912,7 +912,7 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(dalloc(&S->stage, 3 * (size_t)n));
   A_(dalloc(&S->err, 1));
   A_(dalloc(&S->seen, 2));
-  A_(dalloc(&S->jpcnt, 3));
+  A_(dalloc(&S->jpcnt, 4));
   A_(dalloc(&S->jplist[0], (size_t)n));
   A_(dalloc(&S->jplist[1], (size_t)n));
   A_(dalloc(&S->jpmask[0], (size_t)n));
