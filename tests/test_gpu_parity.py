@@ -288,14 +288,16 @@ def test_fp32_form_error_vs_oracle():
 def test_full_size_large_system_sampled_parity():
     # the 432000-atom workload, every atom compared with the oracle:
     #  - the shape the benchmark's autotuner picks on MI355X with rows in
-    #    displacement order (1 spin lane, 1 force lane, fused small classes up
-    #    to the default 128 atoms, no exchange cache) over 10 steps, with M;
-    #  - the other candidate shapes (4 and 2 spin lanes, the cache on) over
-    #    the first 2 steps (a dual spin launch in each step)
+    #    displacement order and atoms in lattice rows (1 spin lane, 1 force
+    #    lane, fused small classes up to the default 128 atoms, the exchange
+    #    cache) and the same shape without the cache, over 10 steps each in
+    #    two calls, with M and the energies;
+    #  - the other candidate shapes (4 and 2 spin lanes, no cache) over the
+    #    first 2 steps (a dual spin launch in each step)
     w = W.large_langevin(n=60)
     o = make_oracle(w)
     o.step(2, w.dt)
-    for shape in ((4, 1, 0, -1), (2, 1, 0, -1), (1, 1, 0, 1)):
+    for shape in ((4, 1, 0, -1), (2, 1, 0, -1), (2, 1, 0, 1)):
         g = make_gpu(w)
         g.set_tuning(*shape)
         g.step(2, w.dt)
@@ -303,21 +305,24 @@ def test_full_size_large_system_sampled_parity():
         _print("432k parity 2 steps", shape, p)
         assert p["ok"], p
         g.close()
-    g = make_gpu(w)
-    g.set_tuning(1, 1, 0, -1)
-    assert g.tuning() == dict(spin_lanes=1, force_lanes=1, small_class=128, jcache=-1,
-                              overlap=-1)
-    g.step(4, w.dt)                   # two calls: the call-start force launch too
-    g.step(6, w.dt)
     o.step(8, w.dt)
-    p = parity(w, o, g)
-    _print("432k parity 10 steps, benchmarked shape", p)
-    assert p["ok"], p
-    assert g.coloring()[1] == o.coloring()[1] == 4
-    _assert_magnetization(o, g)
-    eo, eg = o.energy(), g.energy()
-    for k in eo:
-        assert eg[k] == pytest.approx(eo[k], rel=1e-10, abs=1e-8), k
+    eo = o.energy()
+    for jc in (1, -1):
+        g = make_gpu(w)
+        g.set_tuning(1, 1, 0, jc)
+        assert g.tuning() == dict(spin_lanes=1, force_lanes=1, small_class=128, jcache=jc,
+                                  overlap=-1)
+        g.step(4, w.dt)                   # two calls: the call-start force launch too
+        g.step(6, w.dt)
+        p = parity(w, o, g)
+        _print("432k parity 10 steps", jc, p)
+        assert p["ok"], p
+        assert g.coloring()[1] == o.coloring()[1] == 4
+        _assert_magnetization(o, g)
+        eg = g.energy()
+        for k in eo:
+            assert eg[k] == pytest.approx(eo[k], rel=1e-10, abs=1e-8), k
+        g.close()
 
 
 def test_full_size_widened_step_parity():
