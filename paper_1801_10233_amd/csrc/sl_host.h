@@ -30,6 +30,7 @@ extern thread_local std::string g_create_err;
 
 constexpr int kThermoCap = 1 << 16;
 constexpr int kJpBatch = 16;
+constexpr int kPinWords = 128;  // rebuild read-back: report at 0, class offsets at 16
 constexpr int kSmallClassDefault = 128;
 
 struct Atoms {
@@ -109,6 +110,8 @@ struct sl_system {
   double *thermo = nullptr;
   double *ring = nullptr;      // pinned host [4 boundaries][8]
   double *ring_dev = nullptr;  // device alias of ring
+  int *pin = nullptr;          // pinned host words read back by a rebuild [kPinWords]
+  int *pin_dev = nullptr;      // device alias of pin
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   SlotMeta meta[4];
 

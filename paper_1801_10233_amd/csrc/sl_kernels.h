@@ -136,6 +136,13 @@ void launch_colour_indeg(const ColourArgs &A, int *indeg, unsigned long long *cm
 void launch_colour_round(const ColourArgs &A, int *indeg, const unsigned long long *cmask,
                          const unsigned long long *emask, const int *in, const int *in_count,
                          int *out, int *out_count, int *clear_next, hipStream_t st);
+// Rebuild read-back into pinned host memory: out[0..5] = jp[0..5] (ready
+// counts, rounds, largest colour, colouring error word), out[6] = *err,
+// out[7..8] = seen[0..1]; and the class offsets out[c] = bstart[c * nrow]
+// for c = 0..K (K < 64).
+void launch_rebuild_report(const int *jp, const int *err, const int *seen, int *out,
+                           hipStream_t st);
+void launch_class_offsets(const int *bstart, int nrow, int K, int *out, hipStream_t st);
 // Rounds from r0 in one workgroup while the ready list is non-empty and at
 // most nmax long (at most max_rounds); done[0] = rounds run.
 void launch_colour_finish(const ColourArgs &A, int *indeg, const unsigned long long *cmask,

@@ -650,6 +650,34 @@ void launch_colour_round(const ColourArgs &A, int *indeg, const unsigned long lo
   hipLaunchKernelGGL(k_colour_round, dim3(64), dim3(kBlock), 0, st, A, indeg, cmask, emask, in,
                      in_count, out, out_count, clear_next);
 }
+// Words the host reads after a rebuild's launches, written into pinned
+// host memory (one synchronisation for all): the colouring counters and
+// rounds, the largest colour and the colouring's own error word, the
+// sticky error word and the largest rows of the list build.
+__global__ void k_rebuild_report(const int *jp, const int *err, const int *seen, int *out) {
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 6; ++k) out[k] = jp[k];
+    out[6] = *err;
+    out[7] = seen[0];
+    out[8] = seen[1];
+    __threadfence_system();
+  }
+}
+
+// Class offsets out[c] = bstart[c * nrow], c = 0..K, into pinned memory.
+__global__ void k_class_offsets(const int *bstart, int nrow, int K, int *out) {
+  const int c = threadIdx.x;
+  if (c <= K) out[c] = bstart[(size_t)c * nrow];
+  __threadfence_system();
+}
+
+void launch_rebuild_report(const int *jp, const int *err, const int *seen, int *out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_rebuild_report, dim3(1), dim3(64), 0, st, jp, err, seen, out);
+}
+void launch_class_offsets(const int *bstart, int nrow, int K, int *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_class_offsets, dim3(1), dim3(64), 0, st, bstart, nrow, K, out);
+}
 void launch_colour_finish(const ColourArgs &A, int *indeg, const unsigned long long *cmask,
                           const unsigned long long *emask, int *list0, int *list1, int *count,
                           int r0, int max_rounds, int nmax, int *done, hipStream_t st) {

@@ -88,26 +88,39 @@ ColourArgs colour_args(sl_system *S) {
   return C;
 }
 
-// Colouring rounds until every atom has a colour. Round r reads ready list
-// r % 2 with count r % 3 and writes list (r + 1) % 2 with count (r + 1) % 3.
-// Rounds with at most kFinishMax ready atoms run in one workgroup
-// (k_colour_finish, up to kFinishRounds per launch); longer lists take
-// batches of kJpBatch device-wide rounds. One host synchronisation per
-// launch of the workgroup loop: a repair usually needs just one.
+// Colouring rounds until every atom has a colour, then its statistics.
+// Round r reads ready list r % 2 with count r % 3 and writes list (r + 1) % 2
+// with count (r + 1) % 3. Rounds with at most kFinishMax ready atoms run in
+// one workgroup (k_colour_finish, up to kFinishRounds per launch); longer
+// lists take batches of kJpBatch device-wide rounds. After each workgroup
+// launch the statistics (largest colour, conflicts, own error word) are
+// computed as if the colouring were complete and read back with the
+// counters, the sticky error word and the list build's largest rows in one
+// host synchronisation; a repair usually needs just that one. *mc gets the
+// largest colour.
 constexpr int kFinishMax = 4096, kFinishRounds = 4096;
-int jp_rounds(sl_system *S, const ColourArgs &C) {
+int jp_rounds(sl_system *S, const ColourArgs &C, int *mc) {
   HIPCHK(S, hipMemsetAsync(S->jpcnt, 0, 4 * sizeof(int), S->st));
   launch_colour_indeg(C, S->ctmp, S->jpmask[0], S->jpmask[1], S->jplist[0], &S->jpcnt[0], S->st);
   int r = 0;
   for (;;) {
     launch_colour_finish(C, S->ctmp, S->jpmask[0], S->jpmask[1], S->jplist[0], S->jplist[1],
                          S->jpcnt, r, kFinishRounds, kFinishMax, &S->jpcnt[3], S->st);
-    int h[4] = {0, 0, 0, 0};
-    HIPCHK(S, hipMemcpyAsync(h, S->jpcnt, sizeof(h), hipMemcpyDeviceToHost, S->st));
+    HIPCHK(S, hipMemsetAsync(&S->jpcnt[4], 0xff, sizeof(int), S->st));
+    HIPCHK(S, hipMemsetAsync(&S->jpcnt[5], 0, sizeof(int), S->st));
+    launch_colour_stats(C, &S->jpcnt[4], &S->jpcnt[5], S->st);
+    launch_rebuild_report(S->jpcnt, S->err, S->seen, S->pin_dev, S->st);
     HIPCHK(S, hipStreamSynchronize(S->st));
+    const int *h = S->pin;
     r += h[3];
     const int rem = h[r % 3];
-    if (rem == 0) break;
+    if (rem == 0) {
+      *mc = h[4];
+      S->sticky |= h[5] | h[6];
+      S->seen_spin = h[7];
+      S->seen_all = h[8];
+      break;
+    }
     if (r > S->n + 2 * kJpBatch) return fail(S, SL_E_COLOR, "colouring rounds made no progress");
     if (rem > kFinishMax)
       for (int b = 0; b < kJpBatch; ++b, ++r)
@@ -185,17 +198,13 @@ int colour_and_permute(sl_system *S, bool repair) {
     launch_colour_mark(C, S->ctmp, S->st);
     HIPCHK(S, hipMemcpyAsync(C.colour, S->ctmp, sizeof(int) * n, hipMemcpyDeviceToDevice, S->st));
   }
-  CHK(jp_rounds(S, C));
   int mc = -1;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    HIPCHK(S, hipMemsetAsync(S->maxc, 0xff, sizeof(int), S->st));
-    launch_colour_stats(C, S->maxc, S->err, S->st);
-    HIPCHK(S, hipMemcpyAsync(&mc, S->maxc, sizeof(int), hipMemcpyDeviceToHost, S->st));
-    CHK(read_err(S));
-    CHK(sticky_code(S));
-    if (mc + 1 <= 32 || attempt == 1) break;
+  CHK(jp_rounds(S, C, &mc));
+  CHK(sticky_code(S));
+  if (mc + 1 > 32) {
     launch_colour_fill(n, C.colour, -1, S->st);  // too many colours: start over
-    CHK(jp_rounds(S, C));
+    CHK(jp_rounds(S, C, &mc));
+    CHK(sticky_code(S));
     set_base = true;
   }
   S->K = n > 0 ? mc + 1 : 0;
@@ -258,11 +267,11 @@ int colour_and_permute(sl_system *S, bool repair) {
   S->cur = 1 - S->cur;
   S->jc_ok[0] = S->jc_ok[1] = false;
   // class offsets = bucket starts of the first cell of every colour
-  std::vector<int> bs(nbin + 1);
-  HIPCHK(S, hipMemcpyAsync(bs.data(), S->bstart, sizeof(int) * (nbin + 1), hipMemcpyDeviceToHost, S->st));
+  if (S->K + 1 > kPinWords - 16) return fail(S, SL_E_COLOR, "too many colour classes");
+  launch_class_offsets(S->bstart, nrow, S->K, S->pin_dev + 16, S->st);
   HIPCHK(S, hipStreamSynchronize(S->st));
   S->class_off.assign(S->K + 1, 0);
-  for (int c = 0; c <= S->K; ++c) S->class_off[c] = bs[(size_t)c * nrow];
+  for (int c = 0; c <= S->K; ++c) S->class_off[c] = S->pin[16 + c];
   S->ftile_lanes = -1;  // the force launch's tiles follow the classes
   {
     Atoms &N = S->a[S->cur];
@@ -313,12 +322,9 @@ int rebuild(sl_system *S) {
     B.row_q = S->row_q;
     HIPCHK(S, hipMemsetAsync(S->seen, 0, 2 * sizeof(int), S->st));
     launch_nbr_build(B, S->st);
-    int seen[2] = {0, 0};
-    HIPCHK(S, hipMemcpyAsync(seen, S->seen, sizeof(seen), hipMemcpyDeviceToHost, S->st));
-    CHK(read_err(S));
-    S->seen_spin = seen[0];
-    S->seen_all = seen[1];
-    CHK(sticky_code(S));
+    // the build's error word and largest rows are read back with the
+    // colouring's report (one host synchronisation for both); an
+    // overflowing row only truncates what the colouring sees meanwhile
   }
   S->have_list = true;
   S->rebuilds++;

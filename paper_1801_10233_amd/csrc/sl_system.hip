@@ -912,7 +912,7 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(dalloc(&S->stage, 3 * (size_t)n));
   A_(dalloc(&S->err, 1));
   A_(dalloc(&S->seen, 2));
-  A_(dalloc(&S->jpcnt, 4));
+  A_(dalloc(&S->jpcnt, 6));
   A_(dalloc(&S->jplist[0], (size_t)n));
   A_(dalloc(&S->jplist[1], (size_t)n));
   A_(dalloc(&S->jpmask[0], (size_t)n));
@@ -929,9 +929,12 @@ int sl_create(const sl_params *p, sl_system **out) {
   A_(hipHostMalloc((void **)&S->ring, 32 * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
   for (int k = 0; k < 4; ++k) A_(hipEventCreateWithFlags(&S->ev[k], hipEventDisableTiming));
   A_(hipHostGetDevicePointer((void **)&S->ring_dev, S->ring, 0));
+  A_(hipHostMalloc((void **)&S->pin, kPinWords * sizeof(int), hipHostMallocCoherent | hipHostMallocMapped));
+  A_(hipHostGetDevicePointer((void **)&S->pin_dev, S->pin, 0));
 #undef A_
   std::memset(S->ring, 0, 32 * sizeof(double));
   (void)hipMemsetAsync(S->err, 0, sizeof(int), S->st);
+  (void)hipMemsetAsync(S->seen, 0, 2 * sizeof(int), S->st);
   {
     // running max slots start at 0, the running min at "no watched pair"
     const double inf = kInf;
@@ -980,6 +983,7 @@ int sl_destroy(sl_system *S) {
   if (S->ev_join) (void)hipEventDestroy(S->ev_join);
   if (S->st2) (void)hipStreamDestroy(S->st2);
   if (S->ring) (void)hipHostFree(S->ring);
+  if (S->pin) (void)hipHostFree(S->pin);
   if (S->own_stream && S->st) (void)hipStreamDestroy(S->st);
   delete S;
   return SL_OK;
