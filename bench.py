@@ -134,7 +134,8 @@ def sync():
 
 PROFILE_EVERY = 50   # HIP events bracket the launches of every 50th timed step (every 10th
                      # cost 8.5 us per step at 432 000 atoms, with the same per-launch means)
-TUNE_STEPS = 50      # steps per autotuner window (8 launch shapes x 4 rounds)
+TUNE_STEPS = 50      # steps per autotuner window (ten launch shapes, four rounds)
+SUSTAINED_STEPS = 1000  # steps per window of the sustained (rebuilds included) figure
 
 
 def timed_run(S, steps, dt, profile=False):
@@ -585,6 +586,21 @@ def main():
                            atoms=w.N, dt_ps=w.dt, colours=st["n_colours"], tuning=tuned,
                            rebuilds_in_run=st["rebuilds"], parallelism="single GPU"),
                roofline=roofline)
+    if not args.no_extras:
+        # the same system over longer windows: list rebuilds (about one every
+        # 150-200 steps) inside the window, the cost a 20-step window leaves out
+        sus = []
+        for _ in range(3):
+            rb0 = S.stats()["rebuilds"]
+            el_s, _ = timed_run(S, SUSTAINED_STEPS, w.dt)
+            sus.append((el_s, S.stats()["rebuilds"] - rb0))
+        el_s, rb_s = sorted(sus)[1]
+        out["sustained"] = dict(value=round(w.N * SUSTAINED_STEPS / el_s, 1), unit="atom-steps/s",
+                                steps=SUSTAINED_STEPS, windows=3,
+                                ms_per_step=round(el_s / SUSTAINED_STEPS * 1e3, 5),
+                                rebuilds_in_window=rb_s,
+                                note="median of 3 windows of the same system, rebuilds included")
+        log("sustained:", json.dumps(out["sustained"]))
     S.close()
 
     if not args.no_extras:
