@@ -150,6 +150,35 @@ def test_neighbor_lists_and_colouring_exact_on_disordered_input():
     assert Ko == Kg and np.array_equal(co, cg)
 
 
+def test_colouring_exact_with_long_ready_lists():
+    # a dilute random gas of 24000 atoms: most atoms have few or no spin
+    # neighbours, so the first colouring rounds hold far more than the 4096
+    # ready atoms one workgroup takes and run as device-wide rounds before the
+    # workgroup loop finishes the rest; the colouring (and the list) must be
+    # the oracle's greedy one exactly
+    rng = np.random.default_rng(4242)
+    N = 24000
+    box = np.array([150.0, 150.0, 150.0])
+    w = W.coupled_nve(n=6)
+    w.r = rng.uniform(0.0, 1.0, (N, 3)) * box
+    w.box = box
+    w.v = rng.standard_normal((N, 3)) * 0.5
+    s = rng.standard_normal((N, 3))
+    w.s = s / np.linalg.norm(s, axis=1)[:, None]
+    w.mass = np.full(N, w.mass[0])
+    o = make_oracle(w)
+    g = make_gpu(w)
+    o.build()
+    g.step(0, w.dt)
+    nso, _, ro = o.neighbor_list()
+    nsg, _, rg = g.neighbor_list()
+    assert row_sets(ro, nso, "spin") == row_sets(rg, nsg, "spin")
+    co, Ko = o.coloring()
+    cg, Kg = g.coloring()
+    assert Ko == Kg and np.array_equal(co, cg)
+    assert g.stats()["jp_rounds"] > 0
+
+
 def test_user_supplied_list_and_colouring():
     w = W.spin_frozen(6)
     o = make_oracle(w)
