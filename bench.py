@@ -555,8 +555,9 @@ def main():
                     traffic=None if traffic is None else round(traffic, 1),
                     traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     kernel=KIND_NAME[dom], launch_shape=shape, avg_launch_us=round(avg_ms * 1e3, 3),
-                    timing=f"HIP events on the library stream around every launch of the first "
-                           f"and every {PROFILE_EVERY}th step of each timed window",
+                    timing=f"HIP events on the library stream around each run of consecutive "
+                           f"spin launches and each other launch, in the first and every "
+                           f"{PROFILE_EVERY}th step of each timed window",
                     profiled_steps=n_prof,
                     algorithmic_bytes_per_unit=per_unit,
                     moved_bytes_per_unit=moved_unit,

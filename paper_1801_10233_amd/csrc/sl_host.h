@@ -48,6 +48,7 @@ struct ProfRec {
   int kind;
   hipEvent_t a, b;
   double work;
+  int launches;  // launches between the two events
 };
 
 struct SlotMeta {
@@ -159,6 +160,9 @@ struct sl_system {
   bool prof = false;
   int prof_every = 1;     // time the launches of every prof_every-th step
   bool prof_now = false;  // the current step is timed
+  int prof_group = -1;    // kind of the open run of launches (ProfGroup), or -1
+  int prof_group_n = 0;
+  double prof_group_work = 0.0;
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
   int64_t prof_launch[5] = {0, 0, 0, 0, 0};
@@ -251,6 +255,8 @@ inline hipEvent_t get_event(sl_system *S) {
   return e;
 }
 
+// One launch between two events on its stream; inside a ProfGroup of the same
+// kind the launch is counted in the group and records no events of its own.
 struct ProfScope {
   sl_system *S;
   int kind;
@@ -259,17 +265,49 @@ struct ProfScope {
   hipStream_t st;
   ProfScope(sl_system *S_, int kind_, double work_, hipStream_t st_ = nullptr)
       : S(S_), kind(kind_), work(work_), st(st_ ? st_ : S_->st) {
-    if (S->prof_now) {
-      a = get_event(S);
-      (void)hipEventRecord(a, st);
+    if (!S->prof_now) return;
+    if (S->prof_group == kind && st == S->st) {
+      S->prof_group_n += 1;
+      S->prof_group_work += work;
+      return;
     }
+    a = get_event(S);
+    (void)hipEventRecord(a, st);
   }
   ~ProfScope() {
     if (a) {
       hipEvent_t b = get_event(S);
       (void)hipEventRecord(b, st);
-      S->prof_recs.push_back({kind, a, b, work});
+      S->prof_recs.push_back({kind, a, b, work, 1});
     }
+  }
+};
+
+// A run of consecutive launches of one kind on the library stream, with
+// nothing else launched between them: two events around the whole run, so
+// that the average launch time is not inflated by an event pair per launch.
+struct ProfGroup {
+  sl_system *S;
+  hipEvent_t a = nullptr;
+  ProfGroup(sl_system *S_, int kind) : S(S_) {
+    if (!S->prof_now || S->prof_group >= 0) return;
+    a = get_event(S);
+    (void)hipEventRecord(a, S->st);
+    S->prof_group = kind;
+    S->prof_group_n = 0;
+    S->prof_group_work = 0.0;
+  }
+  ~ProfGroup() {
+    if (!a) return;
+    hipEvent_t b = get_event(S);
+    (void)hipEventRecord(b, S->st);
+    if (S->prof_group_n > 0) {
+      S->prof_recs.push_back({S->prof_group, a, b, S->prof_group_work, S->prof_group_n});
+    } else {
+      S->ev_pool.push_back(a);
+      S->ev_pool.push_back(b);
+    }
+    S->prof_group = -1;
   }
 };
 

@@ -122,7 +122,7 @@ void prof_collect(sl_system *S) {
   for (auto &r : S->prof_recs) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, r.a, r.b);
-    S->prof_launch[r.kind] += 1;
+    S->prof_launch[r.kind] += r.launches;
     S->prof_ms[r.kind] += ms;
     S->prof_work[r.kind] += r.work;
     S->ev_pool.push_back(r.a);
@@ -395,6 +395,7 @@ void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) 
     items.push_back(it);
   }
   auto size_of = [&](int c) { return S->class_off[c + 1] - S->class_off[c]; };
+  ProfGroup pg(S, 0);  // the loop launches spin phases only
   size_t q = 0;
   while (q < items.size()) {
     size_t r = q;
