@@ -98,10 +98,35 @@ def counter_traffic(kernel, precision, shape=None):
         return None
 
 
-def summarize(paths):
+def busy_window(rows, tail_ms):
+    """Kernel occupancy of the last tail_ms of a kernel trace: the union of
+    the dispatch intervals that fall in [t_end - tail_ms, t_end], t_end the
+    last end time, as a fraction of the window."""
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    t1 = max(e for _, e in iv)
+    t0 = t1 - int(tail_ms * 1e6)
+    busy, cur_s, cur_e, n = 0, None, None, 0
+    for a, b in iv:
+        a, b = max(a, t0), min(b, t1)
+        if b <= a:
+            continue
+        n += 1
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = a, b
+        else:
+            cur_e = max(cur_e, b)
+    if cur_e is not None:
+        busy += cur_e - cur_s
+    return n, busy / 1e6, busy / (t1 - t0)
+
+
+def summarize(paths, tail_ms=0.0):
     """Per-kernel averages from rocprofv3 CSV output: kernel-trace files
-    give the mean duration, counter-collection files the mean value of
-    every counter per dispatch."""
+    give the mean duration (and, with tail_ms, the kernel occupancy of the
+    trace's last tail_ms), counter-collection files the mean value of every
+    counter per dispatch."""
     for path in paths:
         with open(path) as fh:
             rows = list(csv.DictReader(fh))
@@ -121,6 +146,10 @@ def summarize(paths):
             for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
                 print(f"calls={len(v):6d}  mean_us={sum(v) / len(v) / 1e3:10.3f}  "
                       f"total_ms={sum(v) / 1e6:10.3f}  {k[:110]}")
+            if tail_ms > 0:
+                n, busy, frac = busy_window(rows, tail_ms)
+                print(f"# last {tail_ms:.3f} ms of the trace: {n} dispatches, kernels running "
+                      f"{busy:.3f} ms ({100 * frac:.1f} %)")
 
 
 def log(*a):
@@ -470,14 +499,17 @@ def main():
                          "(spin lanes, force lanes, exchange cache 1/-1, split force 1/-1)")
     ap.add_argument("--summarize", nargs="+", metavar="CSV",
                     help="print per-kernel averages of rocprofv3 CSV files and exit")
-    ap.add_argument("--part", choices=["all", "mlp"], default="all",
-                    help="mlp: only the learned potential's kernels (for profiling)")
+    ap.add_argument("--tail-ms", type=float, default=0.0,
+                    help="with --summarize: kernel occupancy of the last TAIL_MS of a trace")
+    ap.add_argument("--part", choices=["all", "mlp", "batched"], default="all",
+                    help="mlp: only the learned potential's kernels; batched: only the "
+                         "batched replicas (both for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.summarize:
-        summarize(args.summarize)
+        summarize(args.summarize, args.tail_ms)
         return
     global SERIES_DIR
     SERIES_DIR = args.save_series
@@ -493,6 +525,9 @@ def main():
         return
     if args.part == "mlp":
         print(json.dumps(mlp_part(args.steps)), flush=True)
+        return
+    if args.part == "batched":
+        print(json.dumps(batched_throughput(args.batch_steps, tune=not args.no_tune)), flush=True)
         return
 
     prec = sl.SL_FP64 if args.precision == "fp64" else sl.SL_FP32
@@ -522,7 +557,7 @@ def main():
     log(f"timed {args.steps} steps: {el:.4f} s, {ms_step:.4f} ms/step, {value:.4e} atom-steps/s")
     st = S.stats()
 
-    # the profile holds whole steps only (the first of each window and every
+    # the profile holds whole steps only (the second of each window and every
     # PROFILE_EVERY-th after it); the dominant kernel is the one with the
     # largest summed event time in them
     kinds = {k: v for k, v in prof.items() if k in KIND_NAME and v[0] > 0}
@@ -556,8 +591,8 @@ def main():
                     traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     kernel=KIND_NAME[dom], launch_shape=shape, avg_launch_us=round(avg_ms * 1e3, 3),
                     timing=f"HIP events on the library stream around each run of consecutive "
-                           f"spin launches and each other launch, in the first and every "
-                           f"{PROFILE_EVERY}th step of each timed window",
+                           f"spin launches and each other launch, in the second step of each timed "
+                           f"window and every {PROFILE_EVERY}th after it",
                     profiled_steps=n_prof,
                     algorithmic_bytes_per_unit=per_unit,
                     moved_bytes_per_unit=moved_unit,

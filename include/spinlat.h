@@ -337,10 +337,12 @@ int sl_autotune(sl_system *sys, int steps, double dt, sl_tuning *chosen);
 
 /* Per-kernel timing with HIP events on the system's stream. With on = 1
  * every launch of the spin-phase, force, rebuild and table kernels inside
- * the steps of sl_step is bracketed by a pair of events; with on = N > 1
- * only the launches of the first step of each sl_step call and of every
- * N-th step after it are (the event packets themselves cost a few
- * microseconds of GPU time each); 0 stops. Launches outside whole steps
+ * the steps of sl_step is timed; with on = N > 1 only the launches of the
+ * second step of each sl_step call (the first when the call has one step)
+ * and of every N-th step after it are (the event packets themselves cost a
+ * few microseconds of GPU time each); 0 stops. A run of consecutive
+ * spin-phase launches is bracketed by one pair of events and counted as its
+ * number of launches; every other launch by a pair of its own. Launches outside whole steps
  * (the force launch that opens a call, sl_get_energy and the like) are
  * never timed, so the totals are those of whole steps. sl_get_profile
  * returns, per kernel kind, the launch count, the summed event time in ms

@@ -194,6 +194,10 @@ struct SysView {
                                // entry at these positions, or null
   double *eam;                 // embedded-atom terms of these positions:
                                // F'(rho_i) at [i], F(rho_i) at [ld + i]
+  int held;                    // force launches: atoms [0, held) take their spin
+                               // at [n + i], the state at this step boundary, held
+                               // there by a spin launch that went on to the next
+                               // step's first update of their class (0: none)
 };
 
 struct SpinPhaseArgs {
@@ -206,6 +210,8 @@ struct SpinPhaseArgs {
   uint64_t seed;
   uint32_t replica;
   double rs2;                 // exchange cutoff squared
+  int keep;                   // nrep 2: store the spin after the first update at
+                              // [n + i] (the step-boundary state the force reads)
 };
 
 // Sectored (or serial) ordering: keys of the per-step sort and one class of a

@@ -18,7 +18,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_phase(SysView<real> S, PotConst
   const int i = A.begin + t / LANES;
   spin_update<real, LANGEVIN, ANISO, LANES, MLP, DUAL>(S, P, i, i < A.end, l, A.nrep, A.step,
                                                        A.sub, A.h, A.amp, A.seed, A.replica,
-                                                       A.rs2, &S2);
+                                                       A.rs2, &S2, !DUAL && A.keep != 0);
 }
 
 // A run of small classes (a few atoms each, e.g. the extra colours a repair

@@ -160,6 +160,10 @@ struct sl_system {
   bool prof = false;
   int prof_every = 1;     // time the launches of every prof_every-th step
   bool prof_now = false;  // the current step is timed
+  // Class 0 has already taken the first spin update of step `step` (merged
+  // into the launch that closed the previous step); its spins at the step
+  // boundary are held at [n + i] of the spin arrays for the force launch.
+  bool held = false;
   int prof_group = -1;    // kind of the open run of launches (ProfGroup), or -1
   int prof_group_n = 0;
   double prof_group_work = 0.0;
@@ -234,6 +238,7 @@ inline SysView<real> view(sl_system *S, int posbuf) {
   const bool jc_use = (!S->mlp || S->mlp_mode == SL_MLP_SPLINE) && S->jcache > 0 && !S->pc.soc_on;
   v.jc = (jc_use && S->jc_ok[posbuf]) ? (const real *)S->jc[posbuf] : nullptr;
   v.eam = S->pc.eam_on ? S->eam : nullptr;
+  v.held = 0;
   if (S->mlp && S->mlp_mode == SL_MLP_SPLINE) {
     v.spl = S->mlp->spline_view();
     v.spl.jshift = S->pot.ex_shift ? 1 : 0;

@@ -70,7 +70,8 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
                                             bool valid, int l, int nrep, const int64_t *step,
                                             const int *sub, double hd, double ampd,
                                             uint64_t seed, uint32_t replica, double rs2,
-                                            const SysView<real> *S2 = nullptr) {
+                                            const SysView<real> *S2 = nullptr,
+                                            bool keep0 = false) {
   // Latency is what bounds this update, so every load that does not depend
   // on another is issued at once: the row length, the own position, spin
   // and id, and the list entries of the first round (taken unconditionally
@@ -219,6 +220,11 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
   const real h = (real)hd;
   const real ih = (real)(1.0 / kHbar);
   for (int rep = 0; rep < nrep; ++rep) {
+    if (keep0 && rep == 1) {  // the state between the two updates, for the force
+      S.sx[S.n + i] = sx;
+      S.sy[S.n + i] = sy;
+      S.sz[S.n + i] = sz;
+    }
     const bool second = DUAL && rep == 1;
     real ex = (second ? bx : ax) + (real)P.zB[0], ey = (second ? by : ay) + (real)P.zB[1],
          ez = (second ? bz : az) + (real)P.zB[2];
@@ -323,7 +329,8 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
   real six = 0, siy = 0, siz = 0;
   if (valid) {
     rix = S.rx[i]; riy = S.ry[i]; riz = S.rz[i];
-    six = S.sx[i]; siy = S.sy[i]; siz = S.sz[i];
+    const int is = i < S.held ? S.n + i : i;
+    six = S.sx[is]; siy = S.sy[is]; siz = S.sz[is];
     const int ns = S.nspin[i], na = S.nall[i];
     const int ld = S.ld;
     // the variant may serve replicas without the embedded-atom terms
@@ -360,7 +367,10 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
         for (int c = 0; c < kForceChunk; ++c) {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
           if (kEam) fpj[c] = eam ? (real)S.eam[jj[c]] : (real)0;
-          if (seg == 0 && !kPairPass) { qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]]; }
+          if (seg == 0 && !kPairPass) {
+            const int js = jj[c] < S.held ? S.n + jj[c] : jj[c];
+            qx[c] = S.sx[js]; qy[c] = S.sy[js]; qz[c] = S.sz[js];
+          }
         }
 #pragma unroll
         for (int c = 0; c < kForceChunk; ++c)

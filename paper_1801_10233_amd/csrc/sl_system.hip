@@ -167,9 +167,11 @@ int alloc_atoms(sl_system *S, Atoms &A) {
   HIPCHK(S, dalloc(&A.by, n));
   HIPCHK(S, dalloc(&A.bz, n));
   HIPCHK(S, dalloc(&A.mass, n));
-  HIPCHK(S, hipMalloc(&A.sx, rs * (n > 0 ? n : 1)));
-  HIPCHK(S, hipMalloc(&A.sy, rs * (n > 0 ? n : 1)));
-  HIPCHK(S, hipMalloc(&A.sz, rs * (n > 0 ? n : 1)));
+  // spins: [0, n) the state, [n, 2n) the step-boundary state of class 0
+  // while the next step's first update of it is already applied
+  HIPCHK(S, hipMalloc(&A.sx, rs * (n > 0 ? 2 * n : 1)));
+  HIPCHK(S, hipMalloc(&A.sy, rs * (n > 0 ? 2 * n : 1)));
+  HIPCHK(S, hipMalloc(&A.sz, rs * (n > 0 ? 2 * n : 1)));
   HIPCHK(S, dalloc(&A.id, n));
   HIPCHK(S, dalloc(&A.colour, n));
   HIPCHK(S, dalloc(&A.wmask, n));
@@ -253,7 +255,7 @@ double noise_amp(const sl_system *S, double h);
 // second at the other buffer).
 template <typename real>
 void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps, const int *subs,
-                 double h, bool dual = false) {
+                 double h, bool dual = false, bool keep = false) {
   SpinPhaseArgs A;
   std::memset(&A, 0, sizeof(A));
   A.begin = S->class_off[c];
@@ -268,6 +270,7 @@ void spin_launch(sl_system *S, int posbuf, int c, int nrep, const int64_t *steps
   A.seed = S->prm.seed;
   A.replica = S->prm.replica;
   A.rs2 = S->pot.ex_rc * S->pot.ex_rc;
+  A.keep = keep && nrep == 2 ? 1 : 0;
   ProfScope ps(S, 0, (double)(A.end - A.begin) * nrep);  // atom updates
   if (dual) {
     const SysView<real> v2 = view<real>(S, 1 - posbuf);
@@ -377,8 +380,11 @@ void sect_half(sl_system *S, int posbuf, int64_t step, int sub_fwd, double h) {
   }
 }
 
+// keep_last: the last item is the two updates of class 0 around a step
+// boundary; its launch holds the state between them for the force launch.
 template <typename real>
-void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) {
+void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h,
+                 bool keep_last = false) {
   (void)ensure_table(S, posbuf);
   (void)ensure_jcache<real>(S, posbuf);
   std::vector<Item> items;
@@ -430,7 +436,8 @@ void run_updates(sl_system *S, int posbuf, const std::vector<Upd> &u, double h) 
       launch_spin_tail<real>(view<real>(S, posbuf), S->pc, T, S->spin_lanes, S->st);
       q = r;
     } else {
-      spin_launch<real>(S, posbuf, items[q].c, items[q].nrep, items[q].steps, items[q].subs, h);
+      spin_launch<real>(S, posbuf, items[q].c, items[q].nrep, items[q].steps, items[q].subs, h,
+                        false, keep_last && q + 1 == items.size());
       ++q;
     }
   }
@@ -557,7 +564,8 @@ int force_launch(sl_system *S, int posbuf, int mode, double dt, int64_t boundary
   }
   {
     ProfScope ps(S, 1, (double)S->n);
-    const SysView<real> v = view<real>(S, posbuf);
+    SysView<real> v = view<real>(S, posbuf);
+    v.held = S->held ? S->class_off[1] : 0;
     if (split) {
       launch_force_spin<real>(v, S->pc, F, S->force_lanes, S->st);
     } else {
@@ -684,10 +692,30 @@ int step_frozen(sl_system *S, int64_t n, double dt) {
   return SL_OK;
 }
 
+// Undo a held first update of class 0: its spins go back to the step
+// boundary's (before a rebuild at that boundary, or when a call ends early).
+int release_held(sl_system *S) {
+  if (!S->held) return SL_OK;
+  S->held = false;
+  Atoms &A = S->a[S->cur];
+  const size_t rs = S->prec == SL_FP64 ? sizeof(double) : sizeof(float);
+  const size_t m = (size_t)S->class_off[1];
+  for (void *p : {A.sx, A.sy, A.sz})
+    HIPCHK(S, hipMemcpyAsync(p, (char *)p + rs * S->n, rs * m, hipMemcpyDeviceToDevice, S->st));
+  return SL_OK;
+}
+
+struct HeldGuard {  // a call never returns with a held update
+  sl_system *S;
+  ~HeldGuard() { (void)release_held(S); }
+};
+
 template <typename real>
 int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
   const double h = dt / 4.0;
   const int te = S->prm.thermo_every;
+  CHK(release_held(S));
+  HeldGuard guard{S};
   const int64_t k0 = S->step;
   // decision for the first step uses the predictor of the boundary before it
   if (!S->user_list && S->have_D) {
@@ -703,12 +731,14 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
   if (built) S->meta[k0 & 3].rebuilt_after = true;
   S->have_D = true;
   for (int64_t k = k0; k < k0 + n; ++k) {
-    // timed steps: the first of the call and every prof_every-th after it
-    S->prof_now = S->prof && ((k - k0) % S->prof_every == 0);
+    // timed steps: with prof_every 1 all, else the second of the call (the
+    // first of a call has one spin launch more) and every prof_every-th after it
+    S->prof_now = S->prof && (S->prof_every == 1 || (k - k0) % S->prof_every == (n > 1 ? 1 : 0));
     if (k > k0 && !S->user_list) {
       bool due;
       CHK(wait_predictor(S, k - 1, dt, &due));
       if (due) {
+        CHK(release_held(S));
         CHK(rebuild(S));
         S->meta[k & 3].rebuilt_after = true;
       }
@@ -738,6 +768,10 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
       std::vector<Upd> u, w;
       half_step_updates(S, k, 0, u);
       half_step_updates(S, k, 2, w);
+      if (S->held) {  // class 0's first update of this step is done
+        u.erase(u.begin());
+        S->held = false;
+      }
       // the first class closes one half-step and opens the next: its two
       // updates around the drift go in one dual launch when it is large
       // enough for its own launch anyway
@@ -753,7 +787,15 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
         const int64_t st2[2] = {k, k};
         const int sb2[2] = {1, 2};
         spin_launch<real>(S, S->pos, c0, 2, st2, sb2, h, true);
-        run_updates<real>(S, 1 - S->pos, w, h);
+        // the symmetric sweep (Eq. spin_ST_decomposition) ends this step and
+        // starts the next with class 0, at the drifted positions, with nothing
+        // in between but the force launch, which reads the held state between
+        // the two updates: one launch (undone by release_held if the list is
+        // rebuilt at that boundary)
+        const bool hold = c0 == 0 && w.back().c == 0 && k + 1 < k0 + n;
+        if (hold) w.push_back({0, k + 1, 0});
+        run_updates<real>(S, 1 - S->pos, w, h, hold);
+        S->held = hold;
       } else {
         run_updates<real>(S, S->pos, u, h);
         run_updates<real>(S, 1 - S->pos, w, h);

@@ -41,6 +41,19 @@ def test_summaries_of_trace_and_counter_files(tmp_path, capsys):
     assert "dispatches=     2" in line and "mean=          20.0" in line
 
 
+def test_kernel_occupancy_of_a_trace_window():
+    B = _bench()
+    ns = 1_000_000  # 1 ms
+    rows = [dict(Start_Timestamp=a * ns, End_Timestamp=b * ns)
+            for a, b in ((0, 4), (5, 7), (6, 8), (9, 10))]
+    # last 5 ms = [5, 10]: kernels cover [5, 8] and [9, 10], overlaps counted once
+    n, busy, frac = B.busy_window(rows, 5.0)
+    assert (n, busy, frac) == (3, 4.0, 0.8)
+    # a window reaching back into the first kernel clips it: [3, 10] holds 1 + 3 + 1 ms
+    n, busy, frac = B.busy_window(rows, 7.0)
+    assert n == 4 and busy == 5.0 and abs(frac - 5.0 / 7.0) < 1e-12
+
+
 def test_algorithmic_bytes_and_profile_lookup():
     B = _bench()
     sl = B.sl

@@ -117,6 +117,44 @@ def test_coupled_parity_through_rebuilds():
     assert p["ok"], p
 
 
+def test_held_boundary_update_through_rebuilds_and_samples():
+    # classes above the small-class size (1024 atoms, four classes of 256):
+    # the last class-0 update of a step and the first of the next run in one
+    # launch, with the boundary state held aside for the force launch and its
+    # energy samples; a rebuild at such a boundary undoes the held update
+    w = W.coupled_nve(n=8, T=1500.0)
+    o = make_oracle(w)
+    g = make_gpu(w, thermo_every=10)
+    Es = []
+    for _ in range(20):
+        o.step(10, 2e-4)
+        Es.append(o.energy()["total"])
+    g.step(200, 2e-4)
+    _print("rebuilds", o.num_rebuilds, g.stats())
+    assert o.num_rebuilds >= 2
+    assert g.stats()["rebuilds"] == o.num_rebuilds
+    steps, Eg, _ = g.thermo()
+    assert list(steps) == list(range(10, 201, 10))
+    assert np.allclose(Eg, Es, rtol=1e-11, atol=1e-9)
+    p = parity(w, o, g, rtol_r=1e-10, tol_s=1e-9, rtol_v=1e-9)
+    _print("held-update parity", p)
+    assert p["ok"], p
+    _assert_magnetization(o, g, tol=1e-9)
+    # one step per call holds nothing back, and between rebuilds (a call
+    # that starts at a rebuilt boundary sums its first force over the new
+    # list's order) it must give the same state bit for bit
+    w = W.coupled_nve(n=8)
+    g = make_gpu(w, thermo_every=10)
+    h = make_gpu(w, thermo_every=10)
+    g.step(60, w.dt)
+    for _ in range(60):
+        h.step(1, w.dt)
+    assert g.stats()["rebuilds"] == h.stats()["rebuilds"] <= 1   # the initial build only
+    for a, b in zip(g.get_state(), h.get_state()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(g.thermo()[1], h.thermo()[1])
+
+
 def test_langevin_anisotropy_parity():
     w = W.large_langevin(n=7)                   # 686 atoms, K = 9, lambda = 0.01
     o = make_oracle(w)
