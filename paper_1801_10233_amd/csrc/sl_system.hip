@@ -787,7 +787,7 @@ int step_coupled(sl_system *S, int64_t n, double dt, bool built) {
         const int64_t st2[2] = {k, k};
         const int sb2[2] = {1, 2};
         spin_launch<real>(S, S->pos, c0, 2, st2, sb2, h, true);
-        // the symmetric sweep (Eq. spin_ST_decomposition) ends this step and
+        // the symmetric sweep over classes (Eq. spin_ST_sectoring) ends this step and
         // starts the next with class 0, at the drifted positions, with nothing
         // in between but the force launch, which reads the held state between
         // the two updates: one launch (undone by release_held if the list is
@@ -1253,6 +1253,10 @@ int sl_set_neighbor_list(sl_system *S, const int *offsets, const int *idx, int w
   S->user_list = true;
   S->have_list = true;
   S->have_D = false;
+  // a colouring of the old list may not be one of the new list: the next
+  // step colours and orders the atoms again (sl_set_coloring after this
+  // call sets the caller's), which also drops the caches of the old list
+  S->have_colour = false;
   return SL_OK;
 }
 

@@ -235,6 +235,34 @@ def test_user_supplied_list_and_colouring():
     assert p["ok"], p
 
 
+def test_new_user_list_after_steps_recolours_and_drops_the_caches():
+    # a list set on a system that has stepped (its own list, colouring and
+    # exchange-coefficient cache in its slot order) must be taken as on a
+    # fresh system: colouring and order from the new list, no stale cache
+    w = W.coupled_nve(n=8)
+    o = make_oracle(w)
+    o.step(3, w.dt)
+    o.build()
+    ns, na, rows = o.neighbor_list()            # valid at the state 3 steps on
+    off = np.concatenate([[0], np.cumsum(na)]).astype(np.int32)
+    idx = np.concatenate(rows).astype(np.int32)
+    b = make_gpu(w)
+    b.set_tuning(1, 1, 128, 1)                  # exchange cache on
+    b.step(3, w.dt)
+    r, v, s = b.get_state()
+    a = make_gpu(w)
+    a.set_tuning(1, 1, 128, 1)
+    a.set_state(r, v, s, w.mass)
+    a.set_step(3)
+    a.set_neighbor_list(off, idx)
+    b.set_neighbor_list(off, idx)
+    a.step(20, w.dt)
+    b.step(20, w.dt)
+    assert np.array_equal(a.coloring()[0], b.coloring()[0])
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+
+
 def test_reversibility_on_gpu():
     w = W.coupled_nve(n=6)
     g = make_gpu(w)
