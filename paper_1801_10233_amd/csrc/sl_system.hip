@@ -1075,6 +1075,10 @@ int sl_set_potential(sl_system *S, const sl_potential *pot) {
   CHK(check_box(S));
   if (!S->user_list) S->have_list = false;
   S->have_D = false;
+  // the pair-coefficient caches hold values of the old potential (a user
+  // list keeps its list and colouring, so no rebuild would drop them)
+  S->tab_ok[0] = S->tab_ok[1] = false;
+  S->jc_ok[0] = S->jc_ok[1] = false;
   return SL_OK;
 }
 

@@ -263,6 +263,36 @@ def test_new_user_list_after_steps_recolours_and_drops_the_caches():
         assert np.array_equal(x, y)
 
 
+def test_potential_change_drops_the_exchange_cache():
+    # with a user list (kept, with its colouring, across sl_set_potential)
+    # the cached J(r_ij) of the old potential must not be reused
+    w = W.coupled_nve(n=8)
+    o = make_oracle(w)
+    o.build()
+    ns, na, rows = o.neighbor_list()
+    off = np.concatenate([[0], np.cumsum(na)]).astype(np.int32)
+    idx = np.concatenate(rows).astype(np.int32)
+    pot2 = dict(w.pot, ex_alpha=1.5 * w.pot["ex_alpha"])
+    b = make_gpu(w)
+    b.set_tuning(1, 1, 128, 1)                  # exchange cache on
+    b.set_neighbor_list(off, idx)
+    b.step(3, w.dt)
+    b.set_potential(pot2)
+    r, v, s = b.get_state()
+    c, _ = b.coloring()
+    a = make_gpu(w)
+    a.set_tuning(1, 1, 128, 1)
+    a.set_potential(pot2)
+    a.set_state(r, v, s, w.mass)
+    a.set_step(3)
+    a.set_neighbor_list(off, idx)
+    a.set_coloring(c)
+    a.step(10, w.dt)
+    b.step(10, w.dt)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+
+
 def test_reversibility_on_gpu():
     w = W.coupled_nve(n=6)
     g = make_gpu(w)
