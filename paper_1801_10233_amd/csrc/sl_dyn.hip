@@ -66,16 +66,16 @@ __global__ __launch_bounds__(kBlock) void k_jcache(SysView<real> S, PotConst P, 
   if (i >= end) return;
   const int ns = S.nspin[i];
   const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
-  // slots in chunks of 8 with all loads of a chunk issued before use; the
-  // slot rows below kcap exist for every atom, so their loads need no guard
+  // slots in chunks of 8 with all loads of a chunk issued before use (the
+  // row's own slots only: ns <= kcap)
   constexpr int CH = 8;
   for (int k0 = 0; k0 < ns; k0 += CH) {
     int jj[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int k = k0 + c;
-      const int j = k < S.kcap ? S.nbr[(size_t)k * S.ld + i] : i;
-      jj[c] = (k < ns && (unsigned)j < (unsigned)S.n) ? j : i;
+      const int j = k < ns ? S.nbr[(size_t)k * S.ld + i] : i;
+      jj[c] = (unsigned)j < (unsigned)S.n ? j : i;
     }
     double xj[CH], yj[CH], zj[CH];
 #pragma unroll

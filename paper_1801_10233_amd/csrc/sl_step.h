@@ -42,12 +42,13 @@ __device__ __forceinline__ void cayley_rot(real &sx, real &sy, real &sz, real wx
 // One spin update (or nrep successive ones) of atom i, shared by the
 // per-class launch and the fused small-class launch. All LANES lanes of an
 // atom must call it (cross-lane shuffles); `valid` masks the tail.
-// Neighbour slots one lane gathers per round of the spin phase: with one or
-// two lanes per atom the first round covers 16 list slots (the whole spin
-// segment of bcc at the exchange cutoff, 14 entries) in one go.
+// Neighbour slots one lane gathers per round of the spin phase. With one
+// lane per atom two rounds of 7 cover the 14 entries of a bcc spin segment
+// at the exchange cutoff (rows that thermal motion lengthens to 15 or 16
+// take a third); with two lanes one round of 8 per lane covers 16 slots.
 template <int LANES, int MLP = 0>
 struct SpinChunk {
-  static constexpr int value = LANES >= 8 ? 2 : (LANES >= 4 ? 4 : 8);
+  static constexpr int value = LANES >= 8 ? 2 : (LANES >= 4 ? 4 : (LANES == 2 ? 8 : 7));
 };
 // The spin-orbit variant holds a field vector per slot besides the
 // coefficient, and its dual form a second one: 4 slots per round keep it
@@ -94,11 +95,14 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
     sx = S.sx[i]; sy = S.sy[i]; sz = S.sz[i];
     if (LANGEVIN) aid = (uint32_t)S.id[i];
     for (int base = l, round = 0; round == 0 || base < ns; base += LANES * CH, ++round) {
+      // the first round loads its slots before the row length is known;
+      // later ones (the row length has arrived) load only the row's own
+      const int kend = round == 0 ? S.kcap : ns;
       int jj[CH];
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         const int k = base + LANES * c;
-        const int j = k < S.kcap ? S.nbr[(size_t)k * ld + i] : i;
+        const int j = k < kend ? S.nbr[(size_t)k * ld + i] : i;
         jj[c] = (unsigned)j < (unsigned)S.n ? j : i;
       }
       real qx[CH], qy[CH], qz[CH], J[CH];
@@ -115,11 +119,11 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
       for (int c = 0; c < CH; ++c) {
         const int k = base + LANES * c;
         if (MLP == 1) {
-          jt[c] = k < S.kcap ? S.tab[(size_t)k * ld + i].x : 0.f;
-          if (DUAL) jt2[c] = k < S.kcap ? S2->tab[(size_t)k * ld + i].x : 0.f;
+          jt[c] = k < kend ? S.tab[(size_t)k * ld + i].x : 0.f;
+          if (DUAL) jt2[c] = k < kend ? S2->tab[(size_t)k * ld + i].x : 0.f;
         } else if (MLP == 3) {
-          jr[c] = k < S.kcap ? S.jc[(size_t)k * ld + i] : (real)0;
-          if (DUAL) jr2[c] = k < S.kcap ? S2->jc[(size_t)k * ld + i] : (real)0;
+          jr[c] = k < kend ? S.jc[(size_t)k * ld + i] : (real)0;
+          if (DUAL) jr2[c] = k < kend ? S2->jc[(size_t)k * ld + i] : (real)0;
         } else {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
           if (DUAL) { px2[c] = S2->rx[jj[c]]; py2[c] = S2->ry[jj[c]]; pz2[c] = S2->rz[jj[c]]; }
