@@ -8,8 +8,17 @@
 // colour class).
 #pragma once
 
+#include <type_traits>
+
 #include "sl_device.h"
 #include "sl_kernels.h"
+
+#ifndef SL_SPIN_FIRST
+#define SL_SPIN_FIRST 7  // slots of the first round with one lane per atom
+#endif
+#ifndef SL_SPIN_LATER
+#define SL_SPIN_LATER 8  // slots of each later round with one lane per atom
+#endif
 
 namespace sl {
 
@@ -42,13 +51,16 @@ __device__ __forceinline__ void cayley_rot(real &sx, real &sy, real &sz, real wx
 // One spin update (or nrep successive ones) of atom i, shared by the
 // per-class launch and the fused small-class launch. All LANES lanes of an
 // atom must call it (cross-lane shuffles); `valid` masks the tail.
-// Neighbour slots one lane gathers per round of the spin phase. With one
-// lane per atom two rounds of 7 cover the 14 entries of a bcc spin segment
-// at the exchange cutoff (rows that thermal motion lengthens to 15 or 16
-// take a third); with two lanes one round of 8 per lane covers 16 slots.
+// Neighbour slots one lane gathers per round of the spin phase (value: the
+// first round, later: each later one). With one lane per atom a first round
+// of 7 and a second of 8 cover the 14 entries of a bcc spin segment at the
+// exchange cutoff and the 15 or 16 that thermal motion puts into some rows
+// (measured at 432 000 atoms: 7 + 7, 7 + 9, 6 + 8, 6 + 10, 5 + 9 and 8 + 8
+// were slower); with two lanes one round of 8 per lane covers 16 slots.
 template <int LANES, int MLP = 0>
 struct SpinChunk {
-  static constexpr int value = LANES >= 8 ? 2 : (LANES >= 4 ? 4 : (LANES == 2 ? 8 : 7));
+  static constexpr int value = LANES >= 8 ? 2 : (LANES >= 4 ? 4 : (LANES == 2 ? 8 : SL_SPIN_FIRST));
+  static constexpr int later = LANES == 1 ? SL_SPIN_LATER : value;
 };
 // The spin-orbit variant holds a field vector per slot besides the
 // coefficient, and its dual form a second one: 4 slots per round keep it
@@ -58,6 +70,7 @@ struct SpinChunk {
 template <int LANES>
 struct SpinChunk<LANES, 4> {
   static constexpr int value = LANES >= 8 ? 2 : 4;
+  static constexpr int later = value;
 };
 
 // DUAL: two successive updates of one class at two sets of positions (the
@@ -80,7 +93,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
   // and any index outside [0, n) is replaced by i before it is used). The
   // gathers of positions and spins follow in one batch, and the Philox
   // noise of the first update is computed while they are in flight.
-  constexpr int CH = SpinChunk<LANES, MLP>::value;
+  constexpr int CH0 = SpinChunk<LANES, MLP>::value, CH1 = SpinChunk<LANES, MLP>::later;
   real ax = 0, ay = 0, az = 0;
   real bx = 0, by = 0, bz = 0;  // DUAL: field at the positions of S2
   real sx = 0, sy = 0, sz = 0;
@@ -94,10 +107,13 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
     if (DUAL) { rix2 = S2->rx[i]; riy2 = S2->ry[i]; riz2 = S2->rz[i]; }
     sx = S.sx[i]; sy = S.sy[i]; sz = S.sz[i];
     if (LANGEVIN) aid = (uint32_t)S.id[i];
-    for (int base = l, round = 0; round == 0 || base < ns; base += LANES * CH, ++round) {
+    // one round of CH slots from base (a generic lambda, so that the first
+    // round and the later ones can differ in size)
+    auto gather_round = [&](auto chunk, int base, bool first) {
       // the first round loads its slots before the row length is known;
       // later ones (the row length has arrived) load only the row's own
-      const int kend = round == 0 ? S.kcap : ns;
+      constexpr int CH = decltype(chunk)::value;
+      const int kend = first ? S.kcap : ns;
       int jj[CH];
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
@@ -130,7 +146,7 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
         }
         qx[c] = S.sx[jj[c]]; qy[c] = S.sy[jj[c]]; qz[c] = S.sz[jj[c]];
       }
-      if (LANGEVIN && round == 0 && l == 0)
+      if (LANGEVIN && first && l == 0)
         gauss3(seed, aid, step[0], replica, sub[0], g0);
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
@@ -207,7 +223,10 @@ __device__ __forceinline__ void spin_update(const SysView<real> &S, const PotCon
           }
         }
       }
-    }
+    };
+    gather_round(std::integral_constant<int, CH0>{}, l, true);
+    for (int base = l + LANES * CH0; base < ns; base += LANES * CH1)
+      gather_round(std::integral_constant<int, CH1>{}, base, false);
   }
 #pragma unroll
   for (int o = LANES / 2; o > 0; o >>= 1) {
