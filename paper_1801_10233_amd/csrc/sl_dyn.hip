@@ -5,6 +5,11 @@
 //   * k_reduce8:    fixed-order second pass of the block partial sums.
 #include "sl_step.h"
 
+#ifndef SL_JC_CHUNK
+#define SL_JC_CHUNK 5  // list slots per round of the exchange-cache kernel
+                       // (3, 4 and 5 measured alike, 6, 7, 8 and 14 slower)
+#endif
+
 namespace sl {
 
 template <typename real, bool LANGEVIN, bool ANISO, int LANES, int MLP, bool DUAL>
@@ -66,9 +71,9 @@ __global__ __launch_bounds__(kBlock) void k_jcache(SysView<real> S, PotConst P, 
   if (i >= end) return;
   const int ns = S.nspin[i];
   const double rix = S.rx[i], riy = S.ry[i], riz = S.rz[i];
-  // slots in chunks of 8 with all loads of a chunk issued before use (the
-  // row's own slots only: ns <= kcap)
-  constexpr int CH = 8;
+  // slots in chunks of SL_JC_CHUNK with all loads of a chunk issued before
+  // use (the row's own slots only: ns <= kcap)
+  constexpr int CH = SL_JC_CHUNK;
   for (int k0 = 0; k0 < ns; k0 += CH) {
     int jj[CH];
 #pragma unroll
