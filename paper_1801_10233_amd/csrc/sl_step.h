@@ -20,6 +20,13 @@
 #define SL_SPIN_LATER 8  // slots of each later round with one lane per atom
 #endif
 
+#ifndef SL_FORCE_CHUNK0
+#define SL_FORCE_CHUNK0 2  // force-gather slots per round in the spin segment
+#endif
+#ifndef SL_FORCE_CHUNK1
+#define SL_FORCE_CHUNK1 SL_FORCE_CHUNK  // the same in the rest of the row (positions only)
+#endif
+
 namespace sl {
 
 // Cayley rotation of Sec. 3 about w with step h, in place (an exact
@@ -370,24 +377,27 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
     // than skin/2) and needs positions only.
     // (the two segments are unrolled: each copy knows whether it needs the
     // neighbour spins, and schedules all of a chunk's loads together)
-#pragma unroll
-    for (int seg = 0; seg < 2; ++seg) {
-      if (kSpinPass && seg == 1) continue;
+    // the two segments as one generic lambda called twice, so that each
+    // knows at compile time whether it needs the neighbour spins and takes
+    // its own chunk size
+    auto segment = [&](auto segc, auto chunkc) {
+      constexpr int seg = decltype(segc)::value;
+      constexpr int CHF = decltype(chunkc)::value;
       const int beg = seg == 0 ? 0 : ns, end = seg == 0 ? ns : na;
-      for (int base = beg + l; base < end; base += LANES * kForceChunk) {
-        int jj[kForceChunk];
+      for (int base = beg + l; base < end; base += LANES * CHF) {
+        int jj[CHF];
 #pragma unroll
-        for (int c = 0; c < kForceChunk; ++c) {
+        for (int c = 0; c < CHF; ++c) {
           const int k = base + LANES * c;
           jj[c] = k < end ? S.nbr[(size_t)k * ld + i] : i;
         }
-        double px[kForceChunk], py[kForceChunk], pz[kForceChunk];
-        real sij[kForceChunk];
-        real qx[kForceChunk], qy[kForceChunk], qz[kForceChunk];  // spin segment
-        real fpj[kForceChunk];                                   // kEam
-        float4 tt[kForceChunk];
+        double px[CHF], py[CHF], pz[CHF];
+        real sij[CHF];
+        real qx[CHF], qy[CHF], qz[CHF];  // spin segment
+        real fpj[CHF];                                   // kEam
+        float4 tt[CHF];
 #pragma unroll
-        for (int c = 0; c < kForceChunk; ++c) {
+        for (int c = 0; c < CHF; ++c) {
           px[c] = S.rx[jj[c]]; py[c] = S.ry[jj[c]]; pz[c] = S.rz[jj[c]];
           if (kEam) fpj[c] = eam ? (real)S.eam[jj[c]] : (real)0;
           if (seg == 0 && !kPairPass) {
@@ -396,17 +406,17 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           }
         }
 #pragma unroll
-        for (int c = 0; c < kForceChunk; ++c)
+        for (int c = 0; c < CHF; ++c)
           sij[c] = (seg == 0 && !kPairPass) ? six * qx[c] + siy * qy[c] + siz * qz[c] : (real)0;
         if (kV == 1) {
 #pragma unroll
-          for (int c = 0; c < kForceChunk; ++c) {
+          for (int c = 0; c < CHF; ++c) {
             const int k = base + LANES * c;
             tt[c] = k < end ? S.tab[(size_t)k * ld + i] : make_float4(0.f, 0.f, 0.f, 0.f);
           }
         }
 #pragma unroll
-        for (int c = 0; c < kForceChunk; ++c) {
+        for (int c = 0; c < CHF; ++c) {
           const bool use = base + LANES * c < end;
           const double dxd = min_image(rix - px[c], S.L[0], S.invL[0]);
           const double dyd = min_image(riy - py[c], S.L[1], S.invL[1]);
@@ -473,7 +483,10 @@ __device__ __forceinline__ void force_atom(const SysView<real> &S, const PotCons
           }
         }
       }
-    }
+    };
+    segment(std::integral_constant<int, 0>{}, std::integral_constant<int, SL_FORCE_CHUNK0>{});
+    if (!kSpinPass)
+      segment(std::integral_constant<int, 1>{}, std::integral_constant<int, SL_FORCE_CHUNK1>{});
   }
 #pragma unroll
   for (int o = LANES / 2; o > 0; o >>= 1) {
